@@ -1,0 +1,119 @@
+/*
+ * CPU ORACLE -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, FP64 implementation of the geometry queries of the paper
+ * (Sec. III.C: is a particle inside or outside a solid, what is its minimal
+ * distance to the border, and what is the maximal step along its direction)
+ * and of step selection along a placed-volume tree (Sec. III.A: the particle is
+ * transported to the border when the proposed physics step is longer; Sec. III.B:
+ * elementary solids with coordinate transforms, arranged hierarchically).
+ *
+ * Only the tests, the smoke check and the benchmark's CPU-baseline leg may call
+ * this code.  It shares no source, header, table or helper with the HIP library;
+ * the two meet only in the geometry blob format and the seeded inputs.
+ *
+ * Rules of the oracle:
+ *   - FP64, IEEE round-to-nearest, built with -ffp-contract=off (no FMA).
+ *   - Distances are computed by the event-list definition: every root of every
+ *     full bounding surface splits the ray into intervals; each interval is
+ *     classified by probing the Inside code at 1/4, 1/2 and 3/4 of it (or at
+ *     +1, +2, +4 mm for the last, infinite one); DistanceToIn is the start of
+ *     the first inside interval, DistanceToOut the start of the first outside
+ *     interval.  No per-face analytic logic.
+ *   - One track at a time (Geant4's serial per-particle model, Sec. III.B); the
+ *     batch wrappers only spread independent tracks over threads.
+ *
+ * Parity pins live in tests/test_oracle_*.py.  Functions whose result is a
+ * chosen formula rather than a unique quantity are marked "parity unpinned"
+ * below where no independent check reaches them.
+ */
+#ifndef GV_ORACLE_H
+#define GV_ORACLE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#define OR_KTOL 1e-9   /* kTolerance, mm */
+#define OR_KHALF 5e-10 /* half-width of the surface band, mm */
+#define OR_MAX_NZ 64   /* polycone planes */
+#define OR_MAX_ROOTS (4 * OR_MAX_NZ + 16)
+
+enum { OR_BOX = 0, OR_TUBS = 1, OR_CONS = 2, OR_SPHERE = 3, OR_TRD = 4, OR_PCON = 5 };
+enum { OR_OUTSIDE = 0, OR_SURFACE = 1, OR_INSIDE = 2 };
+enum { OR_SAFETY_AUTO = 0, OR_SAFETY_IN = 1, OR_SAFETY_OUT = 2 };
+
+/* Per-track flags that are part of the transport contract. */
+#define OR_F_OVERFLOW 1u
+#define OR_F_STUCK 2u
+#define OR_F_LOCATE_FAIL 4u
+/* Oracle-only diagnostics: ill-conditioned decisions that two correct FP64
+ * codes may take differently; such tracks are listed, not counted. */
+#define OR_D_NEAR_TIE 16u
+#define OR_D_GRAZE 32u
+#define OR_D_ZERO_STEP 64u
+#define OR_D_BAND_EDGE 128u
+#define OR_D_NO_EXIT 256u
+
+typedef struct {
+  int type;
+  int nz; /* polycone planes */
+  double p[8];
+  /* phi segment (tubs, cons) */
+  int full_phi, convex_wedge;
+  double ns[2], ne[2], us[2], ue[2];
+  /* cons */
+  double ao, bo, co, ai, bi, ci;
+  int has_inner;
+  /* trd */
+  double x0, tx, cx, y0, ty, cy;
+  /* pcon */
+  double z[OR_MAX_NZ], rmin[OR_MAX_NZ], rmax[OR_MAX_NZ];
+  double pc_bo[OR_MAX_NZ], pc_co[OR_MAX_NZ], pc_bi[OR_MAX_NZ], pc_ci[OR_MAX_NZ];
+  int pc_inner[OR_MAX_NZ];
+} or_solid;
+
+/* returns 0 on success, negative on invalid parameters */
+int or_solid_init(or_solid* s, int type, const double* params, int nparams);
+
+double or_signed(const or_solid* s, const double p[3]);
+int or_code(double s);
+int or_inside(const or_solid* s, const double p[3]);
+double or_safety_in(const or_solid* s, const double p[3]);  /* SafetyToIn, point outside */
+double or_safety_out(const or_solid* s, const double p[3]); /* SafetyToOut, point inside */
+double or_safety(const or_solid* s, int mode, const double p[3]);
+double or_dist_in(const or_solid* s, const double p[3], const double d[3], unsigned* diag);
+double or_dist_out(const or_solid* s, const double p[3], const double d[3], unsigned* diag);
+/* as above; *t_suspect receives the start of the first ill-conditioned interval */
+double or_dist_in_ex(const or_solid* s, const double p[3], const double d[3], unsigned* diag,
+                     double* t_suspect);
+double or_dist_out_ex(const or_solid* s, const double p[3], const double d[3], unsigned* diag,
+                      double* t_suspect);
+int or_roots(const or_solid* s, const double p[3], const double d[3], double* roots);
+
+/* ---------------------------------------------------------------- geometry */
+typedef struct {
+  int n_lv, n_pv, n_place, world_lv, max_depth;
+  or_solid* lv_solid;
+  int* pv_lv;
+  int* pv_parent;
+  int* pv_depth;
+  double* pv_xf;   /* 12 per PV: R (row major) and t, relative to the parent */
+  int* pv_child_off; /* CSR over PVs, children in ascending id order */
+  int* pv_child;
+} or_geom;
+
+int or_geom_load(const void* blob, size_t nbytes, or_geom** out);
+void or_geom_free(or_geom* g);
+
+void or_to_local(const or_geom* g, int pv, const double p[3], const double d[3], double pl[3],
+                 double dl[3]);
+int or_locate(const or_geom* g, const double p[3]);
+double or_compute_step(const or_geom* g, const double p[3], const double d[3], int pv,
+                       double pstep, int* next, unsigned* flags, unsigned* diag);
+double or_nav_safety(const or_geom* g, const double p[3], int pv);
+int or_nav_inside(const or_geom* g, const double p[3], int pv);
+int or_transport(const or_geom* g, const double p0[3], const double d[3], int start_pv,
+                 int max_steps, int32_t* out_pv, double* out_step, unsigned* flags,
+                 unsigned* diag);
+
+#endif

@@ -1,0 +1,414 @@
+"""Pins of the CPU oracle's solid-level queries against things other than itself:
+closed forms (slab box, ray/sphere in 50-digit arithmetic, ray/cylinder), reduction
+identities between solids, brute-force ray marching, surface landing, the Safety
+invariant, Monte Carlo volume against analytic volume, and hand-derived Inside codes.
+"""
+import math
+
+import mpmath
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1512_06637_amd import workloads as W
+from tests import pins
+
+SOLIDS = W.config_solids()
+SOLIDS_H = W.config_solids(hollow_pcon=True)
+ALL = dict(SOLIDS, pcon_hollow=SOLIDS_H["pcon"], cons_seg=W.cons(2.0, 8.0, 4.0, 12.0, 25.0, 0.3, 1.5 * math.pi),
+           tubs_narrow=W.tubs(0.0, 15.0, 20.0, -0.4, 0.7 * math.pi), sphere_full=W.sphere(0.0, 30.0))
+
+
+def tracks_for(name, n, seed=0):
+    s = ALL[name]
+    rng = np.random.default_rng(1000 + seed + sum(map(ord, name)))
+    c, h = W.solid_extent(s)
+    p = W.uniform_box_points(rng, n, c, 2.0 * h)
+    d = W.isotropic(rng, n)
+    return W.Tracks(p[0], p[1], p[2], *d)
+
+
+def near_surface_tracks(name, n, seed=0):
+    s = ALL[name]
+    rng = np.random.default_rng(2000 + seed + sum(map(ord, name)))
+    P, N = W.sample_surface(s, rng, n)
+    P = P + N * rng.uniform(-1e-6, 1e-6, n)[None, :]
+    d = W.isotropic(rng, n)
+    return W.Tracks(P[0], P[1], P[2], *d)
+
+
+# ------------------------------------------------------------------ closed forms
+def test_box_matches_slab_closed_form():
+    s = SOLIDS["box"]
+    t = W.config1_tracks("box", 20000)
+    code = O.inside(s, t.x, t.y, t.z)
+    P = np.stack([t.x, t.y, t.z])
+    D = np.stack([t.dx, t.dy, t.dz])
+    din, dgi = O.distance(s, 0, t)
+    dout, dgo = O.distance(s, 1, t)
+    out = code == O.OUTSIDE
+    ins = code == O.INSIDE
+    ref_in = pins.slab_box(s.params, P[:, out], D[:, out], True)
+    ref_out = pins.slab_box(s.params, P[:, ins], D[:, ins], False)
+    ok_i = (dgi[out] & O.D_ILL) == 0
+    ok_o = (dgo[ins] & O.D_ILL) == 0
+    assert ok_i.mean() > 0.999 and ok_o.mean() > 0.999
+    a, b = din[out][ok_i], ref_in[ok_i]
+    assert np.array_equal(np.isinf(a), np.isinf(b))
+    f = np.isfinite(b)
+    assert np.all(np.abs(a[f] - b[f]) <= 1e-12 * np.maximum(1.0, b[f]))
+    a, b = dout[ins][ok_o], ref_out[ok_o]
+    assert np.all(np.abs(a - b) <= 1e-12 * np.maximum(1.0, b))
+    # sentinels
+    assert np.all(din[ins] == -1.0) and np.all(dout[out] == -1.0)
+
+
+def _sphere_ref(rmin, rmax, p, d, want_in):
+    mpmath.mp.dps = 50
+    P = [mpmath.mpf(float(v)) for v in p]
+    Dv = [mpmath.mpf(float(v)) for v in d]
+    A = sum(v * v for v in Dv)
+    B = sum(a * b for a, b in zip(P, Dv))
+    rho2 = sum(v * v for v in P)
+
+    def roots(R):
+        disc = B * B - A * (rho2 - R * R)
+        if disc < 0:
+            return None
+        sq = mpmath.sqrt(disc)
+        # FP64 evaluates C = |p|^2 - R^2 with absolute error ~ eps (|p|^2 + R^2);
+        # the root t = C / q inherits it divided by |q| = |B| + sqrt(D)
+        cond = 8 * 2.0 ** -52 * float((rho2 + R * R) / (abs(B) + sq))
+        return ((-B - sq) / A, (-B + sq) / A, cond)
+
+    rho = mpmath.sqrt(rho2)
+    if want_in:
+        if rho > rmax:
+            r = roots(mpmath.mpf(rmax))
+            return (float(r[0]), r[2]) if (r is not None and r[0] > 0 and r[1] > r[0]) else (math.inf, 0.0)
+        r = roots(mpmath.mpf(rmin))
+        return float(r[1]), r[2]
+    r = roots(mpmath.mpf(rmax))
+    best, cond = r[1], r[2]
+    if rmin > 0:
+        ri = roots(mpmath.mpf(rmin))
+        if ri is not None and ri[0] > 0 and ri[0] < best:
+            best, cond = ri[0], ri[2]
+    return float(best), cond
+
+
+def test_sphere_shell_matches_50_digit_closed_form():
+    s = SOLIDS["sphere"]
+    t = W.config2_tracks("sphere", 3000)
+    code = O.inside(s, t.x, t.y, t.z)
+    din, dgi = O.distance(s, 0, t)
+    dout, dgo = O.distance(s, 1, t)
+    checked = 0
+    for i in range(t.n):
+        p = (t.x[i], t.y[i], t.z[i])
+        d = (t.dx[i], t.dy[i], t.dz[i])
+        if code[i] == O.OUTSIDE and not (dgi[i] & O.D_ILL):
+            ref, cond = _sphere_ref(10.0, 30.0, p, d, True)
+            got = din[i]
+        elif code[i] == O.INSIDE and not (dgo[i] & O.D_ILL):
+            ref, cond = _sphere_ref(10.0, 30.0, p, d, False)
+            got = dout[i]
+        else:
+            continue
+        checked += 1
+        if math.isinf(ref):
+            assert math.isinf(got), (i, got, ref)
+        else:
+            assert abs(got - ref) <= 1e-12 * max(1.0, ref) + cond, (i, got, ref, cond)
+    assert checked > 1900
+
+
+def _cyl_interval(R, P, D):
+    A = D[0] ** 2 + D[1] ** 2
+    B = P[0] * D[0] + P[1] * D[1]
+    Cc = P[0] ** 2 + P[1] ** 2 - R * R
+    disc = B * B - A * Cc
+    with np.errstate(divide="ignore", invalid="ignore"):
+        sq = np.sqrt(np.maximum(disc, 0.0))
+        lo = np.where(A > 0, (-B - sq) / A, np.where(Cc <= 0, -np.inf, np.inf))
+        hi = np.where(A > 0, (-B + sq) / A, np.where(Cc <= 0, np.inf, -np.inf))
+    miss = (disc < 0) & (A > 0)
+    return np.where(miss, np.inf, lo), np.where(miss, -np.inf, hi)
+
+
+def test_full_cylinder_matches_closed_form():
+    s = W.tubs(0.0, 15.0, 20.0)
+    rng = np.random.default_rng(7)
+    n = 20000
+    P = rng.uniform(-1, 1, (3, n)) * np.array([30.0, 30.0, 40.0])[:, None]
+    D = np.stack(W.isotropic(rng, n))
+    t = W.Tracks(*P, *D)
+    code = O.inside(s, *P)
+    din, dgi = O.distance(s, 0, t)
+    dout, dgo = O.distance(s, 1, t)
+    clo, chi = _cyl_interval(15.0, P, D)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        z1 = (-20.0 - P[2]) / D[2]
+        z2 = (20.0 - P[2]) / D[2]
+    zlo = np.where(D[2] == 0, -np.inf, np.minimum(z1, z2))
+    zhi = np.where(D[2] == 0, np.inf, np.maximum(z1, z2))
+    tin = np.maximum(clo, zlo)
+    tout = np.minimum(chi, zhi)
+    ref_in = np.where((tout > tin) & (tout > 0), np.maximum(tin, 0.0), np.inf)
+    ref_out = np.maximum(tout, 0.0)
+    o = (code == O.OUTSIDE) & ((dgi & O.D_ILL) == 0)
+    i = (code == O.INSIDE) & ((dgo & O.D_ILL) == 0)
+    assert o.sum() > 10000 and i.sum() > 1000
+    assert np.array_equal(np.isinf(din[o]), np.isinf(ref_in[o]))
+    f = o & np.isfinite(ref_in)
+    assert np.all(np.abs(din[f] - ref_in[f]) <= 1e-12 * np.maximum(1.0, ref_in[f]))
+    assert np.all(np.abs(dout[i] - ref_out[i]) <= 1e-12 * np.maximum(1.0, ref_out[i]))
+
+
+# ----------------------------------------------------------- reduction identities
+REDUCTIONS = [
+    ("trd_to_box", W.trd(10.0, 10.0, 20.0, 20.0, 30.0), W.box(10.0, 20.0, 30.0)),
+    ("cons_to_tubs", W.cons(5.0, 15.0, 5.0, 15.0, 20.0, 0.0, 1.5 * math.pi), W.tubs(5.0, 15.0, 20.0, 0.0, 1.5 * math.pi)),
+    ("cons_to_tubs_full", W.cons(0.0, 15.0, 0.0, 15.0, 20.0), W.tubs(0.0, 15.0, 20.0)),
+    ("pcon2_to_cons", W.pcon([-25.0, 25.0], [2.0, 4.0], [8.0, 12.0]), W.cons(2.0, 8.0, 4.0, 12.0, 25.0)),
+    ("pcon3_collinear_to_cons", W.pcon([-25.0, 5.0, 25.0], [0.0, 0.0, 0.0], [8.0, 10.4, 12.0]),
+     W.cons(0.0, 8.0, 0.0, 12.0, 25.0)),
+]
+
+
+@pytest.mark.parametrize("name,a,b", REDUCTIONS, ids=[r[0] for r in REDUCTIONS])
+def test_reduction_identities(name, a, b):
+    rng = np.random.default_rng(11)
+    n = 20000
+    c, h = W.solid_extent(b)
+    P = W.uniform_box_points(rng, n, c, 2.0 * h)
+    D = np.stack(W.isotropic(rng, n))
+    t = W.Tracks(*P, *D)
+    ca, cb = O.inside(a, *P), O.inside(b, *P)
+    assert np.mean(ca == cb) > 0.9999
+    same = ca == cb
+    for direction in (0, 1):
+        da, ga = O.distance(a, direction, t)
+        db, gb = O.distance(b, direction, t)
+        ok = same & (((ga | gb) & O.D_ILL) == 0)
+        assert np.array_equal(np.isinf(da[ok]), np.isinf(db[ok]))
+        f = ok & np.isfinite(db)
+        assert np.all(np.abs(da[f] - db[f]) <= 1e-12 * np.maximum(1.0, np.abs(db[f]))), name
+    if name != "pcon2_to_cons" and name != "pcon3_collinear_to_cons":
+        # Safety formulas are the same lower bounds (polycone safety is exact instead)
+        for mode in (0,):
+            sa, sb = O.safety(a, mode, *P), O.safety(b, mode, *P)
+            assert np.all(np.abs(sa[same] - sb[same]) <= 1e-12 * np.maximum(1.0, sb[same]))
+
+
+# -------------------------------------------------------------- brute force march
+def _march(s, t, want, h=2e-3, tmax=None):
+    """First t where the Inside code becomes `want` (INSIDE or OUTSIDE) found by
+    stepping h along the ray with the Inside code only, then bisecting."""
+    res = np.full(t.n, np.inf)
+    c, ext = W.solid_extent(s)
+    for i in range(t.n):
+        p = np.array([t.x[i], t.y[i], t.z[i]])
+        d = np.array([t.dx[i], t.dy[i], t.dz[i]])
+        T = tmax or (np.linalg.norm(p - c) + 2.0 * np.linalg.norm(ext))
+        ts = np.arange(1, int(T / h) + 2) * h
+        Q = p[:, None] + ts[None, :] * d[:, None]
+        code = O.inside(s, Q[0], Q[1], Q[2], threads=8)
+        hit = np.nonzero(code == want)[0]
+        if hit.size == 0:
+            continue
+        k = hit[0]
+        lo = ts[k - 1] if k > 0 else 0.0
+        hi = ts[k]
+        for _ in range(45):
+            mid = 0.5 * (lo + hi)
+            q = p + mid * d
+            if O.inside(s, q[0:1], q[1:2], q[2:3], threads=1)[0] == want:
+                hi = mid
+            else:
+                lo = mid
+        res[i] = lo
+    return res
+
+
+@pytest.mark.parametrize("name", ["box", "tubs", "cons", "sphere", "trd", "pcon", "pcon_hollow", "cons_seg",
+                                  "tubs_narrow"])
+def test_distances_match_ray_marching(name):
+    s = ALL[name]
+    t = tracks_for(name, 120, seed=3)
+    code = O.inside(s, t.x, t.y, t.z)
+    din, dgi = O.distance(s, 0, t)
+    dout, dgo = O.distance(s, 1, t)
+    mi = _march(s, t, O.INSIDE)
+    mo = _march(s, t, O.OUTSIDE)
+    for i in range(t.n):
+        if code[i] == O.OUTSIDE and not (dgi[i] & O.D_ILL):
+            if math.isinf(mi[i]):
+                assert math.isinf(din[i]), (name, i, din[i])
+            else:
+                # the marcher lands within the surface band: |error| < band / |cos|
+                assert abs(din[i] - mi[i]) < 2e-6, (name, i, din[i], mi[i])
+        if code[i] == O.INSIDE and not (dgo[i] & O.D_ILL):
+            assert abs(dout[i] - mo[i]) < 2e-6, (name, i, dout[i], mo[i])
+
+
+# ------------------------------------------------------------- surface landing
+@pytest.mark.parametrize("name", list(ALL))
+def test_surface_landing(name):
+    s = ALL[name]
+    for t in (tracks_for(name, 20000), near_surface_tracks(name, 20000)):
+        code = O.inside(s, t.x, t.y, t.z)
+        for direction, side in ((0, O.OUTSIDE), (1, O.INSIDE)):
+            dist, dg = O.distance(s, direction, t)
+            m = (code == side) & np.isfinite(dist) & ((dg & O.D_ILL) == 0)
+            assert m.sum() > 200
+            q = [a[m] + dist[m] * b[m] for a, b in ((t.x, t.dx), (t.y, t.dy), (t.z, t.dz))]
+            qc = O.inside(s, *q)
+            assert np.all(qc == O.SURFACE), (name, direction, np.nonzero(qc != O.SURFACE)[0][:5])
+
+
+def test_sentinels_and_misses():
+    s = SOLIDS["box"]
+    t = W.Tracks(*[np.array(v, dtype=float) for v in
+                   ([0.0, 50.0, 50.0, 10.0], [0.0, 0.0, 0.0, 0.0], [0.0, 0.0, 0.0, 0.0],
+                    [1.0, 1.0, -1.0, 1.0], [0.0, 0.0, 0.0, 0.0], [0.0, 0.0, 0.0, 0.0])])
+    din, _ = O.distance(s, 0, t)
+    dout, _ = O.distance(s, 1, t)
+    assert din[0] == -1.0 and dout[1] == -1.0
+    assert math.isinf(din[1]) and din[2] == 40.0
+    assert dout[0] == 10.0
+    # on the +x face moving out: leaves at once; moving in: enters at once
+    assert dout[3] == 0.0
+    t2 = W.Tracks(*[np.array([v]) for v in (10.0, 0.0, 0.0, -1.0, 0.0, 0.0)])
+    assert O.distance(s, 0, t2)[0][0] == 0.0
+    assert O.distance(s, 1, t2)[0][0] == 20.0
+
+
+# ----------------------------------------------------------------------- safety
+# formula equals the exact distance and the nearest boundary patch is smooth and
+# wide, so the best of 1024 directions comes within 2 % of it
+EXACT_IN = {"box", "trd", "cons", "sphere", "sphere_full"}
+EXACT_OUT = {"sphere", "sphere_full"}
+
+
+@pytest.mark.parametrize("name", list(ALL))
+def test_safety_invariant_and_exactness(name):
+    s = ALL[name]
+    t = tracks_for(name, 150, seed=5)
+    code = O.inside(s, t.x, t.y, t.z)
+    saf = O.safety(s, 0, t.x, t.y, t.z)
+    dirs = pins.fibonacci_dirs(1024)
+    assert np.all(saf >= 0.0)
+    assert np.all(saf[code == O.SURFACE] == 0.0)
+    for i in range(t.n):
+        if code[i] == O.SURFACE:
+            continue
+        rays = W.Tracks(np.full(1024, t.x[i]), np.full(1024, t.y[i]), np.full(1024, t.z[i]), *dirs)
+        direction = 0 if code[i] == O.OUTSIDE else 1
+        dist, _ = O.distance(s, direction, rays, threads=8)
+        m = float(np.min(dist))
+        assert saf[i] <= m + 1e-12, (name, i, saf[i], m)
+        exact = name in (EXACT_OUT if code[i] == O.OUTSIDE else EXACT_IN)
+        if exact:
+            assert m <= saf[i] * 1.02 + 1e-9, (name, i, saf[i], m)
+    # wrong-side sentinels of the one-sided modes
+    s_in = O.safety(s, 1, t.x, t.y, t.z)
+    s_out = O.safety(s, 2, t.x, t.y, t.z)
+    assert np.all(s_in[code == O.INSIDE] == -1.0) and np.all(s_out[code == O.OUTSIDE] == -1.0)
+
+
+def _profile_points(s, step=2e-3):
+    """Dense samples of the polycone's meridian boundary (lateral segments, inner
+    segments off the axis, end caps)."""
+    z, rmin, rmax = W.pcon_arrays(s)
+    segs = []
+    for j in range(len(z) - 1):
+        segs.append(((rmax[j], z[j]), (rmax[j + 1], z[j + 1])))
+        if rmin[j] > 0 or rmin[j + 1] > 0:
+            segs.append(((rmin[j], z[j]), (rmin[j + 1], z[j + 1])))
+    segs.append(((rmin[0], z[0]), (rmax[0], z[0])))
+    segs.append(((rmin[-1], z[-1]), (rmax[-1], z[-1])))
+    pts = []
+    for (r1, z1), (r2, z2) in segs:
+        n = max(2, int(math.hypot(r2 - r1, z2 - z1) / step) + 1)
+        u = np.linspace(0.0, 1.0, n)
+        pts.append(np.stack([r1 + u * (r2 - r1), z1 + u * (z2 - z1)]))
+    return np.concatenate(pts, axis=1)
+
+
+@pytest.mark.parametrize("name", ["pcon", "pcon_hollow"])
+def test_polycone_safety_equals_profile_distance(name):
+    s = ALL[name]
+    prof = _profile_points(s)
+    t = tracks_for(name, 300, seed=9)
+    code = O.inside(s, t.x, t.y, t.z)
+    saf = O.safety(s, 0, t.x, t.y, t.z)
+    r = np.hypot(t.x, t.y)
+    for i in range(t.n):
+        if code[i] == O.SURFACE:
+            continue
+        dmin = np.min(np.hypot(prof[0] - r[i], prof[1] - t.z[i]))
+        # sampling spacing 2e-3 mm bounds the brute-force excess by 1e-3 mm
+        assert saf[i] <= dmin + 1e-12 and dmin - saf[i] < 1.1e-3, (name, i, saf[i], dmin)
+
+
+def test_box_outside_safety_exact_in_face_regions():
+    s = SOLIDS["box"]
+    rng = np.random.default_rng(3)
+    n = 5000
+    P = rng.uniform(-1, 1, (3, n)) * np.array([10.0, 20.0, 30.0])[:, None]
+    P[0] = 10.0 + rng.uniform(0.01, 5.0, n)  # outside only across the +x face
+    saf = O.safety(s, 0, *P)
+    assert np.allclose(saf, P[0] - 10.0, rtol=0, atol=1e-12)
+
+
+# ----------------------------------------------------------------------- volume
+@pytest.mark.parametrize("name", list(ALL))
+def test_monte_carlo_volume(name):
+    s = ALL[name]
+    rng = np.random.default_rng(99)
+    c, h = W.solid_extent(s)
+    n = 2_000_000
+    P = W.uniform_box_points(rng, n, c, h)
+    f = np.mean(O.inside(s, *P) != O.OUTSIDE)
+    vbox = 8.0 * np.prod(h)
+    v = f * vbox
+    sigma = math.sqrt(f * (1 - f) / n) * vbox
+    ref = pins.analytic_volume(s)
+    assert abs(v - ref) < 4.0 * sigma + 1e-9, (name, v, ref, sigma)
+
+
+# ------------------------------------------------------------------ inside codes
+def _codes(s, pts):
+    P = np.array(pts, dtype=float).T
+    return list(O.inside(s, P[0], P[1], P[2]))
+
+
+def test_inside_codes_hand_derived():
+    b = SOLIDS["box"]
+    assert _codes(b, [(10, 0, 0), (10 + 1e-9, 0, 0), (10 - 1e-9, 0, 0), (10, 20, 30), (0, 0, 0), (4e-10 + 10, 0, 0)]) == \
+        [1, 0, 2, 1, 2, 1]
+    tb = SOLIDS["tubs"]  # rmin 5, rmax 15, dz 20, phi in [0, 1.5 pi]
+    assert _codes(tb, [(0, 0, 0), (10, 0, 0), (0, -10, 0), (7, -7, 0), (-10, 0, 0), (0, 10, 20), (5, 0, 1e-3),
+                       (0, 15, 0), (10, 1e-3, 0), (10, -1e-3, 0), (1e-3, -10, 0), (-1e-3, -10, 0)]) == \
+        [0, 1, 1, 0, 2, 1, 1, 1, 2, 0, 0, 2]
+    sp = SOLIDS["sphere"]
+    assert _codes(sp, [(0, 0, 0), (0, 0, 10), (0, 0, 20), (30, 0, 0), (0, 0, 30.001)]) == [0, 1, 2, 1, 0]
+    cn = SOLIDS["cons"]  # rmin 2->4, rmax 8->12 over z -25..25
+    assert _codes(cn, [(8, 0, -25), (10, 0, 0), (3, 0, 0), (1, 0, 0), (12, 0, 25), (0, 11.9, 25.0 - 1e-3)]) == \
+        [1, 1, 1, 0, 1, 2]
+    td = SOLIDS["trd"]  # dx 10->20, dy 15->25 over z -30..30
+    assert _codes(td, [(15, 0, 0), (0, 20, 0), (0, 0, 30), (14.9, 19.9, 0), (20, 25, 30), (10.5, 0, -30)]) == \
+        [1, 1, 1, 2, 1, 0]
+    pc = SOLIDS["pcon"]
+    z, _, rmax = W.pcon_arrays(pc)
+    pts = [(0, 0, z[0]), (0, 0, 0.5 * (z[0] + z[1])), (rmax[3], 0, z[3]), (rmax[3] + 1e-3, 0, z[3]), (0, 0, z[-1] + 1e-3)]
+    assert _codes(pc, pts) == [1, 2, 1, 0, 0]
+
+
+def test_rejects_invalid_parameters():
+    assert O.solid_ok(SOLIDS["box"])
+    assert not O.solid_ok(W.box(-1.0, 1.0, 1.0))
+    assert not O.solid_ok(W.tubs(10.0, 5.0, 1.0))
+    assert not O.solid_ok(W.pcon([0.0, 0.0], [0.0, 0.0], [1.0, 1.0]))
+    assert not O.solid_ok(W.sphere(5.0, 5.0))
