@@ -1,0 +1,136 @@
+"""Benchmark: FP64 basket navigation through the layered detector on one MI355X.
+
+Workload (one "step" of this benchmark = one nav_transport call over the whole
+batch): 2^20 straight tracks starting uniformly in [-1, 1]^3 mm with isotropic
+directions, transported through the layered detector (world box 4 x 4 x 6 m,
+20 tube layers x 64 box modules, 1,301 placed volumes) until they leave the
+world, recording every track's volume sequence and step lengths.  Inputs are
+resident in HBM before timing starts.
+
+Metric: track-steps/s = (track-steps the batch takes) / (device time per call).
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def cpu_baseline(blob, tracks, target_s=12.0, max_s=30.0):
+    """The CPU oracle on a bounded sample of the same workload, on this host's
+    cores; returns track-steps/s over the sample."""
+    import numpy as np
+
+    import oracle as O
+
+    threads = O.default_threads()
+    og = O.Geometry(blob)
+    done_tracks = done_steps = 0
+    spent = 0.0
+    chunk = 8192
+    start = 0
+    while spent < target_s and start < tracks.n:
+        idx = np.arange(start, min(start + chunk, tracks.n))
+        t0 = time.perf_counter()
+        r = og.transport(tracks.take(idx), threads=threads)
+        spent += time.perf_counter() - t0
+        done_tracks += idx.size
+        done_steps += int(r["nsteps"].sum())
+        start += idx.size
+        if spent < target_s / 4:
+            chunk *= 2
+        if spent > max_s:
+            break
+    og.close()
+    return {"value": done_steps / spent, "unit": "track-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {done_tracks} of the 2^20 tracks ({done_steps} track-steps, {spent:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "tracks are independent, so more GPUs would each transport a contiguous shard", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1512_06637_amd as G
+    from paper_1512_06637_amd import roofline as R
+    from paper_1512_06637_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    blob = W.detector_blob()
+    tracks = W.config3_tracks(args.n)
+    g = G.Geometry(blob)
+    a = [torch.from_numpy(v).to("cuda") for v in tracks.arrays()]
+    max_steps = 128
+    n = tracks.n
+    out = {
+        "pv": torch.empty((n, max_steps + 1), dtype=torch.int32, device="cuda"),
+        "step": torch.empty((n, max_steps), dtype=torch.float64, device="cuda"),
+        "nsteps": torch.empty(n, dtype=torch.int32, device="cuda"),
+        "flags": torch.empty(n, dtype=torch.int32, device="cuda"),
+    }
+    for _ in range(args.warmup):
+        g.transport(*a, max_steps=max_steps, out=out)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        g.transport(*a, max_steps=max_steps, out=out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1) / args.steps
+
+    ns = out["nsteps"].cpu().numpy()
+    pv = out["pv"].cpu().numpy()
+    flags = out["flags"].cpu().numpy()
+    total_steps = int(ns.sum())
+    world, layer, module = R.detector_step_classes(pv, ns)
+    ops = R.detector_ops(world, layer, module)
+    achieved = ops / (ms * 1e-3)
+    res = {
+        "metric": "track-steps/s",
+        "value": total_steps / (ms * 1e-3),
+        "unit": "track-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "layered-detector navigation FP64: 2^20 origin tracks to world exit, 1301 PVs",
+                   "tracks": n, "track_steps": total_steps, "max_steps": max_steps,
+                   "steps_world_layer_module": [world, layer, module], "kernel": "k_transport_lane"},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": R.PEAK_FP64_OPS / 1e12,
+                     "unit": "TOP/s (FP64 lane-ops)", "frac": achieved / R.PEAK_FP64_OPS, "traffic": None},
+        "wall_s": wall,
+        "flags_nonzero": int((flags != 0).sum()),
+    }
+    g.close()
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(blob, tracks)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,252 @@
+"""Python binding of libgvgeom.so -- the MI355X basket geometry library.
+
+Argument marshalling only: every query runs in the HIP kernels behind the C-ABI of
+include/gvgeom.h.  torch supplies device memory (tensors on "cuda") and the
+current HIP stream; it computes nothing here.  There is no CPU fallback: if the
+library is missing or no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgvgeom.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "gvgeom.h")
+
+GV_OK, GV_EINVAL, GV_ENOMEM, GV_EHIP, GV_EFORMAT, GV_ESTATE = 0, -1, -2, -3, -4, -5
+OUTSIDE, SURFACE, INSIDE = 0, 1, 2
+TO_IN, TO_OUT = 0, 1
+SAFETY_AUTO, SAFETY_IN, SAFETY_OUT = 0, 1, 2
+FP64, FP32_REFINE = 0, 1
+FLAG_OVERFLOW, FLAG_STUCK, FLAG_LOCATE_FAIL = 1, 2, 4
+
+_P = C.c_void_p
+_I32 = C.c_int32
+_I64 = C.c_int64
+_SIGS = {
+    "geom_load": [_P, C.c_size_t, C.POINTER(_P)],
+    "geom_free": [_P],
+    "geom_info": [_P, _P],
+    "basket_inside": [_P, _I32, _I64, _P, _P, _P, _P, _P],
+    "basket_safety": [_P, _I32, _I32, _I64, _P, _P, _P, _P, _P, _I32, _P],
+    "basket_distance": [_P, _I32, _I32, _I64] + [_P] * 7 + [_I32, _P],
+    "basket_solid_all": [_P, _I32, _I64] + [_P] * 10 + [_P],
+    "basket_locate": [_P, _I64, _P, _P, _P, _P, _P],
+    "basket_step": [_P, _I64] + [_P] * 11 + [_I32, _P],
+    "basket_nav_safety": [_P, _I64, _P, _P, _P, _P, _P, _I32, _P],
+    "basket_nav_inside": [_P, _I64, _P, _P, _P, _P, _P, _P],
+    "nav_transport": [_P, _I64] + [_P] * 7 + [_I32] + [_P] * 4 + [_I32, _P],
+}
+
+_lib = None
+
+
+class GVError(RuntimeError):
+    def __init__(self, fn, code, msg):
+        super().__init__(f"{fn} failed ({code}): {msg}")
+        self.code = code
+
+
+def lib():
+    """Load libgvgeom.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is None:
+        # torch ships its own libamdhip64.so.7; loading it first lets the library
+        # bind to that runtime by SONAME, so the process holds one HIP runtime
+        # and torch's device pointers and streams are valid in our launches.
+        import torch  # noqa: F401
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.gv_last_error.restype = C.c_char_p
+        L.gv_last_error.argtypes = []
+        _lib = L
+    return _lib
+
+
+def header_functions():
+    """Names of the functions declared by include/gvgeom.h."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(\w+)\s*\(", txt, flags=re.M)))
+
+
+def _check(fn, rc):
+    if rc != GV_OK:
+        raise GVError(fn, rc, lib().gv_last_error().decode(errors="replace"))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    return C.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype, name, numel=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch tensor on the GPU")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name}: tensor must live on the GPU (got {t.device})")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: tensor must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name}: expected {numel} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _opt(t, dtype, name, numel=None):
+    return None if t is None else _dev(t, dtype, name, numel)
+
+
+def _n(*ts):
+    """Common length of the basket arrays; every array must hold exactly n elements."""
+    n = ts[0].numel()
+    for t in ts[1:]:
+        if t is not None and t.numel() != n:
+            raise ValueError(f"basket arrays differ in length ({t.numel()} != {n})")
+    return n
+
+
+class Geometry:
+    """A geometry resident on the current GPU (geom_load / geom_free)."""
+
+    def __init__(self, blob: bytes):
+        h = C.c_void_p()
+        buf = C.create_string_buffer(bytes(blob), len(blob))
+        _check("geom_load", lib().geom_load(buf, len(blob), C.byref(h)))
+        self._h = h
+        counts = (C.c_int32 * 4)()
+        _check("geom_info", lib().geom_info(self._h, counts))
+        self.n_lv, self.n_pv, self.max_depth, self.world_lv = list(counts)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            h, self._h = self._h, None
+            _check("geom_free", lib().geom_free(h))
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ----------------------------------------------------------- solid level
+    def inside(self, lv, x, y, z, out=None):
+        torch = _torch()
+        n = _n(x, y, z, out)
+        out = torch.empty(n, dtype=torch.int8, device=x.device) if out is None else out
+        f64 = torch.float64
+        _check("basket_inside", lib().basket_inside(self._h, lv, n, _dev(x, f64, "x"), _dev(y, f64, "y"),
+                                                    _dev(z, f64, "z"), _dev(out, torch.int8, "out"), _stream()))
+        return out
+
+    def safety(self, lv, x, y, z, side=SAFETY_AUTO, out=None, out_inside=None, precision=FP64):
+        torch = _torch()
+        n = _n(x, y, z, out, out_inside)
+        out = torch.empty(n, dtype=torch.float64, device=x.device) if out is None else out
+        f64 = torch.float64
+        _check("basket_safety", lib().basket_safety(
+            self._h, lv, side, n, _dev(x, f64, "x"), _dev(y, f64, "y"), _dev(z, f64, "z"), _dev(out, f64, "out"),
+            _opt(out_inside, torch.int8, "out_inside"), precision, _stream()))
+        return out
+
+    def distance(self, lv, direction, x, y, z, dx, dy, dz, out=None, precision=FP64):
+        torch = _torch()
+        n = _n(x, y, z, dx, dy, dz, out)
+        out = torch.empty(n, dtype=torch.float64, device=x.device) if out is None else out
+        f64 = torch.float64
+        a = [_dev(v, f64, nm) for v, nm in zip((x, y, z, dx, dy, dz), ("x", "y", "z", "dx", "dy", "dz"))]
+        _check("basket_distance", lib().basket_distance(self._h, lv, direction, n, *a, _dev(out, f64, "out"),
+                                                        precision, _stream()))
+        return out
+
+    def solid_all(self, lv, x, y, z, dx, dy, dz, out_inside=None, out_safety=None, out_din=None, out_dout=None):
+        torch = _torch()
+        n = _n(x, y, z, dx, dy, dz, out_inside, out_safety, out_din, out_dout)
+        f64 = torch.float64
+        a = [_dev(v, f64, nm) for v, nm in zip((x, y, z, dx, dy, dz), ("x", "y", "z", "dx", "dy", "dz"))]
+        _check("basket_solid_all", lib().basket_solid_all(
+            self._h, lv, n, *a, _opt(out_inside, torch.int8, "out_inside"), _opt(out_safety, f64, "out_safety"),
+            _opt(out_din, f64, "out_din"), _opt(out_dout, f64, "out_dout"), _stream()))
+
+    # ------------------------------------------------------------ navigation
+    def locate(self, x, y, z, out=None):
+        torch = _torch()
+        n = _n(x, y, z, out)
+        out = torch.empty(n, dtype=torch.int32, device=x.device) if out is None else out
+        f64 = torch.float64
+        _check("basket_locate", lib().basket_locate(self._h, n, _dev(x, f64, "x"), _dev(y, f64, "y"),
+                                                    _dev(z, f64, "z"), _dev(out, torch.int32, "out"), _stream()))
+        return out
+
+    def step(self, x, y, z, dx, dy, dz, pv, pstep=None, out_step=None, out_next=None, out_flags=None,
+             precision=FP64):
+        torch = _torch()
+        n = _n(x, y, z, dx, dy, dz, pv, pstep, out_step, out_next, out_flags)
+        f64 = torch.float64
+        out_step = torch.empty(n, dtype=f64, device=x.device) if out_step is None else out_step
+        out_next = torch.empty(n, dtype=torch.int32, device=x.device) if out_next is None else out_next
+        a = [_dev(v, f64, nm) for v, nm in zip((x, y, z, dx, dy, dz), ("x", "y", "z", "dx", "dy", "dz"))]
+        _check("basket_step", lib().basket_step(
+            self._h, n, *a, _dev(pv, torch.int32, "pv"), _opt(pstep, f64, "pstep"), _dev(out_step, f64, "out_step"),
+            _dev(out_next, torch.int32, "out_next"), _opt(out_flags, torch.int32, "out_flags"), precision,
+            _stream()))
+        return out_step, out_next
+
+    def nav_safety(self, x, y, z, pv, out=None, precision=FP64):
+        torch = _torch()
+        n = _n(x, y, z, pv, out)
+        f64 = torch.float64
+        out = torch.empty(n, dtype=f64, device=x.device) if out is None else out
+        _check("basket_nav_safety", lib().basket_nav_safety(
+            self._h, n, _dev(x, f64, "x"), _dev(y, f64, "y"), _dev(z, f64, "z"), _dev(pv, torch.int32, "pv"),
+            _dev(out, f64, "out"), precision, _stream()))
+        return out
+
+    def nav_inside(self, x, y, z, pv, out=None):
+        torch = _torch()
+        n = _n(x, y, z, pv, out)
+        f64 = torch.float64
+        out = torch.empty(n, dtype=torch.int8, device=x.device) if out is None else out
+        _check("basket_nav_inside", lib().basket_nav_inside(
+            self._h, n, _dev(x, f64, "x"), _dev(y, f64, "y"), _dev(z, f64, "z"), _dev(pv, torch.int32, "pv"),
+            _dev(out, torch.int8, "out"), _stream()))
+        return out
+
+    def transport(self, x, y, z, dx, dy, dz, start_pv=None, max_steps=128, out=None, precision=FP64):
+        """Returns dict(pv [n, max_steps+1] int32, step [n, max_steps] f64, nsteps, flags)."""
+        torch = _torch()
+        n = _n(x, y, z, dx, dy, dz, start_pv)
+        f64 = torch.float64
+        if out is None:
+            out = {
+                "pv": torch.full((n, max_steps + 1), -2, dtype=torch.int32, device=x.device),
+                "step": torch.full((n, max_steps), float("nan"), dtype=f64, device=x.device),
+                "nsteps": torch.empty(n, dtype=torch.int32, device=x.device),
+                "flags": torch.empty(n, dtype=torch.int32, device=x.device),
+            }
+        a = [_dev(v, f64, nm) for v, nm in zip((x, y, z, dx, dy, dz), ("x", "y", "z", "dx", "dy", "dz"))]
+        _check("nav_transport", lib().nav_transport(
+            self._h, n, *a, _opt(start_pv, torch.int32, "start_pv"), max_steps,
+            _dev(out["pv"], torch.int32, "pv", n * (max_steps + 1)), _dev(out["step"], f64, "step", n * max_steps),
+            _dev(out["nsteps"], torch.int32, "nsteps", n), _dev(out["flags"], torch.int32, "flags", n), precision,
+            _stream()))
+        return out

@@ -1,0 +1,660 @@
+// Host side of the C-ABI declared in include/gvgeom.h: argument validation,
+// geometry-blob parsing and upload, kernel selection and launch on the
+// caller's stream.  No exception or abort crosses the boundary.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/gvgeom.h"
+#include "gv_kernels.h"
+
+using namespace gv;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string t_err;
+
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  t_err = buf;
+  return code;
+}
+
+static int hip_fail(hipError_t e, const char* what) {
+  return fail(GV_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+extern "C" const char* gv_last_error(void) { return t_err.c_str(); }
+
+// --------------------------------------------------------------- geometry
+struct gv_geom {
+  int device = -1;
+  DevGeom dg{};
+  int n_lv = 0, n_pv = 0, n_place = 0, max_depth = 0, world_lv = 0;
+  std::vector<int> lv_type, lv_par;
+  void* dmem = nullptr;
+  // nav_transport workspace (grown on demand)
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+};
+
+namespace {
+
+constexpr int kMaxDepth = 32;
+constexpr long kMaxPv = 1L << 24;
+constexpr int kMaxNz = 64;
+
+int32_t rd_i32(const unsigned char* b, size_t off) {
+  int32_t v;
+  std::memcpy(&v, b + off, 4);
+  return v;
+}
+double rd_f64(const unsigned char* b, size_t off) {
+  double v;
+  std::memcpy(&v, b + off, 8);
+  return v;
+}
+
+// Derived constants of each solid (reciprocal slopes, normalisations, the phi
+// half-plane normals) -- see the parameter layouts in gv_solids.h.
+int phi_mode(double dphi) { return dphi >= 2.0 * M_PI ? 0 : (dphi <= M_PI ? 1 : 2); }
+void phi_vectors(double sphi, double dphi, double* ns, double* ne, double* us, double* ue) {
+  double pe = sphi + dphi;
+  ns[0] = std::sin(sphi);
+  ns[1] = -std::cos(sphi);
+  ne[0] = -std::sin(pe);
+  ne[1] = std::cos(pe);
+  us[0] = std::cos(sphi);
+  us[1] = std::sin(sphi);
+  ue[0] = std::cos(pe);
+  ue[1] = std::sin(pe);
+}
+
+bool derive(int type, const double* q, int nq, std::vector<double>& out, std::string& why) {
+  auto bad = [&](const char* m) {
+    why = m;
+    return false;
+  };
+  switch (type) {
+    case kBox:
+      if (nq != 3 || !(q[0] > 0 && q[1] > 0 && q[2] > 0)) return bad("box needs dx, dy, dz > 0");
+      out.insert(out.end(), q, q + 3);
+      return true;
+    case kTubs: {
+      if (nq != 5 || !(q[0] >= 0 && q[1] > q[0] && q[2] > 0 && q[4] > 0))
+        return bad("tube segment needs 0 <= rmin < rmax, dz > 0, dphi > 0");
+      double v[L::TB_N] = {};
+      v[L::TB_RMIN] = q[0];
+      v[L::TB_RMAX] = q[1];
+      v[L::TB_DZ] = q[2];
+      v[L::TB_PHI] = phi_mode(q[4]);
+      phi_vectors(q[3], q[4], v + L::TB_NS, v + L::TB_NE, v + L::TB_US, v + L::TB_UE);
+      v[L::TB_RMIN2] = q[0] * q[0];
+      v[L::TB_RMAX2] = q[1] * q[1];
+      out.insert(out.end(), v, v + L::TB_N);
+      return true;
+    }
+    case kCons: {
+      if (nq != 7) return bad("cone segment needs 7 parameters");
+      double rmin1 = q[0], rmax1 = q[1], rmin2 = q[2], rmax2 = q[3], dz = q[4];
+      if (!(rmin1 >= 0 && rmax1 >= rmin1 && rmin2 >= 0 && rmax2 >= rmin2 && rmax1 + rmax2 > 0 && dz > 0 && q[6] > 0))
+        return bad("cone segment needs 0 <= rmin <= rmax at both ends, dz > 0, dphi > 0");
+      double v[L::CN_N] = {};
+      for (int i = 0; i < 5; ++i) v[i] = q[i];
+      v[L::CN_PHI] = phi_mode(q[6]);
+      phi_vectors(q[5], q[6], v + L::CN_NS, v + L::CN_NE, v + L::CN_US, v + L::CN_UE);
+      v[L::CN_AO] = 0.5 * (rmax1 + rmax2);
+      v[L::CN_BO] = (rmax2 - rmax1) / (2.0 * dz);
+      v[L::CN_CO] = 1.0 / std::sqrt(1.0 + v[L::CN_BO] * v[L::CN_BO]);
+      v[L::CN_AI] = 0.5 * (rmin1 + rmin2);
+      v[L::CN_BI] = (rmin2 - rmin1) / (2.0 * dz);
+      v[L::CN_CI] = 1.0 / std::sqrt(1.0 + v[L::CN_BI] * v[L::CN_BI]);
+      v[L::CN_INNER] = (rmin1 > 0 || rmin2 > 0) ? 1.0 : 0.0;
+      out.insert(out.end(), v, v + L::CN_N);
+      return true;
+    }
+    case kSphere: {
+      if (nq != 2 || !(q[0] >= 0 && q[1] > q[0])) return bad("sphere shell needs 0 <= rmin < rmax");
+      double v[L::SP_N] = {q[0], q[1], q[0] * q[0], q[1] * q[1]};
+      out.insert(out.end(), v, v + L::SP_N);
+      return true;
+    }
+    case kTrd: {
+      if (nq != 5 || !(q[0] > 0 && q[1] > 0 && q[2] > 0 && q[3] > 0 && q[4] > 0)) return bad("trd needs all > 0");
+      double v[L::TD_N];
+      for (int i = 0; i < 5; ++i) v[i] = q[i];
+      double dz = q[4];
+      v[L::TD_X0] = 0.5 * (q[0] + q[1]);
+      v[L::TD_TX] = (q[1] - q[0]) / (2.0 * dz);
+      v[L::TD_CX] = 1.0 / std::sqrt(1.0 + v[L::TD_TX] * v[L::TD_TX]);
+      v[L::TD_Y0] = 0.5 * (q[2] + q[3]);
+      v[L::TD_TY] = (q[3] - q[2]) / (2.0 * dz);
+      v[L::TD_CY] = 1.0 / std::sqrt(1.0 + v[L::TD_TY] * v[L::TD_TY]);
+      out.insert(out.end(), v, v + L::TD_N);
+      return true;
+    }
+    case kPcon: {
+      if (nq < 1) return bad("polycone needs nz");
+      int nz = (int)q[0];
+      if (nz < 2 || nz > kMaxNz || (double)nz != q[0] || nq != 1 + 3 * nz)
+        return bad("polycone needs 2 <= nz <= 64 and 1 + 3 nz parameters");
+      const double *z = q + 1, *rmin = q + 1 + nz, *rmax = q + 1 + 2 * nz;
+      for (int j = 0; j < nz; ++j) {
+        if (!(rmin[j] >= 0 && rmax[j] >= rmin[j])) return bad("polycone needs 0 <= rmin <= rmax");
+        if (j > 0 && !(z[j] > z[j - 1])) return bad("polycone z planes must increase");
+      }
+      out.push_back(nz);
+      out.insert(out.end(), z, z + nz);
+      out.insert(out.end(), rmin, rmin + nz);
+      out.insert(out.end(), rmax, rmax + nz);
+      std::vector<double> bo(nz - 1), co(nz - 1), bi(nz - 1), ci(nz - 1), in(nz - 1);
+      for (int j = 0; j + 1 < nz; ++j) {
+        if (!(rmax[j] + rmax[j + 1] > 0)) return bad("polycone section with zero outer radius");
+        double h = z[j + 1] - z[j];
+        bo[j] = (rmax[j + 1] - rmax[j]) / h;
+        co[j] = 1.0 / std::sqrt(1.0 + bo[j] * bo[j]);
+        bi[j] = (rmin[j + 1] - rmin[j]) / h;
+        ci[j] = 1.0 / std::sqrt(1.0 + bi[j] * bi[j]);
+        in[j] = (rmin[j] > 0 || rmin[j + 1] > 0) ? 1.0 : 0.0;
+      }
+      for (auto* a : {&bo, &co, &bi, &ci, &in}) out.insert(out.end(), a->begin(), a->end());
+      return true;
+    }
+  }
+  why = "unknown solid type";
+  return false;
+}
+
+struct HostTree {
+  std::vector<int> pv_lv, pv_parent, pv_child_off, pv_child;
+  std::vector<double> pv_gxf;
+  int max_depth = 0;
+};
+
+// composed transform C = A o B (apply B then A): R = Ra Rb, t = Ra tb + ta
+void compose(const double* A, const double* B, double* C) {
+  for (int i = 0; i < 3; ++i) {
+    for (int j = 0; j < 3; ++j)
+      C[3 * i + j] = A[3 * i + 0] * B[0 + j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+    C[9 + i] = A[3 * i + 0] * B[9] + A[3 * i + 1] * B[10] + A[3 * i + 2] * B[11] + A[9 + i];
+  }
+}
+
+}  // namespace
+
+extern "C" int geom_load(const void* blob, size_t nbytes, gv_geom** out) {
+  if (!out) return fail(GV_EINVAL, "geom_load: out is NULL");
+  *out = nullptr;
+  if (!blob) return fail(GV_EINVAL, "geom_load: blob is NULL");
+  const unsigned char* b = (const unsigned char*)blob;
+  static const unsigned char magic[8] = {'G', 'V', 'G', 'E', 'O', 'M', 0, 1};
+  if (nbytes < 32 || std::memcmp(b, magic, 8) != 0) return fail(GV_EFORMAT, "geom_load: bad magic");
+  int version = rd_i32(b, 8), n_lv = rd_i32(b, 12), n_place = rd_i32(b, 16), n_param = rd_i32(b, 20),
+      world = rd_i32(b, 24);
+  if (version != 1) return fail(GV_EFORMAT, "geom_load: unsupported version %d", version);
+  if (n_lv <= 0 || n_place < 0 || n_param < 0 || world < 0 || world >= n_lv)
+    return fail(GV_EFORMAT, "geom_load: bad header counts");
+  size_t need = 32 + (size_t)n_lv * 32 + (size_t)n_place * 104 + (size_t)n_param * 8;
+  if (need != nbytes) return fail(GV_EFORMAT, "geom_load: size %zu != expected %zu", nbytes, need);
+  size_t lv_off = 32, pl_off = lv_off + (size_t)n_lv * 32, pa_off = pl_off + (size_t)n_place * 104;
+
+  try {
+    std::vector<double> raw(n_param);
+    for (int i = 0; i < n_param; ++i) raw[i] = rd_f64(b, pa_off + 8 * (size_t)i);
+    std::vector<int> lv_type(n_lv), lv_par(n_lv), lv_doff(n_lv), lv_dcnt(n_lv);
+    std::vector<double> par;
+    for (int i = 0; i < n_lv; ++i) {
+      size_t o = lv_off + 32 * (size_t)i;
+      int type = rd_i32(b, o), poff = rd_i32(b, o + 4), pcnt = rd_i32(b, o + 8);
+      lv_doff[i] = rd_i32(b, o + 12);
+      lv_dcnt[i] = rd_i32(b, o + 16);
+      if (poff < 0 || pcnt < 0 || (long)poff + pcnt > n_param) return fail(GV_EFORMAT, "geom_load: LV %d params", i);
+      if (lv_doff[i] < 0 || lv_dcnt[i] < 0 || (long)lv_doff[i] + lv_dcnt[i] > n_place)
+        return fail(GV_EFORMAT, "geom_load: LV %d placements", i);
+      lv_type[i] = type;
+      lv_par[i] = (int)par.size();
+      std::string why;
+      if (!derive(type, raw.data() + poff, pcnt, par, why))
+        return fail(GV_EFORMAT, "geom_load: LV %d: %s", i, why.c_str());
+    }
+    std::vector<int> dau_lv(n_place);
+    std::vector<double> dau_xf((size_t)n_place * 12);
+    for (int k = 0; k < n_place; ++k) {
+      size_t o = pl_off + 104 * (size_t)k;
+      dau_lv[k] = rd_i32(b, o);
+      if (dau_lv[k] < 0 || dau_lv[k] >= n_lv) return fail(GV_EFORMAT, "geom_load: placement %d child", k);
+      for (int j = 0; j < 12; ++j) dau_xf[12 * (size_t)k + j] = rd_f64(b, o + 8 + 8 * (size_t)j);
+    }
+    // count the tree first (depth and size limits also reject cycles)
+    std::vector<long> subtree(n_lv, -1);
+    std::vector<int> state(n_lv, 0), height(n_lv, 0);
+    struct Counter {
+      const std::vector<int>&doff, &dcnt, &dlv;
+      std::vector<long>& sub;
+      std::vector<int>&st, &h;
+      bool go(int lv) {
+        if (st[lv] == 2) return true;
+        if (st[lv] == 1) return false;  // cycle
+        st[lv] = 1;
+        long n = 1;
+        int hh = 0;
+        for (int k = 0; k < dcnt[lv]; ++k) {
+          int c = dlv[doff[lv] + k];
+          if (!go(c)) return false;
+          n += sub[c];
+          hh = std::max(hh, h[c] + 1);
+          if (n > kMaxPv || hh > kMaxDepth) return false;
+        }
+        sub[lv] = n;
+        h[lv] = hh;
+        st[lv] = 2;
+        return true;
+      }
+    } counter{lv_doff, lv_dcnt, dau_lv, subtree, state, height};
+    if (!counter.go(world)) return fail(GV_EFORMAT, "geom_load: volume tree has a cycle or is too large/deep");
+    long npv = subtree[world];
+    HostTree T;
+    T.pv_lv.resize(npv);
+    T.pv_parent.resize(npv);
+    T.pv_child_off.resize(npv);
+    T.pv_child.resize(npv > 0 ? npv - 1 : 0);
+    T.pv_gxf.resize((size_t)npv * 12);
+    T.max_depth = height[world];
+    // DFS pre-order expansion with an explicit stack
+    struct Frame {
+      int pv, lv, next_k;
+    };
+    std::vector<Frame> stack;
+    int next_id = 0, child_fill = 0;
+    const double ident[12] = {1, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0};
+    auto open = [&](int lv, int parent, const double* gxf) {
+      int me = next_id++;
+      T.pv_lv[me] = lv;
+      T.pv_parent[me] = parent;
+      std::memcpy(&T.pv_gxf[12 * (size_t)me], gxf, 12 * sizeof(double));
+      T.pv_child_off[me] = child_fill;
+      child_fill += lv_dcnt[lv];
+      stack.push_back(Frame{me, lv, 0});
+    };
+    open(world, -1, ident);
+    while (!stack.empty()) {
+      Frame& f = stack.back();
+      if (f.next_k >= lv_dcnt[f.lv]) {
+        stack.pop_back();
+        continue;
+      }
+      int k = f.next_k++;
+      int pl = lv_doff[f.lv] + k;
+      int parent = f.pv;
+      T.pv_child[T.pv_child_off[parent] + k] = next_id;
+      double g[12];
+      compose(&T.pv_gxf[12 * (size_t)parent], &dau_xf[12 * (size_t)pl], g);
+      open(dau_lv[pl], parent, g);
+    }
+
+    // one device allocation, 256-byte aligned sub-arrays
+    struct Part {
+      const void* src;
+      size_t bytes;
+      size_t off;
+    };
+    std::vector<Part> parts = {
+        {lv_type.data(), lv_type.size() * 4, 0},   {lv_par.data(), lv_par.size() * 4, 0},
+        {lv_doff.data(), lv_doff.size() * 4, 0},   {lv_dcnt.data(), lv_dcnt.size() * 4, 0},
+        {par.data(), par.size() * 8, 0},           {dau_xf.data(), dau_xf.size() * 8, 0},
+        {dau_lv.data(), dau_lv.size() * 4, 0},     {T.pv_lv.data(), T.pv_lv.size() * 4, 0},
+        {T.pv_parent.data(), T.pv_parent.size() * 4, 0}, {T.pv_gxf.data(), T.pv_gxf.size() * 8, 0},
+        {T.pv_child_off.data(), T.pv_child_off.size() * 4, 0}, {T.pv_child.data(), T.pv_child.size() * 4, 0}};
+    size_t total = 0;
+    for (auto& p : parts) {
+      p.off = total;
+      total += (p.bytes + 255) & ~(size_t)255;
+    }
+    std::vector<unsigned char> host(total, 0);
+    for (auto& p : parts)
+      if (p.bytes) std::memcpy(host.data() + p.off, p.src, p.bytes);
+    gv_geom* g = new (std::nothrow) gv_geom();
+    if (!g) return fail(GV_ENOMEM, "geom_load: host allocation");
+    hipError_t e = hipGetDevice(&g->device);
+    if (e != hipSuccess) {
+      delete g;
+      return hip_fail(e, "geom_load: hipGetDevice");
+    }
+    e = hipMalloc(&g->dmem, total);
+    if (e != hipSuccess) {
+      delete g;
+      return fail(GV_ENOMEM, "geom_load: hipMalloc(%zu): %s", total, hipGetErrorString(e));
+    }
+    e = hipMemcpy(g->dmem, host.data(), total, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(g->dmem);
+      delete g;
+      return hip_fail(e, "geom_load: hipMemcpy");
+    }
+    char* base = (char*)g->dmem;
+    DevGeom& D = g->dg;
+    D.n_lv = n_lv;
+    D.n_pv = (int)npv;
+    D.n_place = n_place;
+    D.lv_type = (const int*)(base + parts[0].off);
+    D.lv_par = (const int*)(base + parts[1].off);
+    D.lv_dau_off = (const int*)(base + parts[2].off);
+    D.lv_dau_cnt = (const int*)(base + parts[3].off);
+    D.par = (const double*)(base + parts[4].off);
+    D.dau_xf = (const double*)(base + parts[5].off);
+    D.dau_lv = (const int*)(base + parts[6].off);
+    D.pv_lv = (const int*)(base + parts[7].off);
+    D.pv_parent = (const int*)(base + parts[8].off);
+    D.pv_gxf = (const double*)(base + parts[9].off);
+    D.pv_child_off = (const int*)(base + parts[10].off);
+    D.pv_child = (const int*)(base + parts[11].off);
+    g->n_lv = n_lv;
+    g->n_pv = (int)npv;
+    g->n_place = n_place;
+    g->max_depth = T.max_depth;
+    g->world_lv = world;
+    g->lv_type = lv_type;
+    g->lv_par = lv_par;
+    *out = g;
+    t_err.clear();
+    return GV_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(GV_ENOMEM, "geom_load: out of host memory");
+  } catch (...) {
+    return fail(GV_EFORMAT, "geom_load: internal error");
+  }
+}
+
+extern "C" int geom_free(gv_geom* g) {
+  if (!g) return GV_OK;
+  int dev = -1;
+  (void)hipGetDevice(&dev);
+  if (dev != g->device) (void)hipSetDevice(g->device);
+  hipError_t e = hipDeviceSynchronize();
+  if (g->ws) (void)hipFree(g->ws);
+  if (g->dmem) (void)hipFree(g->dmem);
+  if (dev != g->device && dev >= 0) (void)hipSetDevice(dev);
+  delete g;
+  if (e != hipSuccess) return hip_fail(e, "geom_free: hipDeviceSynchronize");
+  return GV_OK;
+}
+
+extern "C" int geom_info(const gv_geom* g, int32_t* counts) {
+  if (!g || !counts) return fail(GV_EINVAL, "geom_info: NULL argument");
+  counts[0] = g->n_lv;
+  counts[1] = g->n_pv;
+  counts[2] = g->max_depth;
+  counts[3] = g->world_lv;
+  return GV_OK;
+}
+
+// ---------------------------------------------------------------- helpers
+namespace {
+
+struct DeviceGuard {
+  int prev = -1, want;
+  bool ok = true;
+  explicit DeviceGuard(int dev) : want(dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != want) ok = hipSetDevice(want) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0 && prev != want) (void)hipSetDevice(prev);
+  }
+};
+
+bool al8(const void* p) { return ((uintptr_t)p & 7u) == 0; }
+bool al4(const void* p) { return ((uintptr_t)p & 3u) == 0; }
+
+int check_common(const char* fn, gv_geom* g, int64_t n) {
+  if (!g) return fail(GV_EINVAL, "%s: geometry handle is NULL", fn);
+  if (n < 0) return fail(GV_EINVAL, "%s: n = %lld < 0", fn, (long long)n);
+  return GV_OK;
+}
+
+int check_f64(const char* fn, const char* name, const void* p, bool nullable = false) {
+  if (!p) return nullable ? GV_OK : fail(GV_EINVAL, "%s: %s is NULL", fn, name);
+  if (!al8(p)) return fail(GV_EINVAL, "%s: %s is not 8-byte aligned", fn, name);
+  return GV_OK;
+}
+int check_i32(const char* fn, const char* name, const void* p, bool nullable = false) {
+  if (!p) return nullable ? GV_OK : fail(GV_EINVAL, "%s: %s is NULL", fn, name);
+  if (!al4(p)) return fail(GV_EINVAL, "%s: %s is not 4-byte aligned", fn, name);
+  return GV_OK;
+}
+
+constexpr int kBlock = 256;
+unsigned grid_for(int64_t n) {
+  int64_t b = (n + kBlock - 1) / kBlock;
+  if (b > (1 << 20)) b = 1 << 20;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+int launched(const char* fn) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, fn);
+  t_err.clear();
+  return GV_OK;
+}
+
+#define GV_TRY(expr)     \
+  do {                   \
+    int rc_ = (expr);    \
+    if (rc_) return rc_; \
+  } while (0)
+
+}  // namespace
+
+// ------------------------------------------------------ solid-level entry points
+#define GV_SOLID_SWITCH(type, CALL) \
+  switch (type) {                   \
+    case kBox: CALL(Box); break;    \
+    case kTubs: CALL(Tubs); break;  \
+    case kCons: CALL(Cons); break;  \
+    case kSphere: CALL(Sphere); break; \
+    case kTrd: CALL(Trd); break;    \
+    default: CALL(Pcon); break;     \
+  }
+
+extern "C" int basket_inside(gv_geom* g, int32_t lv, int64_t n, const double* x, const double* y, const double* z,
+                             int8_t* out, void* stream) {
+  const char* fn = "basket_inside";
+  GV_TRY(check_common(fn, g, n));
+  if (lv < 0 || lv >= g->n_lv) return fail(GV_EINVAL, "%s: lv %d out of range [0, %d)", fn, lv, g->n_lv);
+  if (n == 0) return GV_OK;
+  GV_TRY(check_f64(fn, "x", x));
+  GV_TRY(check_f64(fn, "y", y));
+  GV_TRY(check_f64(fn, "z", z));
+  if (!out) return fail(GV_EINVAL, "%s: out is NULL", fn);
+  DeviceGuard dgd(g->device);
+  const double* q = g->dg.par + g->lv_par[lv];
+  hipStream_t s = (hipStream_t)stream;
+  unsigned gr = grid_for(n);
+#define CALL(S) hipLaunchKernelGGL(k_inside<S>, dim3(gr), dim3(kBlock), 0, s, q, n, x, y, z, out)
+  GV_SOLID_SWITCH(g->lv_type[lv], CALL)
+#undef CALL
+  return launched(fn);
+}
+
+extern "C" int basket_safety(gv_geom* g, int32_t lv, int32_t side, int64_t n, const double* x, const double* y,
+                             const double* z, double* out_safety, int8_t* out_inside, int32_t precision,
+                             void* stream) {
+  const char* fn = "basket_safety";
+  GV_TRY(check_common(fn, g, n));
+  if (lv < 0 || lv >= g->n_lv) return fail(GV_EINVAL, "%s: lv %d out of range [0, %d)", fn, lv, g->n_lv);
+  if (side < 0 || side > 2) return fail(GV_EINVAL, "%s: side %d", fn, side);
+  if (precision != GV_FP64) return fail(GV_EINVAL, "%s: precision %d not supported", fn, precision);
+  if (n == 0) return GV_OK;
+  GV_TRY(check_f64(fn, "x", x));
+  GV_TRY(check_f64(fn, "y", y));
+  GV_TRY(check_f64(fn, "z", z));
+  GV_TRY(check_f64(fn, "out_safety", out_safety, true));
+  if (!out_safety && !out_inside) return fail(GV_EINVAL, "%s: both outputs are NULL", fn);
+  DeviceGuard dgd(g->device);
+  const double* q = g->dg.par + g->lv_par[lv];
+  hipStream_t s = (hipStream_t)stream;
+  unsigned gr = grid_for(n);
+#define CALL(S) \
+  hipLaunchKernelGGL(k_safety<S>, dim3(gr), dim3(kBlock), 0, s, q, (int)side, n, x, y, z, out_safety, out_inside)
+  GV_SOLID_SWITCH(g->lv_type[lv], CALL)
+#undef CALL
+  return launched(fn);
+}
+
+extern "C" int basket_distance(gv_geom* g, int32_t lv, int32_t dir, int64_t n, const double* x, const double* y,
+                               const double* z, const double* dx, const double* dy, const double* dz, double* out,
+                               int32_t precision, void* stream) {
+  const char* fn = "basket_distance";
+  GV_TRY(check_common(fn, g, n));
+  if (lv < 0 || lv >= g->n_lv) return fail(GV_EINVAL, "%s: lv %d out of range [0, %d)", fn, lv, g->n_lv);
+  if (dir != GV_TO_IN && dir != GV_TO_OUT) return fail(GV_EINVAL, "%s: dir %d", fn, dir);
+  if (precision != GV_FP64) return fail(GV_EINVAL, "%s: precision %d not supported", fn, precision);
+  if (n == 0) return GV_OK;
+  const double* in[6] = {x, y, z, dx, dy, dz};
+  const char* nm[6] = {"x", "y", "z", "dx", "dy", "dz"};
+  for (int i = 0; i < 6; ++i) GV_TRY(check_f64(fn, nm[i], in[i]));
+  GV_TRY(check_f64(fn, "out", out));
+  DeviceGuard dgd(g->device);
+  const double* q = g->dg.par + g->lv_par[lv];
+  hipStream_t s = (hipStream_t)stream;
+  unsigned gr = grid_for(n);
+  if (dir == GV_TO_IN) {
+#define CALL(S) hipLaunchKernelGGL((k_distance<S, 0>), dim3(gr), dim3(kBlock), 0, s, q, n, x, y, z, dx, dy, dz, out)
+    GV_SOLID_SWITCH(g->lv_type[lv], CALL)
+#undef CALL
+  } else {
+#define CALL(S) hipLaunchKernelGGL((k_distance<S, 1>), dim3(gr), dim3(kBlock), 0, s, q, n, x, y, z, dx, dy, dz, out)
+    GV_SOLID_SWITCH(g->lv_type[lv], CALL)
+#undef CALL
+  }
+  return launched(fn);
+}
+
+extern "C" int basket_solid_all(gv_geom* g, int32_t lv, int64_t n, const double* x, const double* y, const double* z,
+                                const double* dx, const double* dy, const double* dz, int8_t* out_inside,
+                                double* out_safety, double* out_dist_in, double* out_dist_out, void* stream) {
+  const char* fn = "basket_solid_all";
+  GV_TRY(check_common(fn, g, n));
+  if (lv < 0 || lv >= g->n_lv) return fail(GV_EINVAL, "%s: lv %d out of range [0, %d)", fn, lv, g->n_lv);
+  if (n == 0) return GV_OK;
+  const double* in[6] = {x, y, z, dx, dy, dz};
+  const char* nm[6] = {"x", "y", "z", "dx", "dy", "dz"};
+  for (int i = 0; i < 6; ++i) GV_TRY(check_f64(fn, nm[i], in[i]));
+  GV_TRY(check_f64(fn, "out_safety", out_safety, true));
+  GV_TRY(check_f64(fn, "out_dist_in", out_dist_in, true));
+  GV_TRY(check_f64(fn, "out_dist_out", out_dist_out, true));
+  if (!out_inside && !out_safety && !out_dist_in && !out_dist_out)
+    return fail(GV_EINVAL, "%s: all outputs are NULL", fn);
+  DeviceGuard dgd(g->device);
+  const double* q = g->dg.par + g->lv_par[lv];
+  hipStream_t s = (hipStream_t)stream;
+  unsigned gr = grid_for(n);
+#define CALL(S)                                                                                          \
+  hipLaunchKernelGGL(k_solid_all<S>, dim3(gr), dim3(kBlock), 0, s, q, n, x, y, z, dx, dy, dz, out_inside, \
+                     out_safety, out_dist_in, out_dist_out)
+  GV_SOLID_SWITCH(g->lv_type[lv], CALL)
+#undef CALL
+  return launched(fn);
+}
+
+// ------------------------------------------------------- navigation entry points
+extern "C" int basket_locate(gv_geom* g, int64_t n, const double* x, const double* y, const double* z,
+                             int32_t* out_pv, void* stream) {
+  const char* fn = "basket_locate";
+  GV_TRY(check_common(fn, g, n));
+  if (n == 0) return GV_OK;
+  GV_TRY(check_f64(fn, "x", x));
+  GV_TRY(check_f64(fn, "y", y));
+  GV_TRY(check_f64(fn, "z", z));
+  GV_TRY(check_i32(fn, "out_pv", out_pv));
+  DeviceGuard dgd(g->device);
+  hipLaunchKernelGGL(k_locate, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, g->dg, n, x, y, z, out_pv);
+  return launched(fn);
+}
+
+extern "C" int basket_step(gv_geom* g, int64_t n, const double* x, const double* y, const double* z,
+                           const double* dx, const double* dy, const double* dz, const int32_t* pv,
+                           const double* pstep, double* out_step, int32_t* out_next_pv, uint32_t* out_flags,
+                           int32_t precision, void* stream) {
+  const char* fn = "basket_step";
+  GV_TRY(check_common(fn, g, n));
+  if (precision != GV_FP64) return fail(GV_EINVAL, "%s: precision %d not supported yet", fn, precision);
+  if (n == 0) return GV_OK;
+  const double* in[6] = {x, y, z, dx, dy, dz};
+  const char* nm[6] = {"x", "y", "z", "dx", "dy", "dz"};
+  for (int i = 0; i < 6; ++i) GV_TRY(check_f64(fn, nm[i], in[i]));
+  GV_TRY(check_i32(fn, "pv", pv));
+  GV_TRY(check_f64(fn, "pstep", pstep, true));
+  GV_TRY(check_f64(fn, "out_step", out_step));
+  GV_TRY(check_i32(fn, "out_next_pv", out_next_pv));
+  GV_TRY(check_i32(fn, "out_flags", out_flags, true));
+  DeviceGuard dgd(g->device);
+  hipLaunchKernelGGL(k_step, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, g->dg, n, x, y, z, dx, dy, dz,
+                     pv, pstep, out_step, out_next_pv, out_flags);
+  return launched(fn);
+}
+
+extern "C" int basket_nav_safety(gv_geom* g, int64_t n, const double* x, const double* y, const double* z,
+                                 const int32_t* pv, double* out, int32_t precision, void* stream) {
+  const char* fn = "basket_nav_safety";
+  GV_TRY(check_common(fn, g, n));
+  if (precision != GV_FP64) return fail(GV_EINVAL, "%s: precision %d not supported", fn, precision);
+  if (n == 0) return GV_OK;
+  GV_TRY(check_f64(fn, "x", x));
+  GV_TRY(check_f64(fn, "y", y));
+  GV_TRY(check_f64(fn, "z", z));
+  GV_TRY(check_i32(fn, "pv", pv));
+  GV_TRY(check_f64(fn, "out", out));
+  DeviceGuard dgd(g->device);
+  hipLaunchKernelGGL(k_nav_safety, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, g->dg, n, x, y, z, pv,
+                     out);
+  return launched(fn);
+}
+
+extern "C" int basket_nav_inside(gv_geom* g, int64_t n, const double* x, const double* y, const double* z,
+                                 const int32_t* pv, int8_t* out, void* stream) {
+  const char* fn = "basket_nav_inside";
+  GV_TRY(check_common(fn, g, n));
+  if (n == 0) return GV_OK;
+  GV_TRY(check_f64(fn, "x", x));
+  GV_TRY(check_f64(fn, "y", y));
+  GV_TRY(check_f64(fn, "z", z));
+  GV_TRY(check_i32(fn, "pv", pv));
+  if (!out) return fail(GV_EINVAL, "%s: out is NULL", fn);
+  DeviceGuard dgd(g->device);
+  hipLaunchKernelGGL(k_nav_inside, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, g->dg, n, x, y, z, pv,
+                     out);
+  return launched(fn);
+}
+
+extern "C" int nav_transport(gv_geom* g, int64_t n, const double* x, const double* y, const double* z,
+                             const double* dx, const double* dy, const double* dz, const int32_t* start_pv,
+                             int32_t max_steps, int32_t* out_pv, double* out_step, int32_t* out_nsteps,
+                             uint32_t* out_flags, int32_t precision, void* stream) {
+  const char* fn = "nav_transport";
+  GV_TRY(check_common(fn, g, n));
+  if (precision != GV_FP64) return fail(GV_EINVAL, "%s: precision %d not supported yet", fn, precision);
+  if (max_steps < 1 || max_steps > 4096) return fail(GV_EINVAL, "%s: max_steps %d not in [1, 4096]", fn, max_steps);
+  if (n == 0) return GV_OK;
+  const double* in[6] = {x, y, z, dx, dy, dz};
+  const char* nm[6] = {"x", "y", "z", "dx", "dy", "dz"};
+  for (int i = 0; i < 6; ++i) GV_TRY(check_f64(fn, nm[i], in[i]));
+  GV_TRY(check_i32(fn, "start_pv", start_pv, true));
+  GV_TRY(check_i32(fn, "out_pv", out_pv));
+  GV_TRY(check_f64(fn, "out_step", out_step));
+  GV_TRY(check_i32(fn, "out_nsteps", out_nsteps));
+  GV_TRY(check_i32(fn, "out_flags", out_flags));
+  DeviceGuard dgd(g->device);
+  hipLaunchKernelGGL(k_transport_lane, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, g->dg, n, x, y, z,
+                     dx, dy, dz, start_pv, (int)max_steps, out_pv, out_step, out_nsteps, out_flags);
+  return launched(fn);
+}

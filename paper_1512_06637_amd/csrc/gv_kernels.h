@@ -1,0 +1,174 @@
+// Kernels of the basket geometry library.  One lane handles one track; every
+// launch is grid-stride over the basket, reading structure-of-arrays inputs
+// with coalesced loads.  Solid-level kernels are instantiated per solid type so
+// a wavefront never diverges on the type.
+#pragma once
+#include "gv_geom.h"
+
+namespace gv {
+
+__device__ __forceinline__ int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
+__device__ __forceinline__ int64_t gstride() { return (int64_t)gridDim.x * blockDim.x; }
+
+// ------------------------------------------------------------ solid level
+template <class S>
+__global__ void k_inside(const double* __restrict__ q, int64_t n, const double* __restrict__ x,
+                         const double* __restrict__ y, const double* __restrict__ z, int8_t* __restrict__ out) {
+  for (int64_t i = gtid(); i < n; i += gstride()) out[i] = (int8_t)code_of(S::sgn(q, ld3(x, y, z, i)));
+}
+
+template <class S>
+__device__ __forceinline__ double safety_value(const double* q, V3 p, int side, int c) {
+  if (side == 1) {  // SafetyToIn
+    if (c == kInside) return -1.0;
+    if (c == kSurface) return 0.0;
+    return fmax(S::safety_in(q, p), 0.0);
+  }
+  if (side == 2) {  // SafetyToOut
+    if (c == kOutside) return -1.0;
+    if (c == kSurface) return 0.0;
+    return fmax(S::safety_out(q, p), 0.0);
+  }
+  if (c == kSurface) return 0.0;
+  return c == kInside ? fmax(S::safety_out(q, p), 0.0) : fmax(S::safety_in(q, p), 0.0);
+}
+
+template <class S>
+__global__ void k_safety(const double* __restrict__ q, int side, int64_t n, const double* __restrict__ x,
+                         const double* __restrict__ y, const double* __restrict__ z, double* __restrict__ out,
+                         int8_t* __restrict__ out_code) {
+  for (int64_t i = gtid(); i < n; i += gstride()) {
+    V3 p = ld3(x, y, z, i);
+    int c = code_of(S::sgn(q, p));
+    double v = safety_value<S>(q, p, side, c);
+    if (out) out[i] = v;
+    if (out_code) out_code[i] = (int8_t)c;
+  }
+}
+
+template <class S, int DIR>
+__global__ void k_distance(const double* __restrict__ q, int64_t n, const double* __restrict__ x,
+                           const double* __restrict__ y, const double* __restrict__ z, const double* __restrict__ dx,
+                           const double* __restrict__ dy, const double* __restrict__ dz, double* __restrict__ out) {
+  for (int64_t i = gtid(); i < n; i += gstride()) {
+    V3 p = ld3(x, y, z, i), d = ld3(dx, dy, dz, i);
+    out[i] = DIR == 0 ? S::dist_in(q, p, d) : S::dist_out(q, p, d);
+  }
+}
+
+// All four answers with one read of the basket.  Only the distance that is
+// defined on the point's side is computed; the other is the -1 sentinel.
+template <class S>
+__global__ void k_solid_all(const double* __restrict__ q, int64_t n, const double* __restrict__ x,
+                            const double* __restrict__ y, const double* __restrict__ z, const double* __restrict__ dx,
+                            const double* __restrict__ dy, const double* __restrict__ dz, int8_t* __restrict__ o_in,
+                            double* __restrict__ o_saf, double* __restrict__ o_din, double* __restrict__ o_dout) {
+  for (int64_t i = gtid(); i < n; i += gstride()) {
+    V3 p = ld3(x, y, z, i), d = ld3(dx, dy, dz, i);
+    int c = code_of(S::sgn(q, p));
+    if (o_in) o_in[i] = (int8_t)c;
+    if (o_saf) o_saf[i] = safety_value<S>(q, p, 0, c);
+    if (o_din) o_din[i] = c == kInside ? -1.0 : S::dist_in(q, p, d);
+    if (o_dout) o_dout[i] = c == kOutside ? -1.0 : S::dist_out(q, p, d);
+  }
+}
+
+// ------------------------------------------------------------- navigation
+__global__ void k_locate(DevGeom G, int64_t n, const double* __restrict__ x, const double* __restrict__ y,
+                         const double* __restrict__ z, int32_t* __restrict__ out) {
+  for (int64_t i = gtid(); i < n; i += gstride()) out[i] = locate(G, ld3(x, y, z, i));
+}
+
+__global__ void k_step(DevGeom G, int64_t n, const double* __restrict__ x, const double* __restrict__ y,
+                       const double* __restrict__ z, const double* __restrict__ dx, const double* __restrict__ dy,
+                       const double* __restrict__ dz, const int32_t* __restrict__ pv,
+                       const double* __restrict__ pstep, double* __restrict__ out_step,
+                       int32_t* __restrict__ out_next, uint32_t* __restrict__ out_flags) {
+  for (int64_t i = gtid(); i < n; i += gstride()) {
+    int v = pv[i];
+    uint32_t fl = 0;
+    int nx = -1;
+    double st = 0.0;
+    if (v >= 0 && v < G.n_pv) {
+      st = compute_step(G, v, ld3(x, y, z, i), ld3(dx, dy, dz, i), pstep ? pstep[i] : GV_INF, &nx, &fl);
+    } else {
+      fl = kFlagLocateFail;
+    }
+    out_step[i] = st;
+    out_next[i] = nx;
+    if (out_flags) out_flags[i] = fl;
+  }
+}
+
+__global__ void k_nav_safety(DevGeom G, int64_t n, const double* __restrict__ x, const double* __restrict__ y,
+                             const double* __restrict__ z, const int32_t* __restrict__ pv, double* __restrict__ out) {
+  for (int64_t i = gtid(); i < n; i += gstride()) {
+    int v = pv[i];
+    out[i] = (v >= 0 && v < G.n_pv) ? nav_safety(G, v, ld3(x, y, z, i)) : 0.0;
+  }
+}
+
+__global__ void k_nav_inside(DevGeom G, int64_t n, const double* __restrict__ x, const double* __restrict__ y,
+                             const double* __restrict__ z, const int32_t* __restrict__ pv, int8_t* __restrict__ out) {
+  for (int64_t i = gtid(); i < n; i += gstride()) {
+    int v = pv[i];
+    if (v < 0 || v >= G.n_pv) {
+      out[i] = (int8_t)kOutside;
+      continue;
+    }
+    int lv = G.pv_lv[v];
+    V3 pl = to_child_p(G.pv_gxf + 12 * (size_t)v, ld3(x, y, z, i));
+    out[i] = (int8_t)code_of(solid_sgn(G.lv_type[lv], G.par + G.lv_par[lv], pl));
+  }
+}
+
+// p + s d without FMA: the global point advances exactly as a plain FP64 code
+// would, so the position does not drift through contraction.
+__device__ __forceinline__ V3 advance(V3 p, double s, V3 d) {
+#pragma clang fp contract(off)
+  return V3{p.x + s * d.x, p.y + s * d.y, p.z + s * d.z};
+}
+
+// Whole-track transport, one lane per track, until the track leaves the world.
+__global__ void k_transport_lane(DevGeom G, int64_t n, const double* __restrict__ x, const double* __restrict__ y,
+                                 const double* __restrict__ z, const double* __restrict__ dx,
+                                 const double* __restrict__ dy, const double* __restrict__ dz,
+                                 const int32_t* __restrict__ start_pv, int max_steps, int32_t* __restrict__ out_pv,
+                                 double* __restrict__ out_step, int32_t* __restrict__ out_nsteps,
+                                 uint32_t* __restrict__ out_flags) {
+  for (int64_t i = gtid(); i < n; i += gstride()) {
+    V3 p = ld3(x, y, z, i), d = ld3(dx, dy, dz, i);
+    uint32_t fl = 0;
+    int pv = start_pv ? start_pv[i] : locate(G, p);
+    if (pv < -1 || pv >= G.n_pv) {
+      pv = -1;
+      fl |= kFlagLocateFail;
+    }
+    int32_t* rp = out_pv + (size_t)i * (max_steps + 1);
+    double* rs = out_step + (size_t)i * max_steps;
+    rp[0] = pv;
+    int k = 0;
+    if (pv >= 0) {
+      int zero_run = 0, nx = pv;
+      while (k < max_steps) {
+        double st = compute_step(G, pv, p, d, GV_INF, &nx, &fl);
+        p = advance(p, st, d);
+        rs[k] = st;
+        rp[k + 1] = nx;
+        ++k;
+        if (nx < 0) break;
+        zero_run = st < kTol ? zero_run + 1 : 0;
+        if (zero_run >= 8) {
+          fl |= kFlagStuck;
+          break;
+        }
+        pv = nx;
+      }
+      if (k == max_steps && nx >= 0 && !(fl & kFlagStuck)) fl |= kFlagOverflow;
+    }
+    out_nsteps[i] = k;
+    out_flags[i] = fl;
+  }
+}
+
+}  // namespace gv

@@ -1,0 +1,53 @@
+"""Algorithmic work accounting for the roofline figures of the benchmark.
+
+An "op" is one FP64 VALU lane operation of the minimal per-track formulation:
+add, sub, mul, fma, min, max and compare count 1 each, and so do a division and
+a square root (which cost several instructions on CDNA).  The per-step figures
+are those of the plain navigator: the mother's DistanceToOut plus, for every
+daughter, the placement transform and its DistanceToIn (Sec. III.A/III.C).
+
+Peak: MI355X has 256 CUs x 4 SIMDs x 16 FP64 lanes at 2.4 GHz = 39.32e12 FP64
+lane-ops/s (78.6 TFLOP/s when every op is an FMA).  HBM3E peak 8 TB/s.
+"""
+PEAK_FP64_OPS = 256 * 64 * 2.4e9  # 39.32e12 lane-ops/s
+PEAK_HBM = 8.0e12  # B/s
+
+TRANSFORM = 21      # p_loc = R^T (p - t): 3 sub + 9 mul/fma; d_loc = R^T d: 9
+BOX_DIST_IN = 33    # inside test 6, three slabs 24, clip + chord test 3
+BOX_DIST_OUT = 16   # inside test 6, three exit planes 9, clamp 1
+TUBE_DIST_IN = 53   # inside test 9, outer cylinder 16, z slab 6, inner cylinder 12, pieces 10
+TUBE_DIST_OUT = 53
+SELECT = 1          # running minimum over candidates, per candidate
+STEP_FIXED = 9      # final selection (3) + advance p += s d (6)
+
+# ops per ComputeStep by the class of the current volume in the layered detector
+OPS_WORLD_STEP = TRANSFORM + BOX_DIST_OUT + 20 * (TRANSFORM + TUBE_DIST_IN + SELECT) + STEP_FIXED
+OPS_LAYER_STEP = TRANSFORM + TUBE_DIST_OUT + 64 * (TRANSFORM + BOX_DIST_IN + SELECT) + STEP_FIXED
+OPS_MODULE_STEP = TRANSFORM + BOX_DIST_OUT + STEP_FIXED
+
+# bytes that must move per track of a transport: the SoA start state in
+# (6 doubles) and the outputs (start PV, per step one int32 PV and one double
+# step, nsteps, flags)
+def transport_bytes(n_tracks: int, n_steps_total: int) -> int:
+    return n_tracks * (48 + 4 + 4 + 4) + n_steps_total * (4 + 8)
+
+
+def detector_step_classes(pv_rows, nsteps, n_modules=64):
+    """Counts of steps taken from the world, a layer and a module, read from the
+    transport's own PV sequences (PV 0 world, 1 + 65 i layer i, else module)."""
+    import numpy as np
+
+    pv = np.asarray(pv_rows)
+    ns = np.asarray(nsteps)
+    k = np.arange(pv.shape[1] - 1)[None, :]
+    cur = pv[:, :-1]
+    valid = k < ns[:, None]
+    stride = n_modules + 1
+    world = int(np.sum(valid & (cur == 0)))
+    layer = int(np.sum(valid & (cur > 0) & ((cur - 1) % stride == 0)))
+    module = int(np.sum(valid)) - world - layer
+    return world, layer, module
+
+
+def detector_ops(world, layer, module) -> float:
+    return float(world) * OPS_WORLD_STEP + float(layer) * OPS_LAYER_STEP + float(module) * OPS_MODULE_STEP
