@@ -120,7 +120,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "layered-detector navigation FP64: 2^20 origin tracks to world exit, 1301 PVs",
                    "tracks": n, "track_steps": total_steps, "max_steps": max_steps,
-                   "steps_world_layer_module": [world, layer, module], "kernel": "k_transport_lane"},
+                   "steps_world_layer_module": [world, layer, module], "kernel": "k_bt_step"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": R.PEAK_FP64_OPS / 1e12,
                      "unit": "TOP/s (FP64 lane-ops)", "frac": achieved / R.PEAK_FP64_OPS, "traffic": None},
         "wall_s": wall,

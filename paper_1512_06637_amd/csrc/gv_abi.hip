@@ -3,6 +3,7 @@
 // caller's stream.  No exception or abort crosses the boundary.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -12,7 +13,7 @@
 #include <vector>
 
 #include "../../include/gvgeom.h"
-#include "gv_kernels.h"
+#include "gv_baskets.h"
 
 using namespace gv;
 
@@ -45,6 +46,13 @@ struct gv_geom {
   // nav_transport workspace (grown on demand)
   void* ws = nullptr;
   size_t ws_bytes = 0;
+  int64_t ws_tracks = 0;
+  TState st[2]{};
+  TLayout lay[2]{};
+  TCtl ctl{};
+  int* newlv = nullptr;
+  int* h_live = nullptr;  // pinned host copies of the live count
+  hipEvent_t ev[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -234,6 +242,20 @@ extern "C" int geom_load(const void* blob, size_t nbytes, gv_geom** out) {
       if (dau_lv[k] < 0 || dau_lv[k] >= n_lv) return fail(GV_EFORMAT, "geom_load: placement %d child", k);
       for (int j = 0; j < 12; ++j) dau_xf[12 * (size_t)k + j] = rd_f64(b, o + 8 + 8 * (size_t)j);
     }
+    // one solid type for all daughters of an LV lets the daughter loop run a
+    // single solid's code
+    std::vector<int> lv_dtype(n_lv, -1);
+    for (int i = 0; i < n_lv; ++i) {
+      int t = -1;
+      for (int k = 0; k < lv_dcnt[i]; ++k) {
+        int ct = lv_type[dau_lv[lv_doff[i] + k]];
+        if (k == 0) t = ct;
+        else if (ct != t) t = -1;
+      }
+      lv_dtype[i] = lv_dcnt[i] > 0 ? t : -1;
+    }
+    std::vector<int> dau_par(n_place);
+    for (int k = 0; k < n_place; ++k) dau_par[k] = lv_par[dau_lv[k]];
     // count the tree first (depth and size limits also reject cycles)
     std::vector<long> subtree(n_lv, -1);
     std::vector<int> state(n_lv, 0), height(n_lv, 0);
@@ -313,7 +335,8 @@ extern "C" int geom_load(const void* blob, size_t nbytes, gv_geom** out) {
         {par.data(), par.size() * 8, 0},           {dau_xf.data(), dau_xf.size() * 8, 0},
         {dau_lv.data(), dau_lv.size() * 4, 0},     {T.pv_lv.data(), T.pv_lv.size() * 4, 0},
         {T.pv_parent.data(), T.pv_parent.size() * 4, 0}, {T.pv_gxf.data(), T.pv_gxf.size() * 8, 0},
-        {T.pv_child_off.data(), T.pv_child_off.size() * 4, 0}, {T.pv_child.data(), T.pv_child.size() * 4, 0}};
+        {T.pv_child_off.data(), T.pv_child_off.size() * 4, 0}, {T.pv_child.data(), T.pv_child.size() * 4, 0},
+        {lv_dtype.data(), lv_dtype.size() * 4, 0}, {dau_par.data(), dau_par.size() * 4, 0}};
     size_t total = 0;
     for (auto& p : parts) {
       p.off = total;
@@ -345,18 +368,20 @@ extern "C" int geom_load(const void* blob, size_t nbytes, gv_geom** out) {
     D.n_lv = n_lv;
     D.n_pv = (int)npv;
     D.n_place = n_place;
-    D.lv_type = (const int*)(base + parts[0].off);
-    D.lv_par = (const int*)(base + parts[1].off);
-    D.lv_dau_off = (const int*)(base + parts[2].off);
-    D.lv_dau_cnt = (const int*)(base + parts[3].off);
-    D.par = (const double*)(base + parts[4].off);
-    D.dau_xf = (const double*)(base + parts[5].off);
-    D.dau_lv = (const int*)(base + parts[6].off);
-    D.pv_lv = (const int*)(base + parts[7].off);
-    D.pv_parent = (const int*)(base + parts[8].off);
-    D.pv_gxf = (const double*)(base + parts[9].off);
-    D.pv_child_off = (const int*)(base + parts[10].off);
-    D.pv_child = (const int*)(base + parts[11].off);
+    D.lv_type = (CQI)(base + parts[0].off);
+    D.lv_par = (CQI)(base + parts[1].off);
+    D.lv_dau_off = (CQI)(base + parts[2].off);
+    D.lv_dau_cnt = (CQI)(base + parts[3].off);
+    D.par = (CQ)(base + parts[4].off);
+    D.dau_xf = (CQ)(base + parts[5].off);
+    D.dau_lv = (CQI)(base + parts[6].off);
+    D.pv_lv = (CQI)(base + parts[7].off);
+    D.pv_parent = (CQI)(base + parts[8].off);
+    D.pv_gxf = (CQ)(base + parts[9].off);
+    D.pv_child_off = (CQI)(base + parts[10].off);
+    D.pv_child = (CQI)(base + parts[11].off);
+    D.lv_dau_type = (CQI)(base + parts[12].off);
+    D.dau_par = (CQI)(base + parts[13].off);
     g->n_lv = n_lv;
     g->n_pv = (int)npv;
     g->n_place = n_place;
@@ -382,6 +407,9 @@ extern "C" int geom_free(gv_geom* g) {
   hipError_t e = hipDeviceSynchronize();
   if (g->ws) (void)hipFree(g->ws);
   if (g->dmem) (void)hipFree(g->dmem);
+  if (g->h_live) (void)hipHostFree(g->h_live);
+  for (auto& ev : g->ev)
+    if (ev) (void)hipEventDestroy(ev);
   if (dev != g->device && dev >= 0) (void)hipSetDevice(dev);
   delete g;
   if (e != hipSuccess) return hip_fail(e, "geom_free: hipDeviceSynchronize");
@@ -476,7 +504,7 @@ extern "C" int basket_inside(gv_geom* g, int32_t lv, int64_t n, const double* x,
   GV_TRY(check_f64(fn, "z", z));
   if (!out) return fail(GV_EINVAL, "%s: out is NULL", fn);
   DeviceGuard dgd(g->device);
-  const double* q = g->dg.par + g->lv_par[lv];
+  CQ q = g->dg.par + g->lv_par[lv];
   hipStream_t s = (hipStream_t)stream;
   unsigned gr = grid_for(n);
 #define CALL(S) hipLaunchKernelGGL(k_inside<S>, dim3(gr), dim3(kBlock), 0, s, q, n, x, y, z, out)
@@ -500,7 +528,7 @@ extern "C" int basket_safety(gv_geom* g, int32_t lv, int32_t side, int64_t n, co
   GV_TRY(check_f64(fn, "out_safety", out_safety, true));
   if (!out_safety && !out_inside) return fail(GV_EINVAL, "%s: both outputs are NULL", fn);
   DeviceGuard dgd(g->device);
-  const double* q = g->dg.par + g->lv_par[lv];
+  CQ q = g->dg.par + g->lv_par[lv];
   hipStream_t s = (hipStream_t)stream;
   unsigned gr = grid_for(n);
 #define CALL(S) \
@@ -524,7 +552,7 @@ extern "C" int basket_distance(gv_geom* g, int32_t lv, int32_t dir, int64_t n, c
   for (int i = 0; i < 6; ++i) GV_TRY(check_f64(fn, nm[i], in[i]));
   GV_TRY(check_f64(fn, "out", out));
   DeviceGuard dgd(g->device);
-  const double* q = g->dg.par + g->lv_par[lv];
+  CQ q = g->dg.par + g->lv_par[lv];
   hipStream_t s = (hipStream_t)stream;
   unsigned gr = grid_for(n);
   if (dir == GV_TO_IN) {
@@ -555,7 +583,7 @@ extern "C" int basket_solid_all(gv_geom* g, int32_t lv, int64_t n, const double*
   if (!out_inside && !out_safety && !out_dist_in && !out_dist_out)
     return fail(GV_EINVAL, "%s: all outputs are NULL", fn);
   DeviceGuard dgd(g->device);
-  const double* q = g->dg.par + g->lv_par[lv];
+  CQ q = g->dg.par + g->lv_par[lv];
   hipStream_t s = (hipStream_t)stream;
   unsigned gr = grid_for(n);
 #define CALL(S)                                                                                          \
@@ -636,6 +664,148 @@ extern "C" int basket_nav_inside(gv_geom* g, int64_t n, const double* x, const d
   return launched(fn);
 }
 
+// ------------------------------------------------ basket transport workspace
+namespace {
+
+size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Two state buffers of n tracks, the next-LV array, and per-LV counters and
+// layouts.  Allocated with hipMalloc on first use and kept in the handle.
+int ensure_workspace(gv_geom* g, int64_t n) {
+  if (g->ws && g->ws_tracks >= n) return GV_OK;
+  int64_t cap = n < 4096 ? 4096 : n;
+  int nl = g->n_lv;
+  size_t state = 6 * al256(8 * (size_t)cap) + 4 * al256(4 * (size_t)cap);
+  size_t total = 2 * state + al256(4 * (size_t)cap) + 6 * al256(4 * (size_t)(nl + 1)) +
+                 2 * al256(4 * (size_t)nl) + al256(4);
+  if (g->ws) {
+    hipError_t e = hipStreamSynchronize(nullptr);
+    (void)e;
+    (void)hipDeviceSynchronize();
+    (void)hipFree(g->ws);
+    g->ws = nullptr;
+    g->ws_tracks = 0;
+  }
+  void* mem = nullptr;
+  hipError_t e = hipMalloc(&mem, total);
+  if (e != hipSuccess) return fail(GV_ENOMEM, "nav_transport: workspace hipMalloc(%zu): %s", total, hipGetErrorString(e));
+  e = hipMemset(mem, 0, total);
+  if (e != hipSuccess) {
+    (void)hipFree(mem);
+    return hip_fail(e, "nav_transport: workspace hipMemset");
+  }
+  char* p = (char*)mem;
+  auto take = [&](size_t b) {
+    char* r = p;
+    p += al256(b);
+    return r;
+  };
+  for (int s = 0; s < 2; ++s) {
+    TState& S = g->st[s];
+    S.x = (double*)take(8 * cap);
+    S.y = (double*)take(8 * cap);
+    S.z = (double*)take(8 * cap);
+    S.dx = (double*)take(8 * cap);
+    S.dy = (double*)take(8 * cap);
+    S.dz = (double*)take(8 * cap);
+    S.pv = (int*)take(4 * cap);
+    S.tid = (int*)take(4 * cap);
+    S.zr = (int*)take(4 * cap);
+    S.fl = (int*)take(4 * cap);
+  }
+  g->newlv = (int*)take(4 * cap);
+  for (int s = 0; s < 2; ++s) {
+    g->lay[s].start = (int*)take(4 * (nl + 1));
+    g->lay[s].count = (int*)take(4 * (nl + 1));
+    g->lay[s].tile = (int*)take(4 * (nl + 1));
+  }
+  g->ctl.cnt_next = (int*)take(4 * nl);
+  g->ctl.cursor = (int*)take(4 * nl);
+  g->ctl.live = (int*)take(4);
+  if (!g->h_live) {
+    e = hipHostMalloc((void**)&g->h_live, 2 * sizeof(int), hipHostMallocDefault);
+    if (e != hipSuccess) return hip_fail(e, "nav_transport: hipHostMalloc");
+    for (int i = 0; i < 2; ++i) {
+      e = hipEventCreateWithFlags(&g->ev[i], hipEventDisableTiming);
+      if (e != hipSuccess) return hip_fail(e, "nav_transport: hipEventCreate");
+    }
+  }
+  g->ws = mem;
+  g->ws_bytes = total;
+  g->ws_tracks = cap;
+  return GV_OK;
+}
+
+constexpr int64_t kBasketMin = 8192;  // smaller batches use one lane per track
+
+unsigned stream_grid(int64_t n) {
+  int64_t b = (n + kBlock - 1) / kBlock;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 2048));
+}
+
+int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, const double* z, const double* dx,
+                     const double* dy, const double* dz, const int32_t* start_pv, int max_steps, int32_t* out_pv,
+                     double* out_step, int32_t* out_nsteps, uint32_t* out_flags, hipStream_t s) {
+  const char* fn = "nav_transport";
+  GV_TRY(ensure_workspace(g, n));
+  const int nl = g->n_lv;
+  TState in{};
+  in.x = (double*)x;
+  in.y = (double*)y;
+  in.z = (double*)z;
+  in.dx = (double*)dx;
+  in.dy = (double*)dy;
+  in.dz = (double*)dz;
+  in.pv = g->st[1].pv;  // located start PVs, staged in the second buffer
+  const unsigned sg = stream_grid(n);
+  const size_t lds = 8 * (size_t)nl;
+  hipLaunchKernelGGL(k_bt_init, dim3(sg), dim3(kBlock), 0, s, g->dg, n, x, y, z, start_pv, max_steps, out_pv,
+                     out_nsteps, out_flags, g->newlv, g->st[1].pv, g->ctl);
+  GV_TRY(launched(fn));
+  hipLaunchKernelGGL(k_bt_scan, dim3(1), dim3(kBlock), 0, s, nl, g->ctl, g->lay[0]);
+  GV_TRY(launched(fn));
+  hipLaunchKernelGGL(k_bt_scatter, dim3(sg), dim3(kBlock), lds, s, in, (const int*)nullptr, n, g->newlv, g->st[0],
+                     g->lay[0], g->ctl, nl);
+  GV_TRY(launched(fn));
+  const int64_t max_tiles = n / kWave + nl + 1;
+  const unsigned step_grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((max_tiles + 3) / 4, 1024));
+  // The host enqueues steps in chunks; once the live count read back after an
+  // earlier chunk is zero, the remaining steps are not enqueued.  Two chunks
+  // stay in flight, so the device never waits for this check.
+  constexpr int kChunk = 8;
+  int chunk = 0;
+  for (int k = 0; k < max_steps; ++k) {
+    int c = k & 1;
+    hipLaunchKernelGGL(k_bt_step, dim3(step_grid), dim3(kBlock), 0, s, g->dg, k, max_steps, g->st[c], g->lay[c],
+                       g->newlv, g->ctl, out_pv, out_step, out_nsteps, out_flags);
+    GV_TRY(launched(fn));
+    if (k + 1 == max_steps) break;
+    hipLaunchKernelGGL(k_bt_scan, dim3(1), dim3(kBlock), 0, s, nl, g->ctl, g->lay[c ^ 1]);
+    GV_TRY(launched(fn));
+    hipLaunchKernelGGL(k_bt_scatter, dim3(sg), dim3(kBlock), lds, s, g->st[c],
+                       (const int*)(g->lay[c].start + nl), (int64_t)0, g->newlv, g->st[c ^ 1], g->lay[c ^ 1], g->ctl,
+                       nl);
+    GV_TRY(launched(fn));
+    if ((k + 1) % kChunk == 0) {
+      int slot = chunk & 1;
+      if (chunk >= 2) {
+        // the copy issued two chunks ago: wait for it, then look
+        hipError_t e = hipEventSynchronize(g->ev[slot]);
+        if (e != hipSuccess) return hip_fail(e, "nav_transport: hipEventSynchronize");
+        if (g->h_live[slot] == 0) break;
+      }
+      hipError_t e = hipMemcpyAsync(&g->h_live[slot], g->ctl.live, sizeof(int), hipMemcpyDeviceToHost, s);
+      if (e != hipSuccess) return hip_fail(e, "nav_transport: hipMemcpyAsync");
+      e = hipEventRecord(g->ev[slot], s);
+      if (e != hipSuccess) return hip_fail(e, "nav_transport: hipEventRecord");
+      ++chunk;
+    }
+  }
+  return GV_OK;
+}
+
+}  // namespace
+
 extern "C" int nav_transport(gv_geom* g, int64_t n, const double* x, const double* y, const double* z,
                              const double* dx, const double* dy, const double* dz, const int32_t* start_pv,
                              int32_t max_steps, int32_t* out_pv, double* out_step, int32_t* out_nsteps,
@@ -654,6 +824,9 @@ extern "C" int nav_transport(gv_geom* g, int64_t n, const double* x, const doubl
   GV_TRY(check_i32(fn, "out_nsteps", out_nsteps));
   GV_TRY(check_i32(fn, "out_flags", out_flags));
   DeviceGuard dgd(g->device);
+  if (n >= kBasketMin && n <= (1L << 30) && g->n_lv <= 8192)
+    return basket_transport(g, n, x, y, z, dx, dy, dz, start_pv, max_steps, out_pv, out_step, out_nsteps, out_flags,
+                            (hipStream_t)stream);
   hipLaunchKernelGGL(k_transport_lane, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, g->dg, n, x, y, z,
                      dx, dy, dz, start_pv, (int)max_steps, out_pv, out_step, out_nsteps, out_flags);
   return launched(fn);

@@ -12,18 +12,20 @@ namespace gv {
 // doubles: R row-major then t, with x_mother = R x_child + t.
 struct DevGeom {
   int n_lv, n_pv, n_place;
-  const int* lv_type;       // [n_lv]
-  const int* lv_par;        // [n_lv] offset into par
-  const int* lv_dau_off;    // [n_lv] first daughter placement
-  const int* lv_dau_cnt;    // [n_lv]
-  const double* par;        // derived solid parameters
-  const double* dau_xf;     // [n_place][12] placement transform, LV frame
-  const int* dau_lv;        // [n_place]
-  const int* pv_lv;         // [n_pv]
-  const int* pv_parent;     // [n_pv]
-  const double* pv_gxf;     // [n_pv][12] composed world <- PV transform
-  const int* pv_child_off;  // [n_pv] children of a PV follow their LV's placement order
-  const int* pv_child;      // [n_pv]
+  CQI lv_type;       // [n_lv]
+  CQI lv_par;        // [n_lv] offset into par
+  CQI lv_dau_off;    // [n_lv] first daughter placement
+  CQI lv_dau_cnt;    // [n_lv]
+  CQI lv_dau_type;   // [n_lv] solid type shared by all daughters, -1 if mixed or none
+  CQ par;            // derived solid parameters
+  CQ dau_xf;         // [n_place][12] placement transform, LV frame
+  CQI dau_lv;        // [n_place]
+  CQI dau_par;       // [n_place] offset of the child solid's parameters in par
+  CQI pv_lv;         // [n_pv]
+  CQI pv_parent;     // [n_pv]
+  CQ pv_gxf;         // [n_pv][12] composed world <- PV transform
+  CQI pv_child_off;  // [n_pv] children of a PV follow their LV's placement order
+  CQI pv_child;      // [n_pv]
 };
 
 __device__ __forceinline__ V3 ld3(const double* x, const double* y, const double* z, int64_t i) {
@@ -31,12 +33,12 @@ __device__ __forceinline__ V3 ld3(const double* x, const double* y, const double
 }
 
 // x_child = R^T (x_mother - t)
-__device__ __forceinline__ V3 to_child_p(const double* X, V3 p) {
+__device__ __forceinline__ V3 to_child_p(CQ X, V3 p) {
   double q0 = p.x - X[9], q1 = p.y - X[10], q2 = p.z - X[11];
   return V3{X[0] * q0 + X[3] * q1 + X[6] * q2, X[1] * q0 + X[4] * q1 + X[7] * q2,
             X[2] * q0 + X[5] * q1 + X[8] * q2};
 }
-__device__ __forceinline__ V3 to_child_d(const double* X, V3 d) {
+__device__ __forceinline__ V3 to_child_d(CQ X, V3 d) {
   return V3{X[0] * d.x + X[3] * d.y + X[6] * d.z, X[1] * d.x + X[4] * d.y + X[7] * d.z,
             X[2] * d.x + X[5] * d.y + X[8] * d.z};
 }
@@ -49,7 +51,7 @@ constexpr uint32_t kFlagOverflow = 1u, kFlagStuck = 2u, kFlagLocateFail = 4u;
 __device__ __forceinline__ double compute_step(const DevGeom& G, int pv, V3 p, V3 d, double pstep, int* next,
                                                uint32_t* flags) {
   int lv = G.pv_lv[pv];
-  const double* X = G.pv_gxf + 12 * (size_t)pv;
+  CQ X = G.pv_gxf + 12 * (size_t)pv;
   V3 pl = to_child_p(X, p), dl = to_child_d(X, d);
   double dout = solid_dist_out(G.lv_type[lv], G.par + G.lv_par[lv], pl, dl);
   if (dout < 0.0) {
@@ -60,7 +62,7 @@ __device__ __forceinline__ double compute_step(const DevGeom& G, int pv, V3 p, V
   int bestk = -1;
   int off = G.lv_dau_off[lv], cnt = G.lv_dau_cnt[lv];
   for (int k = 0; k < cnt; ++k) {
-    const double* Y = G.dau_xf + 12 * (size_t)(off + k);
+    CQ Y = G.dau_xf + 12 * (size_t)(off + k);
     int clv = G.dau_lv[off + k];
     V3 pc = to_child_p(Y, pl), dc = to_child_d(Y, dl);
     double t = solid_dist_in(G.lv_type[clv], G.par + G.lv_par[clv], pc, dc);
@@ -113,14 +115,14 @@ __device__ __forceinline__ double nav_safety(const DevGeom& G, int pv, V3 p) {
   int lv = G.pv_lv[pv];
   V3 pl = to_child_p(G.pv_gxf + 12 * (size_t)pv, p);
   int t = G.lv_type[lv];
-  const double* q = G.par + G.lv_par[lv];
+  CQ q = G.par + G.lv_par[lv];
   if (code_of(solid_sgn(t, q, pl)) != kInside) return 0.0;
   double s = solid_safety_out(t, q, pl);
   int off = G.lv_dau_off[lv], cnt = G.lv_dau_cnt[lv];
   for (int k = 0; k < cnt; ++k) {
     int clv = G.dau_lv[off + k];
     V3 pc = to_child_p(G.dau_xf + 12 * (size_t)(off + k), pl);
-    const double* qc = G.par + G.lv_par[clv];
+    CQ qc = G.par + G.lv_par[clv];
     int tc = G.lv_type[clv];
     if (code_of(solid_sgn(tc, qc, pc)) != kOutside) return 0.0;
     s = fmin(s, solid_safety_in(tc, qc, pc));

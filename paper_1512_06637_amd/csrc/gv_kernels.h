@@ -12,13 +12,13 @@ __device__ __forceinline__ int64_t gstride() { return (int64_t)gridDim.x * block
 
 // ------------------------------------------------------------ solid level
 template <class S>
-__global__ void k_inside(const double* __restrict__ q, int64_t n, const double* __restrict__ x,
+__global__ void k_inside(CQ q, int64_t n, const double* __restrict__ x,
                          const double* __restrict__ y, const double* __restrict__ z, int8_t* __restrict__ out) {
   for (int64_t i = gtid(); i < n; i += gstride()) out[i] = (int8_t)code_of(S::sgn(q, ld3(x, y, z, i)));
 }
 
 template <class S>
-__device__ __forceinline__ double safety_value(const double* q, V3 p, int side, int c) {
+__device__ __forceinline__ double safety_value(CQ q, V3 p, int side, int c) {
   if (side == 1) {  // SafetyToIn
     if (c == kInside) return -1.0;
     if (c == kSurface) return 0.0;
@@ -34,7 +34,7 @@ __device__ __forceinline__ double safety_value(const double* q, V3 p, int side, 
 }
 
 template <class S>
-__global__ void k_safety(const double* __restrict__ q, int side, int64_t n, const double* __restrict__ x,
+__global__ void k_safety(CQ q, int side, int64_t n, const double* __restrict__ x,
                          const double* __restrict__ y, const double* __restrict__ z, double* __restrict__ out,
                          int8_t* __restrict__ out_code) {
   for (int64_t i = gtid(); i < n; i += gstride()) {
@@ -47,7 +47,7 @@ __global__ void k_safety(const double* __restrict__ q, int side, int64_t n, cons
 }
 
 template <class S, int DIR>
-__global__ void k_distance(const double* __restrict__ q, int64_t n, const double* __restrict__ x,
+__global__ void k_distance(CQ q, int64_t n, const double* __restrict__ x,
                            const double* __restrict__ y, const double* __restrict__ z, const double* __restrict__ dx,
                            const double* __restrict__ dy, const double* __restrict__ dz, double* __restrict__ out) {
   for (int64_t i = gtid(); i < n; i += gstride()) {
@@ -59,7 +59,7 @@ __global__ void k_distance(const double* __restrict__ q, int64_t n, const double
 // All four answers with one read of the basket.  Only the distance that is
 // defined on the point's side is computed; the other is the -1 sentinel.
 template <class S>
-__global__ void k_solid_all(const double* __restrict__ q, int64_t n, const double* __restrict__ x,
+__global__ void k_solid_all(CQ q, int64_t n, const double* __restrict__ x,
                             const double* __restrict__ y, const double* __restrict__ z, const double* __restrict__ dx,
                             const double* __restrict__ dy, const double* __restrict__ dz, int8_t* __restrict__ o_in,
                             double* __restrict__ o_saf, double* __restrict__ o_din, double* __restrict__ o_dout) {

@@ -48,6 +48,24 @@ struct V3 {
   double x, y, z;
 };
 
+// Geometry tables never change while a kernel runs, so they are read through
+// the constant address space: a wavefront-uniform address (the LV of a basket,
+// its daughter table) then becomes a scalar load into SGPRs, and a per-lane
+// address an ordinary vector load.
+typedef const __attribute__((address_space(4))) double* CQ;
+typedef const __attribute__((address_space(4))) int* CQI;
+
+// 1/d from the hardware reciprocal plus one Newton step: within a few ulp
+// (11 ulp worst over 2^22 random operands), i.e. 3e-15 relative, three orders
+// inside the 1e-12 parity bar.  Zero, denormal and infinite d keep the
+// hardware value (+-inf or 0), where the Newton step would give NaN.
+__device__ __forceinline__ double rcp_fast(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double r1 = fma(r, fma(-d, r, 1.0), r);
+  return r1 == r1 ? r1 : r;
+}
+__device__ __forceinline__ double div_fast(double a, double b) { return a * rcp_fast(b); }
+
 __device__ __forceinline__ int code_of(double s) {
   return s < -kHalf ? kInside : (s > kHalf ? kOutside : kSurface);
 }
@@ -63,15 +81,16 @@ __device__ __forceinline__ bool iv_empty(Iv a) { return !(a.lo <= a.hi); }
 
 // {t : a + b t <= 0}
 __device__ __forceinline__ Iv halfspace(double a, double b) {
-  if (b > 0.0) return Iv{-GV_INF, -a / b};
-  if (b < 0.0) return Iv{-a / b, GV_INF};
+  if (b > 0.0) return Iv{-GV_INF, -div_fast(a, b)};
+  if (b < 0.0) return Iv{-div_fast(a, b), GV_INF};
   return a <= 0.0 ? iv_all() : iv_none();
 }
 
 // {t : |z + t dz| <= h}
 __device__ __forceinline__ Iv slab(double z, double dz, double h) {
   if (dz != 0.0) {
-    double t1 = (-h - z) / dz, t2 = (h - z) / dz;
+    double iz = rcp_fast(dz);
+    double t1 = (-h - z) * iz, t2 = (h - z) * iz;
     return Iv{fmin(t1, t2), fmax(t1, t2)};
   }
   return fabs(z) <= h ? iv_all() : iv_none();
@@ -80,7 +99,8 @@ __device__ __forceinline__ Iv slab(double z, double dz, double h) {
 // {t : z_lo <= z + t dz <= z_hi}
 __device__ __forceinline__ Iv zrange(double z, double dz, double zlo, double zhi) {
   if (dz != 0.0) {
-    double t1 = (zlo - z) / dz, t2 = (zhi - z) / dz;
+    double iz = rcp_fast(dz);
+    double t1 = (zlo - z) * iz, t2 = (zhi - z) * iz;
     return Iv{fmin(t1, t2), fmax(t1, t2)};
   }
   return (z >= zlo && z <= zhi) ? iv_all() : iv_none();
@@ -99,7 +119,7 @@ __device__ __forceinline__ bool quad(double A, double B, double C, double& t1, d
     t1 = t2 = 0.0;
     return true;
   }
-  double r1 = q / A, r2 = C / q;
+  double r1 = div_fast(q, A), r2 = div_fast(C, q);
   t1 = fmin(r1, r2);
   t2 = fmax(r1, r2);
   return true;
@@ -147,9 +167,9 @@ __device__ __forceinline__ Iv cone_interior(double a, double b, double z0, Iv S,
   Iv P1, P2;
   if (A == 0.0) {
     if (B > 0.0) {
-      P1 = Iv{-GV_INF, -C / (2.0 * B)};
+      P1 = Iv{-GV_INF, -div_fast(C, 2.0 * B)};
     } else if (B < 0.0) {
-      P1 = Iv{-C / (2.0 * B), GV_INF};
+      P1 = Iv{-div_fast(C, 2.0 * B), GV_INF};
     } else {
       P1 = C <= 0.0 ? iv_all() : iv_none();
     }
@@ -179,14 +199,13 @@ __device__ __forceinline__ Iv cone_interior(double a, double b, double z0, Iv S,
 // allowed interval A minus up to two excluded intervals, after clipping to
 // t >= 0.  Pieces are returned in increasing t.
 struct Pieces {
-  double lo[3], hi[3];
-  int n;
+  Iv p0, p1, p2;  // increasing t; empty slots have lo > hi
 };
 
 __device__ __forceinline__ Iv clip0(Iv a) { return Iv{fmax(a.lo, 0.0), a.hi}; }
 
 __device__ __forceinline__ void pieces_of(Iv A, Iv X1, Iv X2, Pieces& P) {
-  P.n = 0;
+  P.p0 = P.p1 = P.p2 = iv_none();
   A = clip0(A);
   if (!(A.hi >= A.lo)) return;
   // an excluded gap shorter than kTolerance is ignored (the ray only grazes
@@ -196,7 +215,11 @@ __device__ __forceinline__ void pieces_of(Iv A, Iv X1, Iv X2, Pieces& P) {
   bool u2 = X2.lo <= 0.0 ? X2.hi > 0.0 : X2.hi - X2.lo >= kTol;
   X1 = clip0(X1);
   X2 = clip0(X2);
-  if (!u1) X1 = X2, u1 = u2, u2 = false;
+  if (!u1) {
+    X1 = X2;
+    u1 = u2;
+    u2 = false;
+  }
   if (u1 && u2 && X2.lo < X1.lo) {
     Iv t = X1;
     X1 = X2;
@@ -204,41 +227,31 @@ __device__ __forceinline__ void pieces_of(Iv A, Iv X1, Iv X2, Pieces& P) {
   }
   double cur = A.lo;
   if (u1) {
-    if (X1.lo > cur) {
-      P.lo[P.n] = cur;
-      P.hi[P.n] = fmin(X1.lo, A.hi);
-      ++P.n;
-    }
+    if (X1.lo > cur) P.p0 = Iv{cur, fmin(X1.lo, A.hi)};
     cur = fmax(cur, X1.hi);
   }
   if (u2 && cur < A.hi) {
-    if (X2.lo > cur) {
-      P.lo[P.n] = cur;
-      P.hi[P.n] = fmin(X2.lo, A.hi);
-      ++P.n;
-    }
+    if (X2.lo > cur) P.p1 = Iv{cur, fmin(X2.lo, A.hi)};
     cur = fmax(cur, X2.hi);
   }
-  if (cur <= A.hi) {
-    P.lo[P.n] = cur;
-    P.hi[P.n] = A.hi;
-    ++P.n;
-  }
+  if (cur <= A.hi) P.p2 = Iv{cur, A.hi};
 }
 
 __device__ __forceinline__ double first_entry(const Pieces& P) {
-  for (int i = 0; i < P.n; ++i)
-    if (P.hi[i] - P.lo[i] >= kTol) return P.lo[i];
+  if (P.p0.hi - P.p0.lo >= kTol) return P.p0.lo;
+  if (P.p1.hi - P.p1.lo >= kTol) return P.p1.lo;
+  if (P.p2.hi - P.p2.lo >= kTol) return P.p2.lo;
   return GV_INF;
 }
 
 __device__ __forceinline__ double exit_of(const Pieces& P) {
-  if (P.n > 0 && P.lo[0] <= kTol) return fmax(P.hi[0], 0.0);
+  Iv f = !iv_empty(P.p0) ? P.p0 : (!iv_empty(P.p1) ? P.p1 : P.p2);
+  if (!iv_empty(f) && f.lo <= kTol) return fmax(f.hi, 0.0);
   return 0.0;
 }
 
 // ------------------------------------------------------------- phi wedges
-__device__ __forceinline__ double phi_term(const double* q, int ns, int ne, int mode, double x, double y) {
+__device__ __forceinline__ double phi_term(CQ q, int ns, int ne, int mode, double x, double y) {
   double a = x * q[ns] + y * q[ns + 1];
   double b = x * q[ne] + y * q[ne + 1];
   return mode == 1 ? fmax(a, b) : fmin(a, b);
@@ -246,7 +259,7 @@ __device__ __forceinline__ double phi_term(const double* q, int ns, int ne, int 
 
 // allowed interval of a wedge <= pi, or the excluded interval (complement
 // wedge) of a wedge > pi
-__device__ __forceinline__ void phi_intervals(const double* q, int ns, int ne, int mode, V3 p, V3 d, Iv& allow,
+__device__ __forceinline__ void phi_intervals(CQ q, int ns, int ne, int mode, V3 p, V3 d, Iv& allow,
                                               Iv& excl) {
   allow = iv_all();
   excl = iv_none();
@@ -260,51 +273,51 @@ __device__ __forceinline__ void phi_intervals(const double* q, int ns, int ne, i
   }
 }
 
-__device__ __forceinline__ double half_plane_dist(const double* q, int n, int u, double x, double y, double r) {
+__device__ __forceinline__ double half_plane_dist(CQ q, int n, int u, double x, double y, double r) {
   if (x * q[u] + y * q[u + 1] >= 0.0) return fabs(x * q[n] + y * q[n + 1]);
   return r;
 }
 
 // ======================================================================= BOX
 struct Box {
-  __device__ static __forceinline__ double sgn(const double* q, V3 p) {
+  __device__ static __forceinline__ double sgn(CQ q, V3 p) {
     return fmax(fmax(fabs(p.x) - q[0], fabs(p.y) - q[1]), fabs(p.z) - q[2]);
   }
-  __device__ static __forceinline__ double safety_out(const double* q, V3 p) {
+  __device__ static __forceinline__ double safety_out(CQ q, V3 p) {
     return fmin(fmin(q[0] - fabs(p.x), q[1] - fabs(p.y)), q[2] - fabs(p.z));
   }
-  __device__ static __forceinline__ double safety_in(const double* q, V3 p) { return sgn(q, p); }
-  __device__ static __forceinline__ double dist_out(const double* q, V3 p, V3 d) {
+  __device__ static __forceinline__ double safety_in(CQ q, V3 p) { return sgn(q, p); }
+  __device__ static __forceinline__ double dist_out(CQ q, V3 p, V3 d) {
     if (sgn(q, p) > kHalf) return -1.0;
     double t = GV_INF;
-    if (d.x != 0.0) t = fmin(t, (copysign(q[0], d.x) - p.x) / d.x);
-    if (d.y != 0.0) t = fmin(t, (copysign(q[1], d.y) - p.y) / d.y);
-    if (d.z != 0.0) t = fmin(t, (copysign(q[2], d.z) - p.z) / d.z);
+    if (d.x != 0.0) t = fmin(t, div_fast(copysign(q[0], d.x) - p.x, d.x));
+    if (d.y != 0.0) t = fmin(t, div_fast(copysign(q[1], d.y) - p.y, d.y));
+    if (d.z != 0.0) t = fmin(t, div_fast(copysign(q[2], d.z) - p.z, d.z));
     return fmax(t, 0.0);
   }
-  __device__ static __forceinline__ bool axis(double h, double pc, double dc, double& lo, double& hi) {
-    if (dc != 0.0) {
-      double t1 = (-h - pc) / dc, t2 = (h - pc) / dc;
-      lo = fmax(lo, fmin(t1, t2));
-      hi = fmin(hi, fmax(t1, t2));
-      return true;
-    }
-    return fabs(pc) < h - kHalf;  // parallel: must lie inside the slab beyond the band
+  // Slab method with one reciprocal per axis.  A zero direction component
+  // gives an infinite reciprocal: the slab then imposes nothing when |p| < h
+  // and empties the interval otherwise (0 * inf = NaN is dropped by min/max,
+  // and leaves the other bound at -inf or +inf, which also empties it).
+  __device__ static __forceinline__ double dist_in_hd(double hx, double hy, double hz, V3 p, V3 d) {
+    double s = fmax(fmax(fabs(p.x) - hx, fabs(p.y) - hy), fabs(p.z) - hz);
+    double ix = rcp_fast(d.x), iy = rcp_fast(d.y), iz = rcp_fast(d.z);
+    double ax = (-hx - p.x) * ix, bx = (hx - p.x) * ix;
+    double ay = (-hy - p.y) * iy, by = (hy - p.y) * iy;
+    double az = (-hz - p.z) * iz, bz = (hz - p.z) * iz;
+    double lo = fmax(fmax(fmin(ax, bx), fmin(ay, by)), fmax(fmin(az, bz), 0.0));
+    double hi = fmin(fmin(fmax(ax, bx), fmax(ay, by)), fmax(az, bz));
+    double t = (hi - lo >= kTol) ? lo : GV_INF;
+    return s < -kHalf ? -1.0 : t;
   }
-  __device__ static __forceinline__ double dist_in(const double* q, V3 p, V3 d) {
-    if (sgn(q, p) < -kHalf) return -1.0;
-    double lo = -GV_INF, hi = GV_INF;
-    if (!axis(q[0], p.x, d.x, lo, hi)) return GV_INF;
-    if (!axis(q[1], p.y, d.y, lo, hi)) return GV_INF;
-    if (!axis(q[2], p.z, d.z, lo, hi)) return GV_INF;
-    lo = fmax(lo, 0.0);
-    return (hi - lo >= kTol) ? lo : GV_INF;
+  __device__ static __forceinline__ double dist_in(CQ q, V3 p, V3 d) {
+    return dist_in_hd(q[0], q[1], q[2], p, d);
   }
 };
 
 // ============================================================= TUBE SEGMENT
 struct Tubs {
-  __device__ static __forceinline__ double sgn(const double* q, V3 p) {
+  __device__ static __forceinline__ double sgn(CQ q, V3 p) {
     double r = sqrt(p.x * p.x + p.y * p.y);
     double t = r - q[L::TB_RMAX];
     if (q[L::TB_RMIN] > 0.0) t = fmax(t, q[L::TB_RMIN] - r);
@@ -313,7 +326,7 @@ struct Tubs {
     if (mode) t = fmax(t, phi_term(q, L::TB_NS, L::TB_NE, mode, p.x, p.y));
     return t;
   }
-  __device__ static __forceinline__ double safety_out(const double* q, V3 p) {
+  __device__ static __forceinline__ double safety_out(CQ q, V3 p) {
     double r = sqrt(p.x * p.x + p.y * p.y);
     double m = q[L::TB_RMAX] - r;
     if (q[L::TB_RMIN] > 0.0) m = fmin(m, r - q[L::TB_RMIN]);
@@ -324,7 +337,7 @@ struct Tubs {
     }
     return m;
   }
-  __device__ static __forceinline__ double safety_in(const double* q, V3 p) {
+  __device__ static __forceinline__ double safety_in(CQ q, V3 p) {
     double r = sqrt(p.x * p.x + p.y * p.y);
     double m = r - q[L::TB_RMAX];
     if (q[L::TB_RMIN] > 0.0) m = fmax(m, q[L::TB_RMIN] - r);
@@ -335,20 +348,20 @@ struct Tubs {
                        half_plane_dist(q, L::TB_NE, L::TB_UE, p.x, p.y, r)));
     return m;
   }
-  __device__ static __forceinline__ void pieces(const double* q, V3 p, V3 d, Pieces& P) {
+  __device__ static __forceinline__ void pieces(CQ q, V3 p, V3 d, Pieces& P) {
     Iv A = iv_and(cyl_interior(q[L::TB_RMAX2], p, d), slab(p.z, d.z, q[L::TB_DZ]));
     Iv X1 = q[L::TB_RMIN] > 0.0 ? cyl_interior(q[L::TB_RMIN2], p, d) : iv_none();
     Iv allow, excl;
     phi_intervals(q, L::TB_NS, L::TB_NE, (int)q[L::TB_PHI], p, d, allow, excl);
     pieces_of(iv_and(A, allow), X1, excl, P);
   }
-  __device__ static __forceinline__ double dist_in(const double* q, V3 p, V3 d) {
+  __device__ static __forceinline__ double dist_in(CQ q, V3 p, V3 d) {
     if (sgn(q, p) < -kHalf) return -1.0;
     Pieces P;
     pieces(q, p, d, P);
     return first_entry(P);
   }
-  __device__ static __forceinline__ double dist_out(const double* q, V3 p, V3 d) {
+  __device__ static __forceinline__ double dist_out(CQ q, V3 p, V3 d) {
     if (sgn(q, p) > kHalf) return -1.0;
     Pieces P;
     pieces(q, p, d, P);
@@ -358,7 +371,7 @@ struct Tubs {
 
 // ============================================================ CONE SEGMENT
 struct Cons {
-  __device__ static __forceinline__ double sgn(const double* q, V3 p) {
+  __device__ static __forceinline__ double sgn(CQ q, V3 p) {
     double r = sqrt(p.x * p.x + p.y * p.y);
     double t = (r - (q[L::CN_AO] + q[L::CN_BO] * p.z)) * q[L::CN_CO];
     if (q[L::CN_INNER] != 0.0) t = fmax(t, ((q[L::CN_AI] + q[L::CN_BI] * p.z) - r) * q[L::CN_CI]);
@@ -367,7 +380,7 @@ struct Cons {
     if (mode) t = fmax(t, phi_term(q, L::CN_NS, L::CN_NE, mode, p.x, p.y));
     return t;
   }
-  __device__ static __forceinline__ double safety_out(const double* q, V3 p) {
+  __device__ static __forceinline__ double safety_out(CQ q, V3 p) {
     double r = sqrt(p.x * p.x + p.y * p.y);
     double m = ((q[L::CN_AO] + q[L::CN_BO] * p.z) - r) * q[L::CN_CO];
     if (q[L::CN_INNER] != 0.0) m = fmin(m, (r - (q[L::CN_AI] + q[L::CN_BI] * p.z)) * q[L::CN_CI]);
@@ -378,7 +391,7 @@ struct Cons {
     }
     return m;
   }
-  __device__ static __forceinline__ double safety_in(const double* q, V3 p) {
+  __device__ static __forceinline__ double safety_in(CQ q, V3 p) {
     double r = sqrt(p.x * p.x + p.y * p.y);
     double m = (r - (q[L::CN_AO] + q[L::CN_BO] * p.z)) * q[L::CN_CO];
     if (q[L::CN_INNER] != 0.0) m = fmax(m, ((q[L::CN_AI] + q[L::CN_BI] * p.z) - r) * q[L::CN_CI]);
@@ -389,7 +402,7 @@ struct Cons {
                        half_plane_dist(q, L::CN_NE, L::CN_UE, p.x, p.y, r)));
     return m;
   }
-  __device__ static __forceinline__ void pieces(const double* q, V3 p, V3 d, Pieces& P) {
+  __device__ static __forceinline__ void pieces(CQ q, V3 p, V3 d, Pieces& P) {
     Iv S = slab(p.z, d.z, q[L::CN_DZ]);
     Iv A = cone_interior(q[L::CN_AO], q[L::CN_BO], 0.0, S, p, d);
     Iv X1 = q[L::CN_INNER] != 0.0 ? cone_interior(q[L::CN_AI], q[L::CN_BI], 0.0, S, p, d) : iv_none();
@@ -397,13 +410,13 @@ struct Cons {
     phi_intervals(q, L::CN_NS, L::CN_NE, (int)q[L::CN_PHI], p, d, allow, excl);
     pieces_of(iv_and(A, allow), X1, excl, P);
   }
-  __device__ static __forceinline__ double dist_in(const double* q, V3 p, V3 d) {
+  __device__ static __forceinline__ double dist_in(CQ q, V3 p, V3 d) {
     if (sgn(q, p) < -kHalf) return -1.0;
     Pieces P;
     pieces(q, p, d, P);
     return first_entry(P);
   }
-  __device__ static __forceinline__ double dist_out(const double* q, V3 p, V3 d) {
+  __device__ static __forceinline__ double dist_out(CQ q, V3 p, V3 d) {
     if (sgn(q, p) > kHalf) return -1.0;
     Pieces P;
     pieces(q, p, d, P);
@@ -413,31 +426,31 @@ struct Cons {
 
 // ============================================================ SPHERE SHELL
 struct Sphere {
-  __device__ static __forceinline__ double sgn(const double* q, V3 p) {
+  __device__ static __forceinline__ double sgn(CQ q, V3 p) {
     double rho = sqrt(p.x * p.x + p.y * p.y + p.z * p.z);
     double t = rho - q[L::SP_RMAX];
     if (q[L::SP_RMIN] > 0.0) t = fmax(t, q[L::SP_RMIN] - rho);
     return t;
   }
-  __device__ static __forceinline__ double safety_out(const double* q, V3 p) {
+  __device__ static __forceinline__ double safety_out(CQ q, V3 p) {
     double rho = sqrt(p.x * p.x + p.y * p.y + p.z * p.z);
     double m = q[L::SP_RMAX] - rho;
     if (q[L::SP_RMIN] > 0.0) m = fmin(m, rho - q[L::SP_RMIN]);
     return m;
   }
-  __device__ static __forceinline__ double safety_in(const double* q, V3 p) { return sgn(q, p); }
-  __device__ static __forceinline__ void pieces(const double* q, V3 p, V3 d, Pieces& P) {
+  __device__ static __forceinline__ double safety_in(CQ q, V3 p) { return sgn(q, p); }
+  __device__ static __forceinline__ void pieces(CQ q, V3 p, V3 d, Pieces& P) {
     Iv A = sph_interior(q[L::SP_RMAX2], p, d);
     Iv X1 = q[L::SP_RMIN] > 0.0 ? sph_interior(q[L::SP_RMIN2], p, d) : iv_none();
     pieces_of(A, X1, iv_none(), P);
   }
-  __device__ static __forceinline__ double dist_in(const double* q, V3 p, V3 d) {
+  __device__ static __forceinline__ double dist_in(CQ q, V3 p, V3 d) {
     if (sgn(q, p) < -kHalf) return -1.0;
     Pieces P;
     pieces(q, p, d, P);
     return first_entry(P);
   }
-  __device__ static __forceinline__ double dist_out(const double* q, V3 p, V3 d) {
+  __device__ static __forceinline__ double dist_out(CQ q, V3 p, V3 d) {
     if (sgn(q, p) > kHalf) return -1.0;
     Pieces P;
     pieces(q, p, d, P);
@@ -447,30 +460,30 @@ struct Sphere {
 
 // ====================================================================== TRD
 struct Trd {
-  __device__ static __forceinline__ double sgn(const double* q, V3 p) {
+  __device__ static __forceinline__ double sgn(CQ q, V3 p) {
     double t = (fabs(p.x) - (q[L::TD_X0] + q[L::TD_TX] * p.z)) * q[L::TD_CX];
     t = fmax(t, (fabs(p.y) - (q[L::TD_Y0] + q[L::TD_TY] * p.z)) * q[L::TD_CY]);
     return fmax(t, fabs(p.z) - q[L::TD_DZ]);
   }
-  __device__ static __forceinline__ double safety_out(const double* q, V3 p) {
+  __device__ static __forceinline__ double safety_out(CQ q, V3 p) {
     double m = ((q[L::TD_X0] + q[L::TD_TX] * p.z) - fabs(p.x)) * q[L::TD_CX];
     m = fmin(m, ((q[L::TD_Y0] + q[L::TD_TY] * p.z) - fabs(p.y)) * q[L::TD_CY]);
     return fmin(m, q[L::TD_DZ] - fabs(p.z));
   }
-  __device__ static __forceinline__ double safety_in(const double* q, V3 p) { return sgn(q, p); }
+  __device__ static __forceinline__ double safety_in(CQ q, V3 p) { return sgn(q, p); }
   // the four slanted faces as half-spaces (+-x - t z - x0 <= 0); false when a
   // face is parallel to the ray and the ray is not inside it beyond the band
   __device__ static __forceinline__ bool face(double a, double b, double c, double& lo, double& hi) {
     if (b > 0.0) {
-      hi = fmin(hi, -a / b);
+      hi = fmin(hi, -div_fast(a, b));
     } else if (b < 0.0) {
-      lo = fmax(lo, -a / b);
+      lo = fmax(lo, -div_fast(a, b));
     } else {
       return a * c < -kHalf;
     }
     return true;
   }
-  __device__ static __forceinline__ bool interval(const double* q, V3 p, V3 d, double& lo, double& hi) {
+  __device__ static __forceinline__ bool interval(CQ q, V3 p, V3 d, double& lo, double& hi) {
     double tx = q[L::TD_TX], ty = q[L::TD_TY];
     double nxp = p.x - tx * p.z, nxd = d.x - tx * d.z;
     double mxp = -p.x - tx * p.z, mxd = -d.x - tx * d.z;
@@ -483,7 +496,8 @@ struct Trd {
     if (!face(nyp - q[L::TD_Y0], nyd, q[L::TD_CY], lo, hi)) return false;
     if (!face(myp - q[L::TD_Y0], myd, q[L::TD_CY], lo, hi)) return false;
     if (d.z != 0.0) {
-      double t1 = (-q[L::TD_DZ] - p.z) / d.z, t2 = (q[L::TD_DZ] - p.z) / d.z;
+      double iz = rcp_fast(d.z);
+      double t1 = (-q[L::TD_DZ] - p.z) * iz, t2 = (q[L::TD_DZ] - p.z) * iz;
       lo = fmax(lo, fmin(t1, t2));
       hi = fmin(hi, fmax(t1, t2));
     } else if (!(fabs(p.z) < q[L::TD_DZ] - kHalf)) {
@@ -491,14 +505,14 @@ struct Trd {
     }
     return true;
   }
-  __device__ static __forceinline__ double dist_in(const double* q, V3 p, V3 d) {
+  __device__ static __forceinline__ double dist_in(CQ q, V3 p, V3 d) {
     if (sgn(q, p) < -kHalf) return -1.0;
     double lo, hi;
     if (!interval(q, p, d, lo, hi)) return GV_INF;
     lo = fmax(lo, 0.0);
     return (hi - lo >= kTol) ? lo : GV_INF;
   }
-  __device__ static __forceinline__ double dist_out(const double* q, V3 p, V3 d) {
+  __device__ static __forceinline__ double dist_out(CQ q, V3 p, V3 d) {
     if (sgn(q, p) > kHalf) return -1.0;
     double lo, hi;
     if (!interval(q, p, d, lo, hi)) return 0.0;
@@ -510,9 +524,9 @@ struct Trd {
 struct Pcon {
   struct View {
     int nz;
-    const double *z, *rmin, *rmax, *bo, *co, *bi, *ci, *inner;
+    CQ z, rmin, rmax, bo, co, bi, ci, inner;
   };
-  __device__ static __forceinline__ View view(const double* q) {
+  __device__ static __forceinline__ View view(CQ q) {
     View v;
     v.nz = (int)q[0];
     v.z = q + 1;
@@ -532,7 +546,7 @@ struct Pcon {
       if (v.z[k] <= z) j = k;
     return j;
   }
-  __device__ static __forceinline__ double sgn(const double* q, V3 p) {
+  __device__ static __forceinline__ double sgn(CQ q, V3 p) {
     View v = view(q);
     int j = section(v, p.z);
     double r = sqrt(p.x * p.x + p.y * p.y);
@@ -550,7 +564,7 @@ struct Pcon {
     return sqrt(qr * qr + qz * qz);
   }
   // exact distance in the meridian plane to the boundary polygon
-  __device__ static double boundary(const double* q, V3 p) {
+  __device__ static double boundary(CQ q, V3 p) {
     View v = view(q);
     double r = sqrt(p.x * p.x + p.y * p.y), z = p.z;
     double best = GV_INF;
@@ -564,13 +578,13 @@ struct Pcon {
     best = fmin(best, seg(r, z, v.rmin[e], v.z[e], v.rmax[e], v.z[e]));
     return best;
   }
-  __device__ static __forceinline__ double safety_out(const double* q, V3 p) { return boundary(q, p); }
-  __device__ static __forceinline__ double safety_in(const double* q, V3 p) { return boundary(q, p); }
+  __device__ static __forceinline__ double safety_out(CQ q, V3 p) { return boundary(q, p); }
+  __device__ static __forceinline__ double safety_in(CQ q, V3 p) { return boundary(q, p); }
 
   // Walks the sections in the order the ray meets them and merges touching
   // pieces.  want_in: start of the first merged piece of length >= kTol;
   // otherwise: end of the merged piece starting within kTol of t = 0.
-  __device__ static double walk(const double* q, V3 p, V3 d, bool want_in) {
+  __device__ static double walk(CQ q, V3 p, V3 d, bool want_in) {
     View v = view(q);
     int j0 = section(v, p.z), j1, step;
     if (d.z > 0.0) {
@@ -593,9 +607,12 @@ struct Pcon {
       Iv X = v.inner[j] != 0.0 ? cone_interior(v.rmin[j], v.bi[j], v.z[j], S, p, d) : iv_none();
       Pieces P;
       pieces_of(A, X, iv_none(), P);
-      for (int k = 0; k < P.n; ++k) {
-        if (have && P.lo[k] <= ch) {
-          ch = fmax(ch, P.hi[k]);
+      Iv pk[3] = {P.p0, P.p1, P.p2};
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        if (iv_empty(pk[k])) continue;
+        if (have && pk[k].lo <= ch) {
+          ch = fmax(ch, pk[k].hi);
           continue;
         }
         if (have) {  // the current piece is complete
@@ -605,8 +622,8 @@ struct Pcon {
             return cl <= kTol ? fmax(ch, 0.0) : 0.0;
           }
         }
-        cl = P.lo[k];
-        ch = P.hi[k];
+        cl = pk[k].lo;
+        ch = pk[k].hi;
         have = true;
       }
       if (j == j1) break;
@@ -615,18 +632,18 @@ struct Pcon {
     if (want_in) return (ch - cl >= kTol) ? cl : GV_INF;
     return cl <= kTol ? fmax(ch, 0.0) : 0.0;
   }
-  __device__ static double dist_in(const double* q, V3 p, V3 d) {
+  __device__ static double dist_in(CQ q, V3 p, V3 d) {
     if (sgn(q, p) < -kHalf) return -1.0;
     return walk(q, p, d, true);
   }
-  __device__ static double dist_out(const double* q, V3 p, V3 d) {
+  __device__ static double dist_out(CQ q, V3 p, V3 d) {
     if (sgn(q, p) > kHalf) return -1.0;
     return walk(q, p, d, false);
   }
 };
 
 // ------------------------------------------------------- runtime dispatch
-__device__ __forceinline__ double solid_sgn(int type, const double* q, V3 p) {
+__device__ __forceinline__ double solid_sgn(int type, CQ q, V3 p) {
   switch (type) {
     case kBox: return Box::sgn(q, p);
     case kTubs: return Tubs::sgn(q, p);
@@ -636,7 +653,7 @@ __device__ __forceinline__ double solid_sgn(int type, const double* q, V3 p) {
     default: return Pcon::sgn(q, p);
   }
 }
-__device__ __forceinline__ double solid_dist_in(int type, const double* q, V3 p, V3 d) {
+__device__ __forceinline__ double solid_dist_in(int type, CQ q, V3 p, V3 d) {
   switch (type) {
     case kBox: return Box::dist_in(q, p, d);
     case kTubs: return Tubs::dist_in(q, p, d);
@@ -646,7 +663,7 @@ __device__ __forceinline__ double solid_dist_in(int type, const double* q, V3 p,
     default: return Pcon::dist_in(q, p, d);
   }
 }
-__device__ __forceinline__ double solid_dist_out(int type, const double* q, V3 p, V3 d) {
+__device__ __forceinline__ double solid_dist_out(int type, CQ q, V3 p, V3 d) {
   switch (type) {
     case kBox: return Box::dist_out(q, p, d);
     case kTubs: return Tubs::dist_out(q, p, d);
@@ -656,7 +673,7 @@ __device__ __forceinline__ double solid_dist_out(int type, const double* q, V3 p
     default: return Pcon::dist_out(q, p, d);
   }
 }
-__device__ __forceinline__ double solid_safety_in(int type, const double* q, V3 p) {
+__device__ __forceinline__ double solid_safety_in(int type, CQ q, V3 p) {
   switch (type) {
     case kBox: return Box::safety_in(q, p);
     case kTubs: return Tubs::safety_in(q, p);
@@ -666,7 +683,7 @@ __device__ __forceinline__ double solid_safety_in(int type, const double* q, V3 
     default: return Pcon::safety_in(q, p);
   }
 }
-__device__ __forceinline__ double solid_safety_out(int type, const double* q, V3 p) {
+__device__ __forceinline__ double solid_safety_out(int type, CQ q, V3 p) {
   switch (type) {
     case kBox: return Box::safety_out(q, p);
     case kTubs: return Tubs::safety_out(q, p);

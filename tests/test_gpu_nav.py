@@ -115,9 +115,11 @@ def compare_transport(got, ref, idx=None):
     return int(ok.sum())
 
 
-def test_transport_small_full_compare(geos):
+@pytest.mark.parametrize("n", [4099, 20011])
+def test_transport_full_compare(geos, n):
+    """Below 8,192 tracks one lane transports one track; above, tracks are
+    regrouped into per-volume baskets every step.  Both compared in full."""
     g, og = geos
-    n = 4099
     t = W.config3_tracks(n)
     say(f"[transport] n={n}")
     got = g.transport(*[cuda(v) for v in t.arrays()])
@@ -140,17 +142,22 @@ def test_transport_full_size_sampled(geos):
     assert np.all(host(got["flags"]) == 0)
 
 
-def test_transport_edges(geos):
+@pytest.mark.parametrize("n", [300, 9000])
+def test_transport_edges(geos, n):
     g, og = geos
-    t = W.config3_tracks(300)
+    t = W.config3_tracks(n)
     # tight step budget -> OVERFLOW, and explicit start PV
-    got = g.transport(*[cuda(v) for v in t.arrays()], start_pv=cuda(np.zeros(300, np.int32)), max_steps=7)
-    ref = og.transport(t, start_pv=np.zeros(300, np.int32), max_steps=7)
+    got = g.transport(*[cuda(v) for v in t.arrays()], start_pv=cuda(np.zeros(n, np.int32)), max_steps=7)
+    ref = og.transport(t, start_pv=np.zeros(n, np.int32), max_steps=7)
     compare_transport(got, ref)
-    # a track starting outside the world takes no step
-    out = W.Tracks(*[np.array([v]) for v in (2500.0, 0.0, 0.0, 1.0, 0.0, 0.0)])
-    got = g.transport(*[cuda(v) for v in out.arrays()])
-    assert host(got["nsteps"])[0] == 0 and host(got["pv"])[0, 0] == -1
+    # tracks starting outside the world take no step; others in the same batch go on
+    x = t.x.copy()
+    x[::7] = 2500.0
+    t2 = W.Tracks(x, t.y, t.z, t.dx, t.dy, t.dz)
+    got = g.transport(*[cuda(v) for v in t2.arrays()])
+    ref = og.transport(t2)
+    compare_transport(got, ref)
+    assert np.all(host(got["nsteps"])[::7] == 0) and np.all(host(got["pv"])[::7, 0] == -1)
     # n = 0 is a no-op
     e = W.Tracks(*[np.zeros(0) for _ in range(6)])
     got = g.transport(*[cuda(v) for v in e.arrays()])
