@@ -47,10 +47,11 @@ struct gv_geom {
   void* ws = nullptr;
   size_t ws_bytes = 0;
   int64_t ws_tracks = 0;
-  TState st[2]{};
+  TRec* rec = nullptr;      // [cap] track records
+  int* idx[2] = {nullptr, nullptr};  // bucketed slot lists
   TLayout lay[2]{};
   TCtl ctl{};
-  int* newlv = nullptr;
+  int* nxt_lv = nullptr;    // [cap] next LV per list entry
   int* h_live = nullptr;  // pinned host copies of the live count
   hipEvent_t ev[2] = {nullptr, nullptr};
 };
@@ -669,18 +670,16 @@ namespace {
 
 size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// Two state buffers of n tracks, the next-LV array, and per-LV counters and
-// layouts.  Allocated with hipMalloc on first use and kept in the handle.
+// Track records, two bucketed index lists, the next-LV array, and per-LV
+// counters and layouts.  Allocated with hipMalloc on first use and kept in the
+// handle.
 int ensure_workspace(gv_geom* g, int64_t n) {
   if (g->ws && g->ws_tracks >= n) return GV_OK;
   int64_t cap = n < 4096 ? 4096 : n;
   int nl = g->n_lv;
-  size_t state = 6 * al256(8 * (size_t)cap) + 4 * al256(4 * (size_t)cap);
-  size_t total = 2 * state + al256(4 * (size_t)cap) + 6 * al256(4 * (size_t)(nl + 1)) +
-                 2 * al256(4 * (size_t)nl) + al256(4);
+  size_t total = al256(sizeof(TRec) * (size_t)cap) + 3 * al256(4 * (size_t)cap) +
+                 6 * al256(4 * (size_t)(nl + 1)) + 2 * al256(4 * (size_t)nl) + al256(4);
   if (g->ws) {
-    hipError_t e = hipStreamSynchronize(nullptr);
-    (void)e;
     (void)hipDeviceSynchronize();
     (void)hipFree(g->ws);
     g->ws = nullptr;
@@ -700,20 +699,10 @@ int ensure_workspace(gv_geom* g, int64_t n) {
     p += al256(b);
     return r;
   };
-  for (int s = 0; s < 2; ++s) {
-    TState& S = g->st[s];
-    S.x = (double*)take(8 * cap);
-    S.y = (double*)take(8 * cap);
-    S.z = (double*)take(8 * cap);
-    S.dx = (double*)take(8 * cap);
-    S.dy = (double*)take(8 * cap);
-    S.dz = (double*)take(8 * cap);
-    S.pv = (int*)take(4 * cap);
-    S.tid = (int*)take(4 * cap);
-    S.zr = (int*)take(4 * cap);
-    S.fl = (int*)take(4 * cap);
-  }
-  g->newlv = (int*)take(4 * cap);
+  g->rec = (TRec*)take(sizeof(TRec) * cap);
+  g->idx[0] = (int*)take(4 * cap);
+  g->idx[1] = (int*)take(4 * cap);
+  g->nxt_lv = (int*)take(4 * cap);
   for (int s = 0; s < 2; ++s) {
     g->lay[s].start = (int*)take(4 * (nl + 1));
     g->lay[s].count = (int*)take(4 * (nl + 1));
@@ -749,23 +738,16 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
   const char* fn = "nav_transport";
   GV_TRY(ensure_workspace(g, n));
   const int nl = g->n_lv;
-  TState in{};
-  in.x = (double*)x;
-  in.y = (double*)y;
-  in.z = (double*)z;
-  in.dx = (double*)dx;
-  in.dy = (double*)dy;
-  in.dz = (double*)dz;
-  in.pv = g->st[1].pv;  // located start PVs, staged in the second buffer
   const unsigned sg = stream_grid(n);
   const size_t lds = 8 * (size_t)nl;
-  hipLaunchKernelGGL(k_bt_init, dim3(sg), dim3(kBlock), 0, s, g->dg, n, x, y, z, start_pv, max_steps, out_pv,
-                     out_nsteps, out_flags, g->newlv, g->st[1].pv, g->ctl);
+  hipLaunchKernelGGL(k_bt_init, dim3(sg), dim3(kBlock), 0, s, g->dg, n, x, y, z, dx, dy, dz, start_pv, max_steps,
+                     out_pv, out_nsteps, out_flags, g->rec, g->nxt_lv, g->ctl);
   GV_TRY(launched(fn));
   hipLaunchKernelGGL(k_bt_scan, dim3(1), dim3(kBlock), 0, s, nl, g->ctl, g->lay[0]);
   GV_TRY(launched(fn));
-  hipLaunchKernelGGL(k_bt_scatter, dim3(sg), dim3(kBlock), lds, s, in, (const int*)nullptr, n, g->newlv, g->st[0],
-                     g->lay[0], g->ctl, nl);
+  const unsigned rg = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 4095) / 4096, 256));
+  hipLaunchKernelGGL(k_bt_reindex, dim3(rg), dim3(1024), lds, s, (const int*)nullptr, (const int*)nullptr, n,
+                     g->nxt_lv, g->idx[0], g->lay[0], g->ctl, nl);
   GV_TRY(launched(fn));
   const int64_t max_tiles = n / kWave + nl + 1;
   const unsigned step_grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((max_tiles + 3) / 4, 1024));
@@ -776,15 +758,16 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
   int chunk = 0;
   for (int k = 0; k < max_steps; ++k) {
     int c = k & 1;
-    hipLaunchKernelGGL(k_bt_step, dim3(step_grid), dim3(kBlock), 0, s, g->dg, k, max_steps, g->st[c], g->lay[c],
-                       g->newlv, g->ctl, out_pv, out_step, out_nsteps, out_flags);
+    hipLaunchKernelGGL(k_bt_step, dim3(step_grid), dim3(kBlock), 4 * (size_t)nl, s, g->dg, k, max_steps,
+                       (const int*)g->idx[c],
+                       g->rec, g->lay[c], g->nxt_lv, g->ctl, out_pv, out_step, out_nsteps, out_flags);
     GV_TRY(launched(fn));
     if (k + 1 == max_steps) break;
     hipLaunchKernelGGL(k_bt_scan, dim3(1), dim3(kBlock), 0, s, nl, g->ctl, g->lay[c ^ 1]);
     GV_TRY(launched(fn));
-    hipLaunchKernelGGL(k_bt_scatter, dim3(sg), dim3(kBlock), lds, s, g->st[c],
-                       (const int*)(g->lay[c].start + nl), (int64_t)0, g->newlv, g->st[c ^ 1], g->lay[c ^ 1], g->ctl,
-                       nl);
+    hipLaunchKernelGGL(k_bt_reindex, dim3(rg), dim3(1024), lds, s, (const int*)g->idx[c],
+                       (const int*)(g->lay[c].start + nl), (int64_t)0, g->nxt_lv, g->idx[c ^ 1], g->lay[c ^ 1],
+                       g->ctl, nl);
     GV_TRY(launched(fn));
     if ((k + 1) % kChunk == 0) {
       int slot = chunk & 1;

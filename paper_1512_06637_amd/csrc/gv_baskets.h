@@ -2,15 +2,18 @@
 // before every step (the paper's baskets: particles located in the same kind of
 // volume are collected and processed together, Sec. II.A item 1 and Sec. III.C).
 //
-// Per step the state buffer holds one contiguous bucket per LV.  A wavefront
-// takes a tile of 64 consecutive tracks of one bucket, so its LV -- the mother
-// solid and the whole daughter table -- is wavefront-uniform: the daughter loop
-// reads transforms and solid parameters with scalar loads into SGPRs and the
-// lanes never diverge on the solid type.  After the step each wavefront adds
-// its tracks to the per-LV counts of the next step; a one-workgroup kernel turns
-// the counts into the next bucket layout, and a scatter kernel moves every live
-// track into its new bucket (workgroup-aggregated atomics keep the writes of one
-// workgroup to one bucket contiguous).
+// Track states stay in place (one 64-byte record per track, slot = track id);
+// what is regrouped is a list of slot indices with one contiguous bucket per LV.
+// A wavefront takes a tile of 64 consecutive list entries of one bucket, so its
+// LV -- the mother solid and the whole daughter table -- is wavefront-uniform:
+// the daughter loop reads transforms and solid parameters with scalar loads into
+// SGPRs and the lanes never diverge on the solid type.  After the step each
+// wavefront adds its tracks to the per-LV counts of the next step; a
+// one-workgroup kernel turns the counts into the next bucket layout, and an
+// index-scatter kernel writes each live slot index into its new bucket
+// (workgroup-aggregated atomics keep one workgroup's writes to a bucket
+// contiguous).  Per track and step that moves 12 bytes of indices instead of
+// the 64-byte state.
 #pragma once
 #include "gv_kernels.h"
 
@@ -18,9 +21,10 @@ namespace gv {
 
 constexpr int kWave = 64;
 
-struct TState {
-  double *x, *y, *z, *dx, *dy, *dz;
-  int *pv, *tid, *zr, *fl;
+// one 64-byte record per track
+struct alignas(64) TRec {
+  double x, y, z, dx, dy, dz;
+  int pv, zr, fl, pad;
 };
 
 // bucket layout: start[b] (exclusive prefix of count, start[nlv] = total),
@@ -99,78 +103,103 @@ __device__ void finish_layout(int nlv, TCtl C, TLayout out) {
 }
 
 // ---------------------------------------------------------------- init
-// Start volume of every track (given or located), entry 0 of its sequence, and
-// the counts of the first layout.  Tracks that start outside the world finish
-// here with zero steps.
+// Start volume of every track (given or located), entry 0 of its sequence, its
+// record, and the counts of the first layout.  Tracks that start outside the
+// world finish here with zero steps.  List position = track id.
 __global__ void k_bt_init(DevGeom G, int64_t n, const double* __restrict__ x, const double* __restrict__ y,
-                          const double* __restrict__ z, const int32_t* __restrict__ start_pv, int max_steps,
+                          const double* __restrict__ z, const double* __restrict__ dx, const double* __restrict__ dy,
+                          const double* __restrict__ dz, const int32_t* __restrict__ start_pv, int max_steps,
                           int32_t* __restrict__ out_pv, int32_t* __restrict__ out_nsteps,
-                          uint32_t* __restrict__ out_flags, int* __restrict__ newlv, int* __restrict__ pv_tmp, TCtl C) {
+                          uint32_t* __restrict__ out_flags, TRec* __restrict__ rec, int* __restrict__ nxt_lv, TCtl C) {
   int64_t stride = gstride();
   int64_t nround = ((n + stride - 1) / stride) * stride;
   for (int64_t i = gtid(); i < nround; i += stride) {
     bool act = i < n;
-    int v = -1;
-    uint32_t fl = 0;
+    int v = -1, lv = -1;
     if (act) {
-      v = start_pv ? start_pv[i] : locate(G, ld3(x, y, z, i));
+      uint32_t fl = 0;
+      V3 p = ld3(x, y, z, i);
+      v = start_pv ? start_pv[i] : locate(G, p);
       if (v < -1 || v >= G.n_pv) {
         v = -1;
         fl = kFlagLocateFail;
       }
       out_pv[(size_t)i * (max_steps + 1)] = v;
-      pv_tmp[i] = v;
-      int lv = v >= 0 ? G.pv_lv[v] : -1;
-      newlv[i] = lv;
       if (v < 0) {
         out_nsteps[i] = 0;
         out_flags[i] = fl;
+      } else {
+        lv = G.pv_lv[v];
+        TRec r;
+        r.x = p.x;
+        r.y = p.y;
+        r.z = p.z;
+        r.dx = dx[i];
+        r.dy = dy[i];
+        r.dz = dz[i];
+        r.pv = v;
+        r.zr = 0;
+        r.fl = 0;
+        r.pad = 0;
+        rec[i] = r;
       }
+      nxt_lv[i] = lv;
     }
-    int lv = act && v >= 0 ? G.pv_lv[v] : 0;
-    wave_count(lv, act && v >= 0, C.cnt_next);
+    wave_count(lv >= 0 ? lv : 0, lv >= 0, C.cnt_next);
   }
 }
 
-// Moves every live track of `src` (slots [0, nsrc)) into its bucket of `dst`.
-// Each workgroup handles 256 consecutive slots at a time: LDS atomics rank the
-// tracks per destination LV, then one global atomic per (workgroup, LV)
-// reserves a contiguous range of the bucket.  A NULL src.tid means identity
-// ids; NULL zr / fl mean zero.  Needs 8 * nlv bytes of dynamic LDS.
-__global__ void __launch_bounds__(256) k_bt_scatter(TState src, const int* __restrict__ nsrc_ptr, int64_t nsrc_fixed,
-                                                     const int* __restrict__ newlv, TState dst, TLayout Lnext, TCtl C,
-                                                     int nlv) {
+// wavefront-aggregated reservation in an LDS counter array: returns, for lanes
+// with on, old count + rank among the wave's lanes with the same value
+__device__ __forceinline__ int wave_lds_reserve(int v, bool on, int* cnt) {
+  uint64_t mask = __ballot(on);
+  int pos = 0;
+  while (mask) {
+    int leader = __ffsll((unsigned long long)mask) - 1;
+    int lv = __shfl(v, leader);
+    uint64_t m = __ballot(on && v == lv) & mask;
+    int base = 0;
+    if ((int)__lane_id() == leader) base = atomicAdd(&cnt[lv], __popcll(m));
+    base = __shfl(base, leader);
+    if (on && v == lv) pos = base + __popcll(m & lanemask_lt());
+    mask &= ~m;
+  }
+  return pos;
+}
+
+// Writes the slot index of every live list entry (positions [0, nsrc)) into its
+// bucket of the next list.  Each workgroup owns one contiguous range of
+// entries: it counts them per destination LV in LDS, reserves one contiguous
+// range per LV with a single global atomic, then writes them in a second pass.
+// A NULL src_idx means identity (entry j is slot j).  Needs 8 * nlv bytes of LDS.
+__global__ void __launch_bounds__(1024) k_bt_reindex(const int* __restrict__ src_idx, const int* __restrict__ nsrc_ptr,
+                                                      int64_t nsrc_fixed, const int* __restrict__ nxt_lv,
+                                                      int* __restrict__ dst_idx, TLayout Lnext, TCtl C, int nlv) {
   extern __shared__ int lds[];
   int* cnt = lds;
   int* base = lds + nlv;
   const int64_t nsrc = nsrc_ptr ? *nsrc_ptr : nsrc_fixed;
-  for (int64_t c0 = (int64_t)blockIdx.x * blockDim.x; c0 < nsrc; c0 += (int64_t)gridDim.x * blockDim.x) {
-    for (int b = threadIdx.x; b < nlv; b += blockDim.x) cnt[b] = 0;
-    __syncthreads();
-    const int64_t i = c0 + threadIdx.x;
-    const int v = i < nsrc ? newlv[i] : -1;
-    int rank = 0;
-    if (v >= 0) rank = atomicAdd(&cnt[v], 1);
-    __syncthreads();
-    for (int b = threadIdx.x; b < nlv; b += blockDim.x) {
-      int c = cnt[b];
-      base[b] = c ? Lnext.start[b] + atomicAdd(&C.cursor[b], c) : 0;
-    }
-    __syncthreads();
-    if (v >= 0) {
-      const int slot = base[v] + rank;
-      dst.x[slot] = src.x[i];
-      dst.y[slot] = src.y[i];
-      dst.z[slot] = src.z[i];
-      dst.dx[slot] = src.dx[i];
-      dst.dy[slot] = src.dy[i];
-      dst.dz[slot] = src.dz[i];
-      dst.pv[slot] = src.pv[i];
-      dst.tid[slot] = src.tid ? src.tid[i] : (int)i;
-      dst.zr[slot] = src.zr ? src.zr[i] : 0;
-      dst.fl[slot] = src.fl ? src.fl[i] : 0;
-    }
-    __syncthreads();
+  const int64_t per = ((nsrc + gridDim.x - 1) / gridDim.x + blockDim.x - 1) / blockDim.x * blockDim.x;
+  const int64_t j0 = (int64_t)blockIdx.x * per, j1 = min(nsrc, j0 + per);
+  if (j0 >= j1) return;  // the whole workgroup leaves together
+  for (int b = threadIdx.x; b < nlv; b += blockDim.x) cnt[b] = 0;
+  __syncthreads();
+  // every thread runs the same number of rounds (the round's first entry is < j1)
+  for (int64_t j = j0 + threadIdx.x; j - threadIdx.x < j1; j += blockDim.x) {
+    const int v = j < j1 ? nxt_lv[j] : -1;
+    (void)wave_lds_reserve(v >= 0 ? v : 0, v >= 0, cnt);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nlv; b += blockDim.x) {
+    int c = cnt[b];
+    base[b] = c ? Lnext.start[b] + atomicAdd(&C.cursor[b], c) : 0;
+    cnt[b] = 0;
+  }
+  __syncthreads();
+  for (int64_t j = j0 + threadIdx.x; j - threadIdx.x < j1; j += blockDim.x) {
+    const int v = j < j1 ? nxt_lv[j] : -1;
+    const int r = wave_lds_reserve(v >= 0 ? v : 0, v >= 0, cnt);
+    if (v >= 0) dst_idx[base[v] + r] = src_idx ? src_idx[j] : (int)j;
   }
 }
 
@@ -260,11 +289,14 @@ __device__ __forceinline__ double step_uniform_lv(const DevGeom& G, int lv, int 
   return dout;
 }
 
-__global__ void __launch_bounds__(256) k_bt_step(DevGeom G, int k, int max_steps, TState S, TLayout L,
-                                                  int* __restrict__ newlv, TCtl C,
+__global__ void __launch_bounds__(256) k_bt_step(DevGeom G, int k, int max_steps, const int* __restrict__ idx,
+                                                  TRec* __restrict__ rec, TLayout L, int* __restrict__ nxt_lv, TCtl C,
                                                   int32_t* __restrict__ out_pv, double* __restrict__ out_step,
                                                   int32_t* __restrict__ out_nsteps, uint32_t* __restrict__ out_flags) {
+  extern __shared__ int hist[];  // per-workgroup counts of next LVs
   const int nlv = G.n_lv;
+  for (int v = threadIdx.x; v < nlv; v += blockDim.x) hist[v] = 0;
+  __syncthreads();
   const int tiles = L.tile[nlv];
   const int lane = __lane_id();
   const int wave = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave);
@@ -281,19 +313,19 @@ __global__ void __launch_bounds__(256) k_bt_step(DevGeom G, int k, int max_steps
     const int j = t - L.tile[b];
     const int within = j * kWave + lane;
     const bool act = within < L.count[b];
-    const int i = L.start[b] + within;
+    const int e = L.start[b] + within;
     int nlv_out = -1;
     if (act) {
-      V3 p = ld3(S.x, S.y, S.z, i), d = ld3(S.dx, S.dy, S.dz, i);
-      int pv = S.pv[i];
-      uint32_t fl = (uint32_t)S.fl[i];
+      const int id = idx[e];
+      TRec r = rec[id];
+      V3 p{r.x, r.y, r.z}, d{r.dx, r.dy, r.dz};
+      uint32_t fl = (uint32_t)r.fl;
       int nx;
-      double st = step_uniform_lv(G, b, pv, p, d, &nx, &fl);
+      double st = step_uniform_lv(G, b, r.pv, p, d, &nx, &fl);
       p = advance(p, st, d);
-      int id = S.tid[i];
       out_step[(size_t)id * max_steps + k] = st;
       out_pv[(size_t)id * (max_steps + 1) + k + 1] = nx;
-      int zr = st < kTol ? S.zr[i] + 1 : 0;
+      int zr = st < kTol ? r.zr + 1 : 0;
       bool done = nx < 0;
       if (!done && zr >= 8) {
         fl |= kFlagStuck;
@@ -307,18 +339,21 @@ __global__ void __launch_bounds__(256) k_bt_step(DevGeom G, int k, int max_steps
         out_nsteps[id] = k + 1;
         out_flags[id] = fl;
       } else {
-        S.x[i] = p.x;
-        S.y[i] = p.y;
-        S.z[i] = p.z;
-        S.pv[i] = nx;
-        S.zr[i] = zr;
-        S.fl[i] = (int)fl;
+        rec[id].x = p.x;
+        rec[id].y = p.y;
+        rec[id].z = p.z;
+        rec[id].pv = nx;
+        rec[id].zr = zr;
+        rec[id].fl = (int)fl;
         nlv_out = G.pv_lv[nx];
       }
-      newlv[i] = nlv_out;
+      nxt_lv[e] = nlv_out;
     }
-    wave_count(nlv_out >= 0 ? nlv_out : 0, nlv_out >= 0, C.cnt_next);
+    wave_count(nlv_out >= 0 ? nlv_out : 0, nlv_out >= 0, hist);
   }
+  __syncthreads();
+  for (int v = threadIdx.x; v < nlv; v += blockDim.x)
+    if (hist[v]) atomicAdd(&C.cnt_next[v], hist[v]);
 }
 
 // Next bucket layout from the counts (one workgroup).
