@@ -159,6 +159,20 @@ int nav_transport(gv_geom* g, int64_t n, const double* x, const double* y, const
                   int32_t max_steps, int32_t* out_pv, double* out_step, int32_t* out_nsteps,
                   uint32_t* out_flags, int32_t precision, void* stream);
 
+/* ------------------------------------------------------------ measurement */
+
+/* Kernel timing for measurement.  While enabled, nav_transport records a pair
+ * of HIP events on the caller's stream around every launch of its per-step
+ * kernel.  gv_profile_read waits for those events and returns the summed
+ * kernel milliseconds and the number of launches since the last read (then
+ * forgets them), and, if `work` is not NULL, the operation counts of the last
+ * basket transport (host array of 20 uint64: [0] steps taken, [1] daughter
+ * bounding-box tests, [2+t] daughter lower-bound checks, [8+t] daughter
+ * DistanceToIn evaluations in culled loops, [14+t] DistanceToIn evaluations in
+ * plain loops, t = daughter solid type 0..5).  Reading synchronises the device. */
+int gv_profile(gv_geom* g, int enable);
+int gv_profile_read(gv_geom* g, double* step_ms, int64_t* step_launches, uint64_t* work);
+
 /* Thread-local text of the last error on this thread ("" if none). */
 const char* gv_last_error(void);
 

@@ -38,6 +38,8 @@ _SIGS = {
     "basket_nav_safety": [_P, _I64, _P, _P, _P, _P, _P, _I32, _P],
     "basket_nav_inside": [_P, _I64, _P, _P, _P, _P, _P, _P],
     "nav_transport": [_P, _I64] + [_P] * 7 + [_I32] + [_P] * 4 + [_I32, _P],
+    "gv_profile": [_P, C.c_int],
+    "gv_profile_read": [_P, _P, _P, _P],
 }
 
 _lib = None
@@ -230,6 +232,19 @@ class Geometry:
             self._h, n, _dev(x, f64, "x"), _dev(y, f64, "y"), _dev(z, f64, "z"), _dev(pv, torch.int32, "pv"),
             _dev(out, torch.int8, "out"), _stream()))
         return out
+
+    def profile(self, enable=True):
+        _check("gv_profile", lib().gv_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """(step-kernel ms, launches, work counts: [0] steps, [1] bounding-box tests,
+        [2+t] lower-bound checks, [8+t] culled DistanceToIn, [14+t] plain DistanceToIn,
+        t = daughter solid type)."""
+        ms = C.c_double(0.0)
+        launches = C.c_int64(0)
+        work = (C.c_uint64 * 20)()
+        _check("gv_profile_read", lib().gv_profile_read(self._h, C.byref(ms), C.byref(launches), work))
+        return ms.value, launches.value, list(work)
 
     def transport(self, x, y, z, dx, dy, dz, start_pv=None, max_steps=128, out=None, precision=FP64):
         """Returns dict(pv [n, max_steps+1] int32, step [n, max_steps] f64, nsteps, flags)."""

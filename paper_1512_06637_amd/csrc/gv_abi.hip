@@ -54,6 +54,10 @@ struct gv_geom {
   int* nxt_lv = nullptr;    // [cap] next LV per list entry
   int* h_live = nullptr;  // pinned host copies of the live count
   hipEvent_t ev[2] = {nullptr, nullptr};
+  // kernel timing for measurement (gv_profile)
+  bool prof = false;
+  std::vector<hipEvent_t> prof_ev;  // pairs around step-kernel launches
+  size_t prof_used = 0;
 };
 
 namespace {
@@ -189,6 +193,31 @@ struct HostTree {
   int max_depth = 0;
 };
 
+// Axis-aligned box holding a solid in its own frame, from the derived
+// parameters (layouts in gv_solids.h).
+void local_extent(int type, const double* q, double* lo, double* hi) {
+  double rx = 0, ry = 0, z0 = 0, z1 = 0;
+  switch (type) {
+    case kBox: rx = q[0], ry = q[1], z0 = -q[2], z1 = q[2]; break;
+    case kTubs: rx = ry = q[L::TB_RMAX], z0 = -q[L::TB_DZ], z1 = q[L::TB_DZ]; break;
+    case kCons:
+      rx = ry = std::max(q[L::CN_RMAX1], q[L::CN_RMAX2]), z0 = -q[L::CN_DZ], z1 = q[L::CN_DZ];
+      break;
+    case kSphere: rx = ry = q[L::SP_RMAX], z0 = -q[L::SP_RMAX], z1 = q[L::SP_RMAX]; break;
+    case kTrd:
+      rx = std::max(q[L::TD_DX1], q[L::TD_DX2]), ry = std::max(q[L::TD_DY1], q[L::TD_DY2]);
+      z0 = -q[L::TD_DZ], z1 = q[L::TD_DZ];
+      break;
+    default: {  // polycone: nz z[] rmin[] rmax[] ...
+      int nz = (int)q[0];
+      for (int j = 0; j < nz; ++j) rx = std::max(rx, q[1 + 2 * nz + j]);
+      ry = rx, z0 = q[1], z1 = q[nz];
+    }
+  }
+  lo[0] = -rx, lo[1] = -ry, lo[2] = z0;
+  hi[0] = rx, hi[1] = ry, hi[2] = z1;
+}
+
 // composed transform C = A o B (apply B then A): R = Ra Rb, t = Ra tb + ta
 void compose(const double* A, const double* B, double* C) {
   for (int i = 0; i < 3; ++i) {
@@ -257,6 +286,30 @@ extern "C" int geom_load(const void* blob, size_t nbytes, gv_geom** out) {
     }
     std::vector<int> dau_par(n_place);
     for (int k = 0; k < n_place; ++k) dau_par[k] = lv_par[dau_lv[k]];
+    // bounding box of each placed child in its mother's frame: the 8 corners of
+    // the child's local box through the placement, padded so that rounding can
+    // never make it smaller than the solid
+    std::vector<double> dau_box((size_t)n_place * 6);
+    for (int k = 0; k < n_place; ++k) {
+      const double* q = par.data() + dau_par[k];
+      double lo[3], hi[3];
+      local_extent(lv_type[dau_lv[k]], q, lo, hi);
+      const double* X = &dau_xf[12 * (size_t)k];
+      double blo[3] = {HUGE_VAL, HUGE_VAL, HUGE_VAL}, bhi[3] = {-HUGE_VAL, -HUGE_VAL, -HUGE_VAL};
+      for (int c = 0; c < 8; ++c) {
+        double v[3] = {(c & 1) ? hi[0] : lo[0], (c & 2) ? hi[1] : lo[1], (c & 4) ? hi[2] : lo[2]};
+        for (int i = 0; i < 3; ++i) {
+          double w = X[3 * i] * v[0] + X[3 * i + 1] * v[1] + X[3 * i + 2] * v[2] + X[9 + i];
+          blo[i] = std::min(blo[i], w);
+          bhi[i] = std::max(bhi[i], w);
+        }
+      }
+      for (int i = 0; i < 3; ++i) {
+        double pad = 1e-6 + 1e-9 * (std::fabs(blo[i]) + std::fabs(bhi[i]));
+        dau_box[6 * (size_t)k + i] = blo[i] - pad;
+        dau_box[6 * (size_t)k + 3 + i] = bhi[i] + pad;
+      }
+    }
     // count the tree first (depth and size limits also reject cycles)
     std::vector<long> subtree(n_lv, -1);
     std::vector<int> state(n_lv, 0), height(n_lv, 0);
@@ -337,7 +390,8 @@ extern "C" int geom_load(const void* blob, size_t nbytes, gv_geom** out) {
         {dau_lv.data(), dau_lv.size() * 4, 0},     {T.pv_lv.data(), T.pv_lv.size() * 4, 0},
         {T.pv_parent.data(), T.pv_parent.size() * 4, 0}, {T.pv_gxf.data(), T.pv_gxf.size() * 8, 0},
         {T.pv_child_off.data(), T.pv_child_off.size() * 4, 0}, {T.pv_child.data(), T.pv_child.size() * 4, 0},
-        {lv_dtype.data(), lv_dtype.size() * 4, 0}, {dau_par.data(), dau_par.size() * 4, 0}};
+        {lv_dtype.data(), lv_dtype.size() * 4, 0}, {dau_par.data(), dau_par.size() * 4, 0},
+        {dau_box.data(), dau_box.size() * 8, 0}};
     size_t total = 0;
     for (auto& p : parts) {
       p.off = total;
@@ -383,6 +437,7 @@ extern "C" int geom_load(const void* blob, size_t nbytes, gv_geom** out) {
     D.pv_child = (CQI)(base + parts[11].off);
     D.lv_dau_type = (CQI)(base + parts[12].off);
     D.dau_par = (CQI)(base + parts[13].off);
+    D.dau_box = (CQ)(base + parts[14].off);
     g->n_lv = n_lv;
     g->n_pv = (int)npv;
     g->n_place = n_place;
@@ -409,6 +464,7 @@ extern "C" int geom_free(gv_geom* g) {
   if (g->ws) (void)hipFree(g->ws);
   if (g->dmem) (void)hipFree(g->dmem);
   if (g->h_live) (void)hipHostFree(g->h_live);
+  for (auto& ev : g->prof_ev) (void)hipEventDestroy(ev);
   for (auto& ev : g->ev)
     if (ev) (void)hipEventDestroy(ev);
   if (dev != g->device && dev >= 0) (void)hipSetDevice(dev);
@@ -678,7 +734,7 @@ int ensure_workspace(gv_geom* g, int64_t n) {
   int64_t cap = n < 4096 ? 4096 : n;
   int nl = g->n_lv;
   size_t total = al256(sizeof(TRec) * (size_t)cap) + 3 * al256(4 * (size_t)cap) +
-                 6 * al256(4 * (size_t)(nl + 1)) + 2 * al256(4 * (size_t)nl) + al256(4);
+                 6 * al256(4 * (size_t)(nl + 1)) + 2 * al256(4 * (size_t)nl) + al256(4) + al256(8 * kWorkN);
   if (g->ws) {
     (void)hipDeviceSynchronize();
     (void)hipFree(g->ws);
@@ -711,6 +767,7 @@ int ensure_workspace(gv_geom* g, int64_t n) {
   g->ctl.cnt_next = (int*)take(4 * nl);
   g->ctl.cursor = (int*)take(4 * nl);
   g->ctl.live = (int*)take(4);
+  g->ctl.work = (unsigned long long*)take(8 * kWorkN);
   if (!g->h_live) {
     e = hipHostMalloc((void**)&g->h_live, 2 * sizeof(int), hipHostMallocDefault);
     if (e != hipSuccess) return hip_fail(e, "nav_transport: hipHostMalloc");
@@ -758,10 +815,24 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
   int chunk = 0;
   for (int k = 0; k < max_steps; ++k) {
     int c = k & 1;
+    hipEvent_t* pe = nullptr;
+    if (g->prof) {
+      if (g->prof_used + 2 > g->prof_ev.size()) {
+        hipEvent_t e0, e1;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+          return fail(GV_EHIP, "nav_transport: hipEventCreate for profiling");
+        g->prof_ev.push_back(e0);
+        g->prof_ev.push_back(e1);
+      }
+      pe = &g->prof_ev[g->prof_used];
+      g->prof_used += 2;
+      (void)hipEventRecord(pe[0], s);
+    }
     hipLaunchKernelGGL(k_bt_step, dim3(step_grid), dim3(kBlock), 4 * (size_t)nl, s, g->dg, k, max_steps,
-                       (const int*)g->idx[c],
-                       g->rec, g->lay[c], g->nxt_lv, g->ctl, out_pv, out_step, out_nsteps, out_flags);
+                       (const int*)g->idx[c], g->rec, g->lay[c], g->nxt_lv, g->ctl, out_pv, out_step, out_nsteps,
+                       out_flags);
     GV_TRY(launched(fn));
+    if (pe) (void)hipEventRecord(pe[1], s);
     if (k + 1 == max_steps) break;
     hipLaunchKernelGGL(k_bt_scan, dim3(1), dim3(kBlock), 0, s, nl, g->ctl, g->lay[c ^ 1]);
     GV_TRY(launched(fn));
@@ -813,4 +884,39 @@ extern "C" int nav_transport(gv_geom* g, int64_t n, const double* x, const doubl
   hipLaunchKernelGGL(k_transport_lane, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, g->dg, n, x, y, z,
                      dx, dy, dz, start_pv, (int)max_steps, out_pv, out_step, out_nsteps, out_flags);
   return launched(fn);
+}
+
+// ------------------------------------------------------------ measurement
+extern "C" int gv_profile(gv_geom* g, int enable) {
+  if (!g) return fail(GV_EINVAL, "gv_profile: geometry handle is NULL");
+  g->prof = enable != 0;
+  return GV_OK;
+}
+
+extern "C" int gv_profile_read(gv_geom* g, double* step_ms, int64_t* step_launches, uint64_t* work) {
+  static_assert(kWorkN == 20, "gvgeom.h documents 20 work counters");
+  if (!g) return fail(GV_EINVAL, "gv_profile_read: geometry handle is NULL");
+  DeviceGuard dgd(g->device);
+  double ms = 0.0;
+  for (size_t i = 0; i + 1 < g->prof_used; i += 2) {
+    hipError_t e = hipEventSynchronize(g->prof_ev[i + 1]);
+    if (e != hipSuccess) return hip_fail(e, "gv_profile_read: hipEventSynchronize");
+    float t = 0.0f;
+    e = hipEventElapsedTime(&t, g->prof_ev[i], g->prof_ev[i + 1]);
+    if (e != hipSuccess) return hip_fail(e, "gv_profile_read: hipEventElapsedTime");
+    ms += t;
+  }
+  if (step_ms) *step_ms = ms;
+  if (step_launches) *step_launches = (int64_t)(g->prof_used / 2);
+  g->prof_used = 0;
+  if (work) {
+    if (!g->ws) {
+      for (int i = 0; i < kWorkN; ++i) work[i] = 0;
+    } else {
+      hipError_t e = hipDeviceSynchronize();
+      if (e == hipSuccess) e = hipMemcpy(work, g->ctl.work, 8 * kWorkN, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) return hip_fail(e, "gv_profile_read: counters");
+    }
+  }
+  return GV_OK;
 }

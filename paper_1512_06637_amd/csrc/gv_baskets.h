@@ -37,7 +37,13 @@ struct TCtl {
   int* cnt_next;  // [nlv] tracks entering each LV at the next step
   int* cursor;    // [nlv] scatter cursors
   int* live;      // live tracks after the latest step (device copy)
+  unsigned long long* work;  // [kWorkN] operation counts of the current call
 };
+
+// Work counters of one transport: steps, daughter bounding-box tests, then per
+// daughter solid type the lower-bound checks, the full DistanceToIn
+// evaluations of culled loops, and those of plain loops (6 types each).
+enum { kWorkSteps = 0, kWorkBox = 1, kWorkBound = 2, kWorkFull = 8, kWorkPlain = 14, kWorkN = 20 };
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return __lanemask_lt(); }
 
@@ -111,6 +117,7 @@ __global__ void k_bt_init(DevGeom G, int64_t n, const double* __restrict__ x, co
                           const double* __restrict__ dz, const int32_t* __restrict__ start_pv, int max_steps,
                           int32_t* __restrict__ out_pv, int32_t* __restrict__ out_nsteps,
                           uint32_t* __restrict__ out_flags, TRec* __restrict__ rec, int* __restrict__ nxt_lv, TCtl C) {
+  if (gtid() < kWorkN) C.work[gtid()] = 0ull;
   int64_t stride = gstride();
   int64_t nround = ((n + stride - 1) / stride) * stride;
   for (int64_t i = gtid(); i < nround; i += stride) {
@@ -247,8 +254,80 @@ __device__ __forceinline__ void daughters_of_type(const DevGeom& G, int off, int
   }
 }
 
+// Lower bound of a child's DistanceToIn: its isotropic SafetyToIn (each
+// solid's formula is a lower bound of the true distance); <= 0 when inside.
+template <class S>
+__device__ __forceinline__ double lower_bound(CQ q, V3 pc) {
+  return S::safety_in(q, pc);
+}
+
+// Work counting: the first active lane adds the number of active lanes (times
+// `mult`) to a per-workgroup LDS counter, so a count stays exact inside
+// divergent loops.
+struct Work {
+  unsigned long long* c;  // [kWorkN] in LDS
+};
+__device__ __forceinline__ void count_active(unsigned long long* ctr, unsigned mult = 1) {
+  uint64_t m = __ballot(1);
+  if ((int)__lane_id() == __ffsll((unsigned long long)m) - 1)
+    atomicAdd(ctr, (unsigned long long)__popcll(m) * mult);
+}
+
+// Culled daughter loop.  A daughter can only win if its DistanceToIn is at most
+// the mother's DistanceToOut and below the best daughter found so far, and its
+// DistanceToIn is never below its padded bounding box's entry distance nor
+// below its SafetyToIn.  Pass 1 tests every daughter's bounding box against
+// each lane's ray with wavefront-uniform data and collects per-lane candidate
+// masks; pass 2 lets each lane walk its own candidates in index order, checks
+// the SafetyToIn bound, and evaluates DistanceToIn only where it can still win.
+// The selected daughter is the one the full loop would select.
+template <class S>
+__device__ __forceinline__ void daughters_culled(const DevGeom& G, int off, int cnt, V3 pl, V3 dl, double dout,
+                                                 double& best, int& bestk, bool& neg, Work& w) {
+  const V3 inv{rcp_fast(dl.x), rcp_fast(dl.y), rcp_fast(dl.z)};
+  const V3 pin{-pl.x * inv.x, -pl.y * inv.y, -pl.z * inv.z};
+  const double bound = dout + kTol;
+  for (int c0 = 0; c0 < cnt; c0 += 64) {
+    const int m = min(64, cnt - c0);
+    uint64_t cand = 0;
+    for (int k = 0; k < m; ++k) {
+      CQ B = G.dau_box + 6 * (size_t)(off + c0 + k);
+      double ax = fma(B[0], inv.x, pin.x), bx = fma(B[3], inv.x, pin.x);
+      double ay = fma(B[1], inv.y, pin.y), by = fma(B[4], inv.y, pin.y);
+      double az = fma(B[2], inv.z, pin.z), bz = fma(B[5], inv.z, pin.z);
+      double nr = fmax(fmax(fmin(ax, bx), fmin(ay, by)), fmin(az, bz));
+      double fr = fmin(fmin(fmax(ax, bx), fmax(ay, by)), fmax(az, bz));
+      // NaN-safe: an undecidable comparison keeps the daughter
+      bool out = nr > fr || fr < 0.0 || nr > bound;
+      cand |= out ? 0ull : (1ull << k);
+    }
+    count_active(&w.c[kWorkBox], (unsigned)m);
+    while (cand) {
+      const int k = __builtin_ctzll(cand);
+      cand &= cand - 1;
+      const int pk = off + c0 + k;
+      CQ Y = G.dau_xf + 12 * (size_t)pk;
+      CQ q = G.par + G.dau_par[pk];
+      V3 pc = to_child_p(Y, pl);
+      count_active(&w.c[kWorkBound + S::kType]);
+      if (lower_bound<S>(q, pc) > fmin(best, dout) + kTol) continue;
+      count_active(&w.c[kWorkFull + S::kType]);
+      V3 dc = to_child_d(Y, dl);
+      double t = S::dist_in(q, pc, dc);
+      neg = neg || t < 0.0;
+      t = fmax(t, 0.0);
+      if (t < best) {
+        best = t;
+        bestk = c0 + k;
+      }
+    }
+  }
+}
+
+constexpr int kCullMin = 8;  // LVs with fewer daughters run the plain loop
+
 __device__ __forceinline__ double step_uniform_lv(const DevGeom& G, int lv, int pv, V3 p, V3 d, int* next,
-                                                  uint32_t* flags) {
+                                                  uint32_t* flags, Work& w) {
   CQ X = G.pv_gxf + 12 * (size_t)pv;
   V3 pl = to_child_p(X, p), dl = to_child_d(X, d);
   double dout = solid_dist_out(G.lv_type[lv], G.par + G.lv_par[lv], pl, dl);
@@ -261,16 +340,24 @@ __device__ __forceinline__ double step_uniform_lv(const DevGeom& G, int lv, int 
   int bestk = -1;
   const int off = G.lv_dau_off[lv], cnt = G.lv_dau_cnt[lv], dtype = G.lv_dau_type[lv];
   bool neg = false;
-  if (dtype == kBox) {
+  if (dtype == kBox && cnt >= kCullMin) {
+    daughters_culled<Box>(G, off, cnt, pl, dl, dout, best, bestk, neg, w);
+  } else if (dtype == kTubs && cnt >= kCullMin) {
+    daughters_culled<Tubs>(G, off, cnt, pl, dl, dout, best, bestk, neg, w);
+  } else if (dtype == kBox) {
     daughters_of_type<Box>(G, off, cnt, pl, dl, best, bestk, neg);
+    count_active(&w.c[kWorkPlain + kBox], (unsigned)cnt);
   } else if (dtype == kTubs) {
     daughters_of_type<Tubs>(G, off, cnt, pl, dl, best, bestk, neg);
+    count_active(&w.c[kWorkPlain + kTubs], (unsigned)cnt);
   } else {
     for (int k = 0; k < cnt; ++k) {
       CQ Y = G.dau_xf + 12 * (size_t)(off + k);
       const int clv = G.dau_lv[off + k];
       V3 pc = to_child_p(Y, pl), dc = to_child_d(Y, dl);
-      double t = solid_dist_in(G.lv_type[clv], G.par + G.lv_par[clv], pc, dc);
+      const int ct = G.lv_type[clv];
+      double t = solid_dist_in(ct, G.par + G.lv_par[clv], pc, dc);
+      count_active(&w.c[kWorkPlain + ct]);
       neg = neg || t < 0.0;
       t = fmax(t, 0.0);
       if (t < best) {
@@ -294,9 +381,12 @@ __global__ void __launch_bounds__(256) k_bt_step(DevGeom G, int k, int max_steps
                                                   int32_t* __restrict__ out_pv, double* __restrict__ out_step,
                                                   int32_t* __restrict__ out_nsteps, uint32_t* __restrict__ out_flags) {
   extern __shared__ int hist[];  // per-workgroup counts of next LVs
+  __shared__ unsigned long long wsum[kWorkN];
   const int nlv = G.n_lv;
   for (int v = threadIdx.x; v < nlv; v += blockDim.x) hist[v] = 0;
+  for (int i = threadIdx.x; i < kWorkN; i += blockDim.x) wsum[i] = 0;
   __syncthreads();
+  Work w{wsum};
   const int tiles = L.tile[nlv];
   const int lane = __lane_id();
   const int wave = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave);
@@ -321,7 +411,7 @@ __global__ void __launch_bounds__(256) k_bt_step(DevGeom G, int k, int max_steps
       V3 p{r.x, r.y, r.z}, d{r.dx, r.dy, r.dz};
       uint32_t fl = (uint32_t)r.fl;
       int nx;
-      double st = step_uniform_lv(G, b, r.pv, p, d, &nx, &fl);
+      double st = step_uniform_lv(G, b, r.pv, p, d, &nx, &fl, w);
       p = advance(p, st, d);
       out_step[(size_t)id * max_steps + k] = st;
       out_pv[(size_t)id * (max_steps + 1) + k + 1] = nx;
@@ -349,11 +439,14 @@ __global__ void __launch_bounds__(256) k_bt_step(DevGeom G, int k, int max_steps
       }
       nxt_lv[e] = nlv_out;
     }
+    if (act) count_active(&wsum[kWorkSteps]);
     wave_count(nlv_out >= 0 ? nlv_out : 0, nlv_out >= 0, hist);
   }
   __syncthreads();
   for (int v = threadIdx.x; v < nlv; v += blockDim.x)
     if (hist[v]) atomicAdd(&C.cnt_next[v], hist[v]);
+  for (int i = threadIdx.x; i < kWorkN; i += blockDim.x)
+    if (wsum[i]) atomicAdd(&C.work[i], wsum[i]);
 }
 
 // Next bucket layout from the counts (one workgroup).

@@ -21,6 +21,7 @@ struct DevGeom {
   CQ dau_xf;         // [n_place][12] placement transform, LV frame
   CQI dau_lv;        // [n_place]
   CQI dau_par;       // [n_place] offset of the child solid's parameters in par
+  CQ dau_box;        // [n_place][6] child's bounding box in the mother frame (lo xyz, hi xyz), padded
   CQI pv_lv;         // [n_pv]
   CQI pv_parent;     // [n_pv]
   CQ pv_gxf;         // [n_pv][12] composed world <- PV transform

@@ -280,6 +280,7 @@ __device__ __forceinline__ double half_plane_dist(CQ q, int n, int u, double x, 
 
 // ======================================================================= BOX
 struct Box {
+  static constexpr int kType = kBox;
   __device__ static __forceinline__ double sgn(CQ q, V3 p) {
     return fmax(fmax(fabs(p.x) - q[0], fabs(p.y) - q[1]), fabs(p.z) - q[2]);
   }
@@ -317,6 +318,7 @@ struct Box {
 
 // ============================================================= TUBE SEGMENT
 struct Tubs {
+  static constexpr int kType = kTubs;
   __device__ static __forceinline__ double sgn(CQ q, V3 p) {
     double r = sqrt(p.x * p.x + p.y * p.y);
     double t = r - q[L::TB_RMAX];
@@ -371,6 +373,7 @@ struct Tubs {
 
 // ============================================================ CONE SEGMENT
 struct Cons {
+  static constexpr int kType = kCons;
   __device__ static __forceinline__ double sgn(CQ q, V3 p) {
     double r = sqrt(p.x * p.x + p.y * p.y);
     double t = (r - (q[L::CN_AO] + q[L::CN_BO] * p.z)) * q[L::CN_CO];
@@ -426,6 +429,7 @@ struct Cons {
 
 // ============================================================ SPHERE SHELL
 struct Sphere {
+  static constexpr int kType = kSphere;
   __device__ static __forceinline__ double sgn(CQ q, V3 p) {
     double rho = sqrt(p.x * p.x + p.y * p.y + p.z * p.z);
     double t = rho - q[L::SP_RMAX];
@@ -460,6 +464,7 @@ struct Sphere {
 
 // ====================================================================== TRD
 struct Trd {
+  static constexpr int kType = kTrd;
   __device__ static __forceinline__ double sgn(CQ q, V3 p) {
     double t = (fabs(p.x) - (q[L::TD_X0] + q[L::TD_TX] * p.z)) * q[L::TD_CX];
     t = fmax(t, (fabs(p.y) - (q[L::TD_Y0] + q[L::TD_TY] * p.z)) * q[L::TD_CY]);
@@ -522,6 +527,7 @@ struct Trd {
 
 // ================================================================= POLYCONE
 struct Pcon {
+  static constexpr int kType = kPcon;
   struct View {
     int nz;
     CQ z, rmin, rmax, bo, co, bi, ci, inner;

@@ -50,4 +50,31 @@ def detector_step_classes(pv_rows, nsteps, n_modules=64):
 
 
 def detector_ops(world, layer, module) -> float:
+    """Plain navigator: every daughter's DistanceToIn at every step."""
     return float(world) * OPS_WORLD_STEP + float(layer) * OPS_LAYER_STEP + float(module) * OPS_MODULE_STEP
+
+
+# Culled navigator (the daughter loops that run): a bounding-box test per
+# daughter (6 fma, 6 min/max per axis pair, 4 to combine, 3 compares, 1 select),
+# then per candidate the point transform (12) and the child's SafetyToIn bound,
+# then for survivors the direction transform (9), DistanceToIn and the select.
+AABB_TEST = 20
+RAY_SETUP = 6  # three reciprocals and three products per step
+SAFETY_IN = {0: 5, 1: 9}        # box, tube (by daughter solid type)
+DIST_IN = {0: BOX_DIST_IN, 1: TUBE_DIST_IN}
+DIST_OUT = {"world": BOX_DIST_OUT, "layer": TUBE_DIST_OUT, "module": BOX_DIST_OUT}
+
+
+def detector_ops_culled(world, layer, module, work) -> float:
+    """Operation count of the culled navigator from the library's work counters
+    ([0] steps, [1] box tests, [2+t] bound checks, [8+t] culled DistanceToIn,
+    [14+t] plain DistanceToIn, t = daughter solid type)."""
+    fixed = TRANSFORM + STEP_FIXED
+    ops = world * (fixed + DIST_OUT["world"] + RAY_SETUP) + layer * (fixed + DIST_OUT["layer"] + RAY_SETUP)
+    ops += module * (fixed + DIST_OUT["module"])
+    ops += work[1] * AABB_TEST
+    for t in (0, 1):
+        ops += work[2 + t] * (12 + SAFETY_IN[t])
+        ops += work[8 + t] * (9 + DIST_IN[t] + SELECT)
+        ops += work[14 + t] * (TRANSFORM + DIST_IN[t] + SELECT)
+    return float(ops)
