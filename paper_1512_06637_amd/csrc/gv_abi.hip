@@ -49,7 +49,6 @@ struct gv_geom {
   int64_t ws_tracks = 0;
   TRec* rec = nullptr;      // [cap] track records
   int* idx[2] = {nullptr, nullptr};  // bucketed slot lists
-  TLayout lay[2]{};
   TCtl ctl{};
   int* nxt_lv = nullptr;    // [cap] next LV per list entry
   int* h_live = nullptr;  // pinned host copies of the live count
@@ -733,8 +732,8 @@ int ensure_workspace(gv_geom* g, int64_t n) {
   if (g->ws && g->ws_tracks >= n) return GV_OK;
   int64_t cap = n < 4096 ? 4096 : n;
   int nl = g->n_lv;
-  size_t total = al256(sizeof(TRec) * (size_t)cap) + 3 * al256(4 * (size_t)cap) +
-                 6 * al256(4 * (size_t)(nl + 1)) + 2 * al256(4 * (size_t)nl) + al256(4) + al256(8 * kWorkN);
+  size_t total = al256(sizeof(TRec) * (size_t)cap) + 3 * al256(4 * (size_t)cap) + 6 * al256(4 * (size_t)nl) +
+                 al256(4) + al256(8 * kWorkN);
   if (g->ws) {
     (void)hipDeviceSynchronize();
     (void)hipFree(g->ws);
@@ -759,13 +758,10 @@ int ensure_workspace(gv_geom* g, int64_t n) {
   g->idx[0] = (int*)take(4 * cap);
   g->idx[1] = (int*)take(4 * cap);
   g->nxt_lv = (int*)take(4 * cap);
-  for (int s = 0; s < 2; ++s) {
-    g->lay[s].start = (int*)take(4 * (nl + 1));
-    g->lay[s].count = (int*)take(4 * (nl + 1));
-    g->lay[s].tile = (int*)take(4 * (nl + 1));
+  for (int s = 0; s < 3; ++s) {
+    g->ctl.cnt[s] = (int*)take(4 * nl);
+    g->ctl.cur[s] = (int*)take(4 * nl);
   }
-  g->ctl.cnt_next = (int*)take(4 * nl);
-  g->ctl.cursor = (int*)take(4 * nl);
   g->ctl.live = (int*)take(4);
   g->ctl.work = (unsigned long long*)take(8 * kWorkN);
   if (!g->h_live) {
@@ -796,15 +792,16 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
   GV_TRY(ensure_workspace(g, n));
   const int nl = g->n_lv;
   const unsigned sg = stream_grid(n);
-  const size_t lds = 8 * (size_t)nl;
-  hipLaunchKernelGGL(k_bt_init, dim3(sg), dim3(kBlock), 0, s, g->dg, n, x, y, z, dx, dy, dz, start_pv, max_steps,
-                     out_pv, out_nsteps, out_flags, g->rec, g->nxt_lv, g->ctl);
-  GV_TRY(launched(fn));
-  hipLaunchKernelGGL(k_bt_scan, dim3(1), dim3(kBlock), 0, s, nl, g->ctl, g->lay[0]);
-  GV_TRY(launched(fn));
+  const size_t lds_ix = 16 * (size_t)nl + 8, lds_step = 12 * (size_t)nl + 8;
   const unsigned rg = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 4095) / 4096, 256));
-  hipLaunchKernelGGL(k_bt_reindex, dim3(rg), dim3(1024), lds, s, (const int*)nullptr, (const int*)nullptr, n,
-                     g->nxt_lv, g->idx[0], g->lay[0], g->ctl, nl);
+  TCtl& C = g->ctl;
+  hipLaunchKernelGGL(k_bt_clear, dim3(1), dim3(kBlock), 0, s, C, nl);
+  GV_TRY(launched(fn));
+  hipLaunchKernelGGL(k_bt_init, dim3(sg), dim3(kBlock), 0, s, g->dg, n, x, y, z, dx, dy, dz, start_pv, max_steps,
+                     out_pv, out_nsteps, out_flags, g->rec, g->nxt_lv, C);
+  GV_TRY(launched(fn));
+  hipLaunchKernelGGL(k_bt_reindex, dim3(rg), dim3(1024), lds_ix, s, (const int*)nullptr, (const int*)nullptr, n,
+                     (const int*)g->nxt_lv, g->idx[0], (const int*)C.cnt[0], C.cur[0], C.cnt[1], C.cur[1], C.live, nl);
   GV_TRY(launched(fn));
   const int64_t max_tiles = n / kWave + nl + 1;
   const unsigned step_grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((max_tiles + 3) / 4, 1024));
@@ -814,7 +811,7 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
   constexpr int kChunk = 8;
   int chunk = 0;
   for (int k = 0; k < max_steps; ++k) {
-    int c = k & 1;
+    const int c = k & 1, k0 = k % 3, k1 = (k + 1) % 3, k2 = (k + 2) % 3;
     hipEvent_t* pe = nullptr;
     if (g->prof) {
       if (g->prof_used + 2 > g->prof_ev.size()) {
@@ -828,17 +825,15 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
       g->prof_used += 2;
       (void)hipEventRecord(pe[0], s);
     }
-    hipLaunchKernelGGL(k_bt_step, dim3(step_grid), dim3(kBlock), 4 * (size_t)nl, s, g->dg, k, max_steps,
-                       (const int*)g->idx[c], g->rec, g->lay[c], g->nxt_lv, g->ctl, out_pv, out_step, out_nsteps,
-                       out_flags);
+    hipLaunchKernelGGL(k_bt_step, dim3(step_grid), dim3(kBlock), lds_step, s, g->dg, k, max_steps,
+                       (const int*)g->idx[c], g->rec, (const int*)C.cnt[k0], g->nxt_lv, C.cnt[k1], C, out_pv,
+                       out_step, out_nsteps, out_flags);
     GV_TRY(launched(fn));
     if (pe) (void)hipEventRecord(pe[1], s);
     if (k + 1 == max_steps) break;
-    hipLaunchKernelGGL(k_bt_scan, dim3(1), dim3(kBlock), 0, s, nl, g->ctl, g->lay[c ^ 1]);
-    GV_TRY(launched(fn));
-    hipLaunchKernelGGL(k_bt_reindex, dim3(rg), dim3(1024), lds, s, (const int*)g->idx[c],
-                       (const int*)(g->lay[c].start + nl), (int64_t)0, g->nxt_lv, g->idx[c ^ 1], g->lay[c ^ 1],
-                       g->ctl, nl);
+    hipLaunchKernelGGL(k_bt_reindex, dim3(rg), dim3(1024), lds_ix, s, (const int*)g->idx[c], (const int*)C.cnt[k0],
+                       (int64_t)0, (const int*)g->nxt_lv, g->idx[c ^ 1], (const int*)C.cnt[k1], C.cur[k1], C.cnt[k2],
+                       C.cur[k2], C.live, nl);
     GV_TRY(launched(fn));
     if ((k + 1) % kChunk == 0) {
       int slot = chunk & 1;
@@ -878,7 +873,7 @@ extern "C" int nav_transport(gv_geom* g, int64_t n, const double* x, const doubl
   GV_TRY(check_i32(fn, "out_nsteps", out_nsteps));
   GV_TRY(check_i32(fn, "out_flags", out_flags));
   DeviceGuard dgd(g->device);
-  if (n >= kBasketMin && n <= (1L << 30) && g->n_lv <= 8192)
+  if (n >= kBasketMin && n <= (1L << 30) && g->n_lv <= 4096)
     return basket_transport(g, n, x, y, z, dx, dy, dz, start_pv, max_steps, out_pv, out_step, out_nsteps, out_flags,
                             (hipStream_t)stream);
   hipLaunchKernelGGL(k_transport_lane, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, g->dg, n, x, y, z,

@@ -27,25 +27,23 @@ struct alignas(64) TRec {
   int pv, zr, fl, pad;
 };
 
-// bucket layout: start[b] (exclusive prefix of count, start[nlv] = total),
-// count[b], tile[b] (exclusive prefix of ceil(count/64), tile[nlv] = tiles)
-struct TLayout {
-  int *start, *count, *tile;
-};
-
-struct TCtl {
-  int* cnt_next;  // [nlv] tracks entering each LV at the next step
-  int* cursor;    // [nlv] scatter cursors
-  int* live;      // live tracks after the latest step (device copy)
-  unsigned long long* work;  // [kWorkN] operation counts of the current call
-};
-
 // Work counters of one transport: steps, daughter bounding-box tests, then per
 // daughter solid type the lower-bound checks, the full DistanceToIn
 // evaluations of culled loops, and those of plain loops (6 types each).
 enum { kWorkSteps = 0, kWorkBox = 1, kWorkBound = 2, kWorkFull = 8, kWorkPlain = 14, kWorkN = 20 };
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return __lanemask_lt(); }
+
+// Per-step control arrays.  Counts and cursors are triple-buffered: step k
+// reads counts k and accumulates counts k+1; the index kernel after it reads
+// counts k+1 through cursors k+1 and clears counts and cursors k+2, which no
+// kernel of steps k..k+1 reads.
+struct TCtl {
+  int* cnt[3];    // [nlv] tracks per LV in list k % 3
+  int* cur[3];    // [nlv] index-scatter cursors of list k % 3
+  int* live;      // live tracks in the newest list (read back by the host)
+  unsigned long long* work;  // [kWorkN] operation counts of the current call
+};
 
 // wavefront-aggregated histogram update: one atomic per distinct LV in the wave
 __device__ __forceinline__ void wave_count(int v, bool on, int* cnt) {
@@ -59,53 +57,52 @@ __device__ __forceinline__ void wave_count(int v, bool on, int* cnt) {
   }
 }
 
-__device__ __forceinline__ int ld_acq(const int* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Bucket layout of a list from its per-LV counts, computed by the first
+// wavefront of the workgroup into LDS: start[b] (exclusive prefix, start[nlv] =
+// total) and tile[b] (exclusive prefix of ceil(count/64), tile[nlv] = number
+// of tiles).  Chunks of 64 LVs, a shuffle scan per chunk.  All threads of the
+// workgroup must call it (it ends with a barrier); any block size works.
+__device__ void block_layout(const int* __restrict__ cnt, int nlv, int* start, int* tile) {
+  if (threadIdx.x < kWave) {
+    const int lane = threadIdx.x;
+    int carry = 0, tcarry = 0;
+    for (int b0 = 0; b0 < nlv; b0 += kWave) {
+      const int b = b0 + lane;
+      const int c = b < nlv ? cnt[b] : 0;
+      const int tc = (c + kWave - 1) / kWave;
+      int s = c, ts = tc;  // inclusive scans
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        int u = __shfl_up(s, o), tu = __shfl_up(ts, o);
+        if (lane >= o) {
+          s += u;
+          ts += tu;
+        }
+      }
+      if (b < nlv) {
+        start[b] = carry + s - c;
+        tile[b] = tcarry + ts - tc;
+      }
+      carry += __shfl(s, kWave - 1);
+      tcarry += __shfl(ts, kWave - 1);
+    }
+    if (lane == 0) {
+      start[nlv] = carry;
+      tile[nlv] = tcarry;
+    }
+  }
+  __syncthreads();
 }
 
-// Next layout from the counts, then reset counts and cursors (one workgroup).
-__device__ void finish_layout(int nlv, TCtl C, TLayout out) {
-  __shared__ int part[256];
-  __shared__ int tpart[256];
-  int tid = threadIdx.x, nt = blockDim.x;
-  int per = (nlv + nt - 1) / nt;
-  int b0 = tid * per, b1 = min(nlv, b0 + per);
-  int s = 0, ts = 0;
-  for (int b = b0; b < b1; ++b) {
-    int c = ld_acq(&C.cnt_next[b]);
-    s += c;
-    ts += (c + kWave - 1) / kWave;
-  }
-  part[tid] = s;
-  tpart[tid] = ts;
-  __syncthreads();
-  if (tid == 0) {
-    int a = 0, ta = 0;
-    for (int k = 0; k < nt; ++k) {
-      int v = part[k], tv = tpart[k];
-      part[k] = a;
-      tpart[k] = ta;
-      a += v;
-      ta += tv;
+// Clears the control arrays at the start of a transport.
+__global__ void k_bt_clear(TCtl C, int nlv) {
+  for (int64_t i = gtid(); i < nlv; i += gstride()) {
+    for (int s = 0; s < 3; ++s) {
+      C.cnt[s][i] = 0;
+      C.cur[s][i] = 0;
     }
-    out.start[nlv] = a;
-    out.tile[nlv] = ta;
-    out.count[nlv] = 0;
-    *C.live = a;
   }
-  __syncthreads();
-  s = part[tid];
-  ts = tpart[tid];
-  for (int b = b0; b < b1; ++b) {
-    int c = ld_acq(&C.cnt_next[b]);
-    out.start[b] = s;
-    out.count[b] = c;
-    out.tile[b] = ts;
-    s += c;
-    ts += (c + kWave - 1) / kWave;
-    C.cnt_next[b] = 0;
-    C.cursor[b] = 0;
-  }
+  if (gtid() < kWorkN) C.work[gtid()] = 0ull;
 }
 
 // ---------------------------------------------------------------- init
@@ -117,7 +114,6 @@ __global__ void k_bt_init(DevGeom G, int64_t n, const double* __restrict__ x, co
                           const double* __restrict__ dz, const int32_t* __restrict__ start_pv, int max_steps,
                           int32_t* __restrict__ out_pv, int32_t* __restrict__ out_nsteps,
                           uint32_t* __restrict__ out_flags, TRec* __restrict__ rec, int* __restrict__ nxt_lv, TCtl C) {
-  if (gtid() < kWorkN) C.work[gtid()] = 0ull;
   int64_t stride = gstride();
   int64_t nround = ((n + stride - 1) / stride) * stride;
   for (int64_t i = gtid(); i < nround; i += stride) {
@@ -152,7 +148,7 @@ __global__ void k_bt_init(DevGeom G, int64_t n, const double* __restrict__ x, co
       }
       nxt_lv[i] = lv;
     }
-    wave_count(lv >= 0 ? lv : 0, lv >= 0, C.cnt_next);
+    wave_count(lv >= 0 ? lv : 0, lv >= 0, C.cnt[0]);
   }
 }
 
@@ -174,18 +170,42 @@ __device__ __forceinline__ int wave_lds_reserve(int v, bool on, int* cnt) {
   return pos;
 }
 
-// Writes the slot index of every live list entry (positions [0, nsrc)) into its
-// bucket of the next list.  Each workgroup owns one contiguous range of
-// entries: it counts them per destination LV in LDS, reserves one contiguous
-// range per LV with a single global atomic, then writes them in a second pass.
-// A NULL src_idx means identity (entry j is slot j).  Needs 8 * nlv bytes of LDS.
-__global__ void __launch_bounds__(1024) k_bt_reindex(const int* __restrict__ src_idx, const int* __restrict__ nsrc_ptr,
+// Writes the slot index of every live entry of list k (positions [0, total of
+// counts k), or [0, n) with identity slots for the first list) into its bucket
+// of list k+1.  Each workgroup owns one contiguous range of entries: it counts
+// them per destination LV in LDS, reserves one contiguous range per LV with a
+// single global atomic, then writes them in a second pass.  Workgroup 0 also
+// publishes the live count and clears counts and cursors of list k+2.  Needs
+// 16 * nlv + 8 bytes of dynamic LDS.
+__global__ void __launch_bounds__(1024) k_bt_reindex(const int* __restrict__ src_idx, const int* __restrict__ cnt_src,
                                                       int64_t nsrc_fixed, const int* __restrict__ nxt_lv,
-                                                      int* __restrict__ dst_idx, TLayout Lnext, TCtl C, int nlv) {
+                                                      int* __restrict__ dst_idx, const int* __restrict__ cnt_dst,
+                                                      int* __restrict__ cur_dst, int* __restrict__ cnt_clear,
+                                                      int* __restrict__ cur_clear, int* __restrict__ live, int nlv) {
   extern __shared__ int lds[];
   int* cnt = lds;
   int* base = lds + nlv;
-  const int64_t nsrc = nsrc_ptr ? *nsrc_ptr : nsrc_fixed;
+  int* start = lds + 2 * nlv;     // nlv + 1 entries
+  int* tile = lds + 3 * nlv + 1;  // nlv + 1 entries (unused here)
+  block_layout(cnt_dst, nlv, start, tile);
+  int64_t nsrc = nsrc_fixed;
+  if (cnt_src) {
+    __shared__ int total;
+    if (threadIdx.x == 0) total = 0;
+    __syncthreads();
+    int acc = 0;
+    for (int b = threadIdx.x; b < nlv; b += blockDim.x) acc += cnt_src[b];
+    atomicAdd(&total, acc);
+    __syncthreads();
+    nsrc = total;
+  }
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) *live = start[nlv];
+    for (int b = threadIdx.x; b < nlv; b += blockDim.x) {
+      cnt_clear[b] = 0;
+      cur_clear[b] = 0;
+    }
+  }
   const int64_t per = ((nsrc + gridDim.x - 1) / gridDim.x + blockDim.x - 1) / blockDim.x * blockDim.x;
   const int64_t j0 = (int64_t)blockIdx.x * per, j1 = min(nsrc, j0 + per);
   if (j0 >= j1) return;  // the whole workgroup leaves together
@@ -199,7 +219,7 @@ __global__ void __launch_bounds__(1024) k_bt_reindex(const int* __restrict__ src
   __syncthreads();
   for (int b = threadIdx.x; b < nlv; b += blockDim.x) {
     int c = cnt[b];
-    base[b] = c ? Lnext.start[b] + atomicAdd(&C.cursor[b], c) : 0;
+    base[b] = c ? start[b] + atomicAdd(&cur_dst[b], c) : 0;
     cnt[b] = 0;
   }
   __syncthreads();
@@ -377,17 +397,22 @@ __device__ __forceinline__ double step_uniform_lv(const DevGeom& G, int lv, int 
 }
 
 __global__ void __launch_bounds__(256) k_bt_step(DevGeom G, int k, int max_steps, const int* __restrict__ idx,
-                                                  TRec* __restrict__ rec, TLayout L, int* __restrict__ nxt_lv, TCtl C,
+                                                  TRec* __restrict__ rec, const int* __restrict__ cnt_cur,
+                                                  int* __restrict__ nxt_lv, int* __restrict__ cnt_next, TCtl C,
                                                   int32_t* __restrict__ out_pv, double* __restrict__ out_step,
                                                   int32_t* __restrict__ out_nsteps, uint32_t* __restrict__ out_flags) {
-  extern __shared__ int hist[];  // per-workgroup counts of next LVs
+  // dynamic LDS: next-LV histogram [nlv], this list's layout start/tile [nlv+1] each
+  extern __shared__ int lds[];
   __shared__ unsigned long long wsum[kWorkN];
   const int nlv = G.n_lv;
+  int* hist = lds;
+  int* start = lds + nlv;
+  int* tilep = lds + 2 * nlv + 1;
   for (int v = threadIdx.x; v < nlv; v += blockDim.x) hist[v] = 0;
   for (int i = threadIdx.x; i < kWorkN; i += blockDim.x) wsum[i] = 0;
-  __syncthreads();
+  block_layout(cnt_cur, nlv, start, tilep);
   Work w{wsum};
-  const int tiles = L.tile[nlv];
+  const int tiles = tilep[nlv];
   const int lane = __lane_id();
   const int wave = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave);
   const int nwaves = (int)(gridDim.x * (int64_t)blockDim.x / kWave);
@@ -396,14 +421,14 @@ __global__ void __launch_bounds__(256) k_bt_step(DevGeom G, int k, int max_steps
     int lo = 0, hi = nlv - 1;
     while (lo < hi) {
       int mid = (lo + hi + 1) >> 1;
-      if (L.tile[mid] <= t) lo = mid;
+      if (tilep[mid] <= t) lo = mid;
       else hi = mid - 1;
     }
     const int b = __builtin_amdgcn_readfirstlane(lo);
-    const int j = t - L.tile[b];
+    const int j = t - tilep[b];
     const int within = j * kWave + lane;
-    const bool act = within < L.count[b];
-    const int e = L.start[b] + within;
+    const bool act = within < start[b + 1] - start[b];
+    const int e = start[b] + within;
     int nlv_out = -1;
     if (act) {
       const int id = idx[e];
@@ -444,12 +469,10 @@ __global__ void __launch_bounds__(256) k_bt_step(DevGeom G, int k, int max_steps
   }
   __syncthreads();
   for (int v = threadIdx.x; v < nlv; v += blockDim.x)
-    if (hist[v]) atomicAdd(&C.cnt_next[v], hist[v]);
+    if (hist[v]) atomicAdd(&cnt_next[v], hist[v]);
   for (int i = threadIdx.x; i < kWorkN; i += blockDim.x)
     if (wsum[i]) atomicAdd(&C.work[i], wsum[i]);
 }
 
-// Next bucket layout from the counts (one workgroup).
-__global__ void __launch_bounds__(256) k_bt_scan(int nlv, TCtl C, TLayout Lnext) { finish_layout(nlv, C, Lnext); }
 
 }  // namespace gv
