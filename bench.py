@@ -51,6 +51,46 @@ def cpu_baseline(blob, tracks, target_s=12.0, max_s=30.0):
             "sample": f"first {done_tracks} of the 2^20 tracks ({done_steps} track-steps, {spent:.1f} s)"}
 
 
+def fp32_leg(g, a, ref, max_steps, args, ms64):
+    """The same workload with precision FP32_REFINE (FP32 daughter screens, FP64
+    distances): time per call, whether every output equals the FP64 run's, and
+    the share of culled track-steps whose screens ran in FP32."""
+    import torch
+
+    import paper_1512_06637_amd as G
+
+    n = ref["nsteps"].shape[0]
+    out = {k: torch.empty_like(v) for k, v in ref.items()}
+    for _ in range(args.warmup):
+        g.transport(*a, max_steps=max_steps, out=out, precision=G.FP32_REFINE)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        g.transport(*a, max_steps=max_steps, out=out, precision=G.FP32_REFINE)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    g.profile(True)
+    g.transport(*a, max_steps=max_steps, out=out, precision=G.FP32_REFINE)
+    step_ms, _, work = g.profile_read()
+    g.profile(False)
+    ns = ref["nsteps"]
+    k = torch.arange(max_steps, device=ns.device)[None, :]
+    m = k < ns[:, None].long()
+    mp = torch.cat([torch.ones((n, 1), dtype=torch.bool, device=ns.device), m], dim=1)
+    same = (torch.equal(ns, out["nsteps"]) and torch.equal(ref["flags"], out["flags"])
+            and torch.equal(ref["pv"][mp], out["pv"][mp])
+            and torch.equal(ref["step"][m].view(torch.int64), out["step"][m].view(torch.int64)))
+    total = int(ns.sum())
+    return {"ms_per_step": ms, "value": total / (ms * 1e-3), "speedup_vs_fp64": ms64 / ms,
+            "kernel_ms_per_transport": step_ms, "identical_to_fp64": bool(same),
+            "fp32_screened_frac": work[20] / max(1, work[20] + work[21]),
+            "daughter_box_tests": work[1], "dist_in_box_tube": work[8:10]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -58,6 +98,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-screen + FP64-refine leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -142,6 +183,8 @@ def main():
         "wall_s": wall,
         "flags_nonzero": int((flags != 0).sum()),
     }
+    if not args.no_fp32:
+        res["fp32_refine"] = fp32_leg(g, a, out, max_steps, args, ms)
     g.close()
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(blob, tracks)

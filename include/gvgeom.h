@@ -38,7 +38,7 @@ extern "C" {
 
 typedef struct gv_geom gv_geom; /* opaque, device resident, owned by the library */
 
-enum { GV_OK = 0, GV_EINVAL = -1, GV_ENOMEM = -2, GV_EHIP = -3, GV_EFORMAT = -4, GV_ESTATE = -5 };
+enum { GV_OK = 0, GV_EINVAL = -1, GV_ENOMEM = -2, GV_EHIP = -3, GV_EFORMAT = -4, GV_ESTATE = -5, GV_EAGAIN = -6 };
 
 /* Inside codes (int8) */
 enum { GV_OUTSIDE = 0, GV_SURFACE = 1, GV_INSIDE = 2 };
@@ -46,7 +46,14 @@ enum { GV_OUTSIDE = 0, GV_SURFACE = 1, GV_INSIDE = 2 };
 enum { GV_TO_IN = 0, GV_TO_OUT = 1 };
 /* basket_safety side */
 enum { GV_SAFETY_AUTO = 0, GV_SAFETY_IN = 1, GV_SAFETY_OUT = 2 };
-/* arithmetic of the navigation entry points */
+/* Arithmetic of the navigation entry points.  GV_FP32_REFINE screens the
+ * daughters of box- and tube-daughter volumes in FP32 (bounding-box slab test
+ * and a SafetyToIn lower bound, on FP32 copies of the tables, with rounding
+ * margins that keep both conservative) and computes every surviving distance
+ * in FP64 (Sec. III.C: the single-precision variant of the vectorised
+ * navigator, here as a screen only).  Its outputs equal those of GV_FP64 bit
+ * for bit; a wavefront whose points lie outside the range the FP32 margins
+ * cover falls back to the FP64 screens. */
 enum { GV_FP64 = 0, GV_FP32_REFINE = 1 };
 /* per-track transport flags */
 #define GV_FLAG_OVERFLOW 1u    /* max_steps reached before leaving the world */
@@ -136,7 +143,8 @@ int basket_step(gv_geom* g, int64_t n, const double* x, const double* y, const d
 
 /* Isotropic safety of each point in its volume: max(0, min(SafetyToOut of the
  * volume, SafetyToIn of every daughter)); 0 when the point is not strictly
- * inside its volume or not strictly outside every daughter. */
+ * inside its volume or not strictly outside every daughter.  precision GV_FP64
+ * or GV_FP32_REFINE (same values). */
 int basket_nav_safety(gv_geom* g, int64_t n, const double* x, const double* y, const double* z,
                       const int32_t* pv, double* out, int32_t precision, void* stream);
 
@@ -151,6 +159,7 @@ int basket_nav_inside(gv_geom* g, int64_t n, const double* x, const double* y, c
  *             step k (-1 = left the world); entries past out_nsteps untouched;
  *   out_step  [n][max_steps] double: step lengths;
  *   out_nsteps[n] int32, out_flags[n] uint32 (GV_FLAG_*).
+ * precision GV_FP64 or GV_FP32_REFINE (same outputs).
  * 1 <= max_steps <= 4096.  The library keeps a device workspace inside `g`,
  * grown on demand (hipMalloc) and freed by geom_free; concurrent calls on the
  * same `g` from several streams are not allowed (GV_ESTATE is not detected). */
@@ -166,12 +175,76 @@ int nav_transport(gv_geom* g, int64_t n, const double* x, const double* y, const
  * kernel.  gv_profile_read waits for those events and returns the summed
  * kernel milliseconds and the number of launches since the last read (then
  * forgets them), and, if `work` is not NULL, the operation counts of the last
- * basket transport (host array of 20 uint64: [0] steps taken, [1] daughter
+ * basket transport (host array of 22 uint64: [0] steps taken, [1] daughter
  * bounding-box tests, [2+t] daughter lower-bound checks, [8+t] daughter
  * DistanceToIn evaluations in culled loops, [14+t] DistanceToIn evaluations in
- * plain loops, t = daughter solid type 0..5).  Reading synchronises the device. */
+ * plain loops, t = daughter solid type 0..5, [20] track-steps of culled loops
+ * screened in FP32, [21] those screened in FP64).  Reading synchronises the
+ * device. */
 int gv_profile(gv_geom* g, int enable);
 int gv_profile_read(gv_geom* g, double* step_ms, int64_t* step_launches, uint64_t* work);
+
+/* --------------------------------------------------------------- serving */
+/* A serving engine answers baskets of navigation queries that arrive over
+ * time.  The paper's scheduler gathers tracks into baskets and hands each full
+ * basket to the vectorised geometry code (Sec. II.A item 1, Sec. III.C); here
+ * clients hand in baskets, and every basket waiting when a stream falls idle
+ * is answered by one round: one copy of the round's inputs per contiguous run,
+ * ONE fused kernel over all of its queries, one copy back per run.
+ *
+ * Host byte layout of one basket of n tracks (packed, in this order):
+ *   GV_Q_STEP    in : x y z dx dy dz pstep (n double each), pv (n int32)   60 n bytes
+ *                out: step (n double), next_pv (n int32), flags (n uint32) 16 n bytes
+ *   GV_Q_SAFETY  in : x y z (n double each), pv (n int32)                  28 n bytes
+ *                out: safety (n double)                                     8 n bytes
+ *   GV_Q_INSIDE  in : as GV_Q_SAFETY;  out: Inside code (n int8)              n bytes
+ * The answers are those of basket_step (pstep = +inf: no physics limit),
+ * basket_nav_safety and basket_nav_inside, in the basket's precision.
+ *
+ * The engine runs on the calling thread only, inside submit, poll and drain
+ * (no background thread); one server is used from one thread at a time.  A
+ * server must be destroyed before its geometry.  After a GV_EHIP return the
+ * server should only be destroyed. */
+typedef struct gv_server gv_server;
+enum { GV_Q_STEP = 0, GV_Q_SAFETY = 1, GV_Q_INSIDE = 2 };
+
+/* Creates a server on the geometry's device: at most `slots` (1..1024)
+ * baskets admitted and not yet returned, an HBM arena of `hbm_budget` bytes
+ * (64 KiB .. 1 TiB; 4/5 for inputs, 1/5 for outputs, one hipMalloc here and
+ * none later) with a pinned host mirror of the same size, and `nstreams`
+ * (1..8) streams, so up to nstreams rounds are in flight. */
+int gv_server_create(gv_geom* g, int32_t slots, int64_t hbm_budget, int32_t nstreams, gv_server** out);
+
+/* Admits one basket (n >= 1 tracks; kind GV_Q_*; precision GV_FP64 or
+ * GV_FP32_REFINE).  `in` (host, layout above) is copied into pinned staging
+ * before the call returns; `out` (host, layout above) must stay valid until
+ * gv_server_poll returns this basket's *ticket, and is written then.
+ * GV_EAGAIN: all slots taken or no contiguous room in an arena now (nothing
+ * admitted; poll and retry).  GV_EINVAL: the basket can never fit the budget. */
+int gv_server_submit(gv_server* s, int32_t kind, int32_t precision, int64_t n, const void* in, void* out,
+                     uint64_t* ticket);
+
+/* Non-blocking.  Completes every finished round (outputs written to the
+ * callers' buffers, slots and arena space released), launches waiting baskets,
+ * and returns up to `max` completed tickets in completion order, with
+ * t_done[i] (nullable) the device completion time of the ticket's round on the
+ * gv_now() clock (mapped from HIP events). */
+int gv_server_poll(gv_server* s, int32_t max, uint64_t* tickets, double* t_done, int32_t* count);
+
+/* Blocks until every admitted basket has completed (tickets still come from
+ * gv_server_poll). */
+int gv_server_drain(gv_server* s);
+
+/* out[0..7] = admitted, waiting (not yet launched), rounds launched, baskets
+ * launched, tracks launched, largest round (baskets), input-arena bytes held,
+ * output-arena bytes held. */
+int gv_server_stats(const gv_server* s, int64_t* out);
+
+/* Drains, then frees the server's memory, streams and events.  NULL is a no-op. */
+int gv_server_destroy(gv_server* s);
+
+/* Seconds on the monotonic clock that gv_server_poll's times use. */
+double gv_now(void);
 
 /* Thread-local text of the last error on this thread ("" if none). */
 const char* gv_last_error(void);

@@ -15,11 +15,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgvgeom.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "gvgeom.h")
 
-GV_OK, GV_EINVAL, GV_ENOMEM, GV_EHIP, GV_EFORMAT, GV_ESTATE = 0, -1, -2, -3, -4, -5
+GV_OK, GV_EINVAL, GV_ENOMEM, GV_EHIP, GV_EFORMAT, GV_ESTATE, GV_EAGAIN = 0, -1, -2, -3, -4, -5, -6
+Q_STEP, Q_SAFETY, Q_INSIDE = 0, 1, 2
 OUTSIDE, SURFACE, INSIDE = 0, 1, 2
 TO_IN, TO_OUT = 0, 1
 SAFETY_AUTO, SAFETY_IN, SAFETY_OUT = 0, 1, 2
 FP64, FP32_REFINE = 0, 1
+WORK_N = 22  # work counters returned by gv_profile_read
 FLAG_OVERFLOW, FLAG_STUCK, FLAG_LOCATE_FAIL = 1, 2, 4
 
 _P = C.c_void_p
@@ -40,6 +42,12 @@ _SIGS = {
     "nav_transport": [_P, _I64] + [_P] * 7 + [_I32] + [_P] * 4 + [_I32, _P],
     "gv_profile": [_P, C.c_int],
     "gv_profile_read": [_P, _P, _P, _P],
+    "gv_server_create": [_P, _I32, _I64, _I32, C.POINTER(_P)],
+    "gv_server_submit": [_P, _I32, _I32, _I64, _P, _P, _P],
+    "gv_server_poll": [_P, _I32, _P, _P, _P],
+    "gv_server_drain": [_P],
+    "gv_server_stats": [_P, _P],
+    "gv_server_destroy": [_P],
 }
 
 _lib = None
@@ -68,6 +76,8 @@ def lib():
             f.restype = C.c_int
         L.gv_last_error.restype = C.c_char_p
         L.gv_last_error.argtypes = []
+        L.gv_now.restype = C.c_double
+        L.gv_now.argtypes = []
         _lib = L
     return _lib
 
@@ -76,7 +86,7 @@ def header_functions():
     """Names of the functions declared by include/gvgeom.h."""
     txt = open(HEADER).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(\w+)\s*\(", txt, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|double|const char\*)\s+(\w+)\s*\(", txt, flags=re.M)))
 
 
 def _check(fn, rc):
@@ -239,10 +249,11 @@ class Geometry:
     def profile_read(self):
         """(step-kernel ms, launches, work counts: [0] steps, [1] bounding-box tests,
         [2+t] lower-bound checks, [8+t] culled DistanceToIn, [14+t] plain DistanceToIn,
-        t = daughter solid type)."""
+        t = daughter solid type, [20] culled track-steps screened in FP32, [21] culled
+        track-steps screened in FP64)."""
         ms = C.c_double(0.0)
         launches = C.c_int64(0)
-        work = (C.c_uint64 * 20)()
+        work = (C.c_uint64 * WORK_N)()
         _check("gv_profile_read", lib().gv_profile_read(self._h, C.byref(ms), C.byref(launches), work))
         return ms.value, launches.value, list(work)
 
@@ -265,3 +276,100 @@ class Geometry:
             _dev(out["nsteps"], torch.int32, "nsteps", n), _dev(out["flags"], torch.int32, "flags", n), precision,
             _stream()))
         return out
+
+
+# ------------------------------------------------------------------ serving
+def serve_in_bytes(kind, n):
+    return (60 if kind == Q_STEP else 28) * n
+
+
+def serve_out_bytes(kind, n):
+    return (16 if kind == Q_STEP else 8 if kind == Q_SAFETY else 1) * n
+
+
+def pack_basket(kind, x, y, z, pv, dx=None, dy=None, dz=None, pstep=None):
+    """Host byte block of one basket in the serving layout (numpy uint8)."""
+    import numpy as np
+    n = len(x)
+    f = [np.ascontiguousarray(v, np.float64) for v in (x, y, z)]
+    if kind == Q_STEP:
+        ps = np.full(n, np.inf) if pstep is None else pstep
+        f += [np.ascontiguousarray(v, np.float64) for v in (dx, dy, dz, ps)]
+    parts = [v.view(np.uint8) for v in f] + [np.ascontiguousarray(pv, np.int32).view(np.uint8)]
+    out = np.concatenate(parts)
+    assert out.size == serve_in_bytes(kind, n)
+    return out
+
+
+def unpack_result(kind, buf, n):
+    """Views of a basket's output block: (step, next_pv, flags), safety, or code."""
+    import numpy as np
+    if kind == Q_STEP:
+        return (buf[:8 * n].view(np.float64), buf[8 * n:12 * n].view(np.int32), buf[12 * n:16 * n].view(np.uint32))
+    if kind == Q_SAFETY:
+        return buf[:8 * n].view(np.float64)
+    return buf[:n].view(np.int8)
+
+
+def now():
+    """Seconds on the clock of Server.poll's completion times."""
+    return lib().gv_now()
+
+
+class Server:
+    """Serving engine over a resident Geometry (gv_server_* of include/gvgeom.h).
+    Input and output blocks are host numpy uint8 arrays in the serving layout;
+    an output block must stay alive until poll() returns its ticket."""
+
+    def __init__(self, geometry, slots=64, hbm_budget=256 << 20, nstreams=2):
+        self._g = geometry
+        h = C.c_void_p()
+        _check("gv_server_create", lib().gv_server_create(geometry._h, slots, hbm_budget, nstreams, C.byref(h)))
+        self._h = h
+        self._keep = {}  # ticket -> output buffer (kept alive until returned)
+
+    def submit(self, kind, precision, n, inbuf, outbuf):
+        """Ticket, or None when the server is full now (GV_EAGAIN)."""
+        import numpy as np
+        assert inbuf.dtype == np.uint8 and inbuf.flags.c_contiguous and inbuf.size == serve_in_bytes(kind, n)
+        assert outbuf.dtype == np.uint8 and outbuf.flags.c_contiguous and outbuf.size == serve_out_bytes(kind, n)
+        t = C.c_uint64(0)
+        rc = lib().gv_server_submit(self._h, kind, precision, n, C.c_void_p(inbuf.ctypes.data),
+                                    C.c_void_p(outbuf.ctypes.data), C.byref(t))
+        if rc == GV_EAGAIN:
+            return None
+        _check("gv_server_submit", rc)
+        self._keep[t.value] = outbuf
+        return t.value
+
+    def poll(self, max_n=1024):
+        """[(ticket, device completion time)] of baskets finished since the last poll."""
+        tk = (C.c_uint64 * max_n)()
+        td = (C.c_double * max_n)()
+        cnt = C.c_int32(0)
+        _check("gv_server_poll", lib().gv_server_poll(self._h, max_n, tk, td, C.byref(cnt)))
+        out = [(tk[i], td[i]) for i in range(cnt.value)]
+        for t, _ in out:
+            self._keep.pop(t, None)
+        return out
+
+    def drain(self):
+        _check("gv_server_drain", lib().gv_server_drain(self._h))
+
+    def stats(self):
+        v = (C.c_int64 * 8)()
+        _check("gv_server_stats", lib().gv_server_stats(self._h, v))
+        keys = ("admitted", "waiting", "rounds", "baskets", "tracks", "max_round", "in_bytes", "out_bytes")
+        return dict(zip(keys, list(v)))
+
+    def close(self):
+        if self._h:
+            rc = lib().gv_server_destroy(self._h)
+            self._h = None
+            _check("gv_server_destroy", rc)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -51,7 +51,8 @@ struct gv_geom {
   int* idx[2] = {nullptr, nullptr};  // bucketed slot lists
   TCtl ctl{};
   int* nxt_lv = nullptr;    // [cap] next LV per list entry
-  int* h_live = nullptr;  // pinned host copies of the live count
+  int* h_live = nullptr;  // [2] pinned, mapped host copies of the live count
+  int* d_live = nullptr;  // device address of h_live
   hipEvent_t ev[2] = {nullptr, nullptr};
   // kernel timing for measurement (gv_profile)
   bool prof = false;
@@ -309,6 +310,55 @@ extern "C" int geom_load(const void* blob, size_t nbytes, gv_geom** out) {
         dau_box[6 * (size_t)k + 3 + i] = bhi[i] + pad;
       }
     }
+    // FP32 screen tables.  S of an LV bounds |coordinate| of its solid's points;
+    // the FP32 boxes are widened by 128 u (S(mother) + |box|inf), u = 2^-24,
+    // and rounded outward, so the FP32 slab test never drops a box the FP64 one
+    // keeps for a point with |p|inf <= S (error budget in gv_step.h).
+    const double u32 = std::ldexp(1.0, -24);
+    auto down32 = [](double v) {
+      float f = (float)v;
+      return (double)f > v ? std::nextafter(f, -HUGE_VALF) : f;
+    };
+    auto up32 = [](double v) {
+      float f = (float)v;
+      return (double)f < v ? std::nextafter(f, HUGE_VALF) : f;
+    };
+    std::vector<float> lv_scr(n_lv);
+    std::vector<double> lv_ext(n_lv);
+    for (int i = 0; i < n_lv; ++i) {
+      double lo[3], hi[3];
+      local_extent(lv_type[i], par.data() + lv_par[i], lo, hi);
+      double e = 0;
+      for (int a = 0; a < 3; ++a) e = std::max(e, std::max(std::fabs(lo[a]), std::fabs(hi[a])));
+      lv_ext[i] = e;
+      lv_scr[i] = up32(e + 1.0);
+    }
+    std::vector<float> dau_box32((size_t)n_place * 8, 0.0f), dau_scr32((size_t)n_place * 16, 0.0f);
+    for (int i = 0; i < n_lv; ++i) {
+      for (int k = lv_doff[i]; k < lv_doff[i] + lv_dcnt[i]; ++k) {
+        const double* B = &dau_box[6 * (size_t)k];
+        double bmax = 0;
+        for (int a = 0; a < 6; ++a) bmax = std::max(bmax, std::fabs(B[a]));
+        const double delta = 128.0 * u32 * ((double)lv_scr[i] + bmax);
+        for (int a = 0; a < 3; ++a) {
+          dau_box32[8 * (size_t)k + a] = down32(B[a] - delta);
+          dau_box32[8 * (size_t)k + 3 + a] = up32(B[3 + a] + delta);
+        }
+        const double* X = &dau_xf[12 * (size_t)k];
+        float* Y = &dau_scr32[16 * (size_t)k];
+        double tmax = 0;
+        for (int j = 0; j < 12; ++j) Y[j] = (float)X[j];
+        for (int j = 9; j < 12; ++j) tmax = std::max(tmax, std::fabs(X[j]));
+        const int clv = dau_lv[k];
+        const double* q = par.data() + lv_par[clv];
+        if (lv_type[clv] == kBox) {
+          Y[12] = (float)q[0], Y[13] = (float)q[1], Y[14] = (float)q[2];
+        } else if (lv_type[clv] == kTubs) {
+          Y[12] = (float)q[L::TB_RMIN], Y[13] = (float)q[L::TB_RMAX], Y[14] = (float)q[L::TB_DZ];
+        }
+        Y[15] = up32(tmax + lv_ext[clv] + 1.0);
+      }
+    }
     // count the tree first (depth and size limits also reject cycles)
     std::vector<long> subtree(n_lv, -1);
     std::vector<int> state(n_lv, 0), height(n_lv, 0);
@@ -390,7 +440,8 @@ extern "C" int geom_load(const void* blob, size_t nbytes, gv_geom** out) {
         {T.pv_parent.data(), T.pv_parent.size() * 4, 0}, {T.pv_gxf.data(), T.pv_gxf.size() * 8, 0},
         {T.pv_child_off.data(), T.pv_child_off.size() * 4, 0}, {T.pv_child.data(), T.pv_child.size() * 4, 0},
         {lv_dtype.data(), lv_dtype.size() * 4, 0}, {dau_par.data(), dau_par.size() * 4, 0},
-        {dau_box.data(), dau_box.size() * 8, 0}};
+        {dau_box.data(), dau_box.size() * 8, 0},   {lv_scr.data(), lv_scr.size() * 4, 0},
+        {dau_box32.data(), dau_box32.size() * 4, 0}, {dau_scr32.data(), dau_scr32.size() * 4, 0}};
     size_t total = 0;
     for (auto& p : parts) {
       p.off = total;
@@ -437,6 +488,9 @@ extern "C" int geom_load(const void* blob, size_t nbytes, gv_geom** out) {
     D.lv_dau_type = (CQI)(base + parts[12].off);
     D.dau_par = (CQI)(base + parts[13].off);
     D.dau_box = (CQ)(base + parts[14].off);
+    D.lv_scr = (CQF)(base + parts[15].off);
+    D.dau_box32 = (CQF)(base + parts[16].off);
+    D.dau_scr32 = (CQF)(base + parts[17].off);
     g->n_lv = n_lv;
     g->n_pv = (int)npv;
     g->n_place = n_place;
@@ -548,6 +602,14 @@ int launched(const char* fn) {
     case kTrd: CALL(Trd); break;    \
     default: CALL(Pcon); break;     \
   }
+
+// Navigation entry points take GV_FP64 or GV_FP32_REFINE (FP32 daughter
+// screens, FP64 values: the same outputs).
+int check_nav_precision(const char* fn, int32_t precision) {
+  if (precision != GV_FP64 && precision != GV_FP32_REFINE)
+    return fail(GV_EINVAL, "%s: precision %d is neither GV_FP64 nor GV_FP32_REFINE", fn, precision);
+  return GV_OK;
+}
 
 extern "C" int basket_inside(gv_geom* g, int32_t lv, int64_t n, const double* x, const double* y, const double* z,
                              int8_t* out, void* stream) {
@@ -671,7 +733,7 @@ extern "C" int basket_step(gv_geom* g, int64_t n, const double* x, const double*
                            int32_t precision, void* stream) {
   const char* fn = "basket_step";
   GV_TRY(check_common(fn, g, n));
-  if (precision != GV_FP64) return fail(GV_EINVAL, "%s: precision %d not supported yet", fn, precision);
+  GV_TRY(check_nav_precision(fn, precision));
   if (n == 0) return GV_OK;
   const double* in[6] = {x, y, z, dx, dy, dz};
   const char* nm[6] = {"x", "y", "z", "dx", "dy", "dz"};
@@ -682,8 +744,8 @@ extern "C" int basket_step(gv_geom* g, int64_t n, const double* x, const double*
   GV_TRY(check_i32(fn, "out_next_pv", out_next_pv));
   GV_TRY(check_i32(fn, "out_flags", out_flags, true));
   DeviceGuard dgd(g->device);
-  hipLaunchKernelGGL(k_step, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, g->dg, n, x, y, z, dx, dy, dz,
-                     pv, pstep, out_step, out_next_pv, out_flags);
+  hipLaunchKernelGGL(precision == GV_FP64 ? k_step : k_step_scr, dim3(grid_for(n)), dim3(kBlock), 0,
+                     (hipStream_t)stream, g->dg, n, x, y, z, dx, dy, dz, pv, pstep, out_step, out_next_pv, out_flags);
   return launched(fn);
 }
 
@@ -691,7 +753,7 @@ extern "C" int basket_nav_safety(gv_geom* g, int64_t n, const double* x, const d
                                  const int32_t* pv, double* out, int32_t precision, void* stream) {
   const char* fn = "basket_nav_safety";
   GV_TRY(check_common(fn, g, n));
-  if (precision != GV_FP64) return fail(GV_EINVAL, "%s: precision %d not supported", fn, precision);
+  GV_TRY(check_nav_precision(fn, precision));
   if (n == 0) return GV_OK;
   GV_TRY(check_f64(fn, "x", x));
   GV_TRY(check_f64(fn, "y", y));
@@ -699,8 +761,8 @@ extern "C" int basket_nav_safety(gv_geom* g, int64_t n, const double* x, const d
   GV_TRY(check_i32(fn, "pv", pv));
   GV_TRY(check_f64(fn, "out", out));
   DeviceGuard dgd(g->device);
-  hipLaunchKernelGGL(k_nav_safety, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, g->dg, n, x, y, z, pv,
-                     out);
+  hipLaunchKernelGGL(precision == GV_FP64 ? k_nav_safety : k_nav_safety_scr, dim3(grid_for(n)), dim3(kBlock), 0,
+                     (hipStream_t)stream, g->dg, n, x, y, z, pv, out);
   return launched(fn);
 }
 
@@ -733,7 +795,7 @@ int ensure_workspace(gv_geom* g, int64_t n) {
   int64_t cap = n < 4096 ? 4096 : n;
   int nl = g->n_lv;
   size_t total = al256(sizeof(TRec) * (size_t)cap) + 3 * al256(4 * (size_t)cap) + 6 * al256(4 * (size_t)nl) +
-                 al256(4) + al256(8 * kWorkN);
+                 al256(8 * kWorkN);
   if (g->ws) {
     (void)hipDeviceSynchronize();
     (void)hipFree(g->ws);
@@ -762,11 +824,12 @@ int ensure_workspace(gv_geom* g, int64_t n) {
     g->ctl.cnt[s] = (int*)take(4 * nl);
     g->ctl.cur[s] = (int*)take(4 * nl);
   }
-  g->ctl.live = (int*)take(4);
   g->ctl.work = (unsigned long long*)take(8 * kWorkN);
   if (!g->h_live) {
-    e = hipHostMalloc((void**)&g->h_live, 2 * sizeof(int), hipHostMallocDefault);
+    e = hipHostMalloc((void**)&g->h_live, 2 * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent);
     if (e != hipSuccess) return hip_fail(e, "nav_transport: hipHostMalloc");
+    e = hipHostGetDevicePointer((void**)&g->d_live, g->h_live, 0);
+    if (e != hipSuccess) return hip_fail(e, "nav_transport: hipHostGetDevicePointer");
     for (int i = 0; i < 2; ++i) {
       e = hipEventCreateWithFlags(&g->ev[i], hipEventDisableTiming);
       if (e != hipSuccess) return hip_fail(e, "nav_transport: hipEventCreate");
@@ -787,7 +850,7 @@ unsigned stream_grid(int64_t n) {
 
 int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, const double* z, const double* dx,
                      const double* dy, const double* dz, const int32_t* start_pv, int max_steps, int32_t* out_pv,
-                     double* out_step, int32_t* out_nsteps, uint32_t* out_flags, hipStream_t s) {
+                     double* out_step, int32_t* out_nsteps, uint32_t* out_flags, bool fp32, hipStream_t s) {
   const char* fn = "nav_transport";
   GV_TRY(ensure_workspace(g, n));
   const int nl = g->n_lv;
@@ -801,13 +864,15 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
                      out_pv, out_nsteps, out_flags, g->rec, g->nxt_lv, C);
   GV_TRY(launched(fn));
   hipLaunchKernelGGL(k_bt_reindex, dim3(rg), dim3(1024), lds_ix, s, (const int*)nullptr, (const int*)nullptr, n,
-                     (const int*)g->nxt_lv, g->idx[0], (const int*)C.cnt[0], C.cur[0], C.cnt[1], C.cur[1], C.live, nl);
+                     (const int*)g->nxt_lv, g->idx[0], (const int*)C.cnt[0], C.cur[0], C.cnt[1], C.cur[1],
+                     (int*)nullptr, nl);
   GV_TRY(launched(fn));
   const int64_t max_tiles = n / kWave + nl + 1;
   const unsigned step_grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((max_tiles + 3) / 4, 1024));
-  // The host enqueues steps in chunks; once the live count read back after an
-  // earlier chunk is zero, the remaining steps are not enqueued.  Two chunks
-  // stay in flight, so the device never waits for this check.
+  // The host enqueues steps in chunks; once the live count that the index
+  // kernel at the end of an earlier chunk stored into pinned host memory is
+  // zero, the remaining steps are not enqueued.  Two chunks stay in flight, so
+  // the device never waits for this check.
   constexpr int kChunk = 8;
   int chunk = 0;
   for (int k = 0; k < max_steps; ++k) {
@@ -825,27 +890,26 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
       g->prof_used += 2;
       (void)hipEventRecord(pe[0], s);
     }
-    hipLaunchKernelGGL(k_bt_step, dim3(step_grid), dim3(kBlock), lds_step, s, g->dg, k, max_steps,
-                       (const int*)g->idx[c], g->rec, (const int*)C.cnt[k0], g->nxt_lv, C.cnt[k1], C, out_pv,
-                       out_step, out_nsteps, out_flags);
+    hipLaunchKernelGGL(fp32 ? k_bt_step<true> : k_bt_step<false>, dim3(step_grid), dim3(kBlock), lds_step, s, g->dg,
+                       k, max_steps, (const int*)g->idx[c], g->rec, (const int*)C.cnt[k0], g->nxt_lv, C.cnt[k1], C,
+                       out_pv, out_step, out_nsteps, out_flags);
     GV_TRY(launched(fn));
     if (pe) (void)hipEventRecord(pe[1], s);
     if (k + 1 == max_steps) break;
+    const bool report = (k + 1) % kChunk == 0;
+    const int slot = chunk & 1;
+    if (report && chunk >= 2) {
+      // the count stored two chunks ago: wait for its kernel, then look
+      hipError_t e = hipEventSynchronize(g->ev[slot]);
+      if (e != hipSuccess) return hip_fail(e, "nav_transport: hipEventSynchronize");
+      if (((volatile int*)g->h_live)[slot] == 0) break;
+    }
     hipLaunchKernelGGL(k_bt_reindex, dim3(rg), dim3(1024), lds_ix, s, (const int*)g->idx[c], (const int*)C.cnt[k0],
                        (int64_t)0, (const int*)g->nxt_lv, g->idx[c ^ 1], (const int*)C.cnt[k1], C.cur[k1], C.cnt[k2],
-                       C.cur[k2], C.live, nl);
+                       C.cur[k2], report ? g->d_live + slot : (int*)nullptr, nl);
     GV_TRY(launched(fn));
-    if ((k + 1) % kChunk == 0) {
-      int slot = chunk & 1;
-      if (chunk >= 2) {
-        // the copy issued two chunks ago: wait for it, then look
-        hipError_t e = hipEventSynchronize(g->ev[slot]);
-        if (e != hipSuccess) return hip_fail(e, "nav_transport: hipEventSynchronize");
-        if (g->h_live[slot] == 0) break;
-      }
-      hipError_t e = hipMemcpyAsync(&g->h_live[slot], g->ctl.live, sizeof(int), hipMemcpyDeviceToHost, s);
-      if (e != hipSuccess) return hip_fail(e, "nav_transport: hipMemcpyAsync");
-      e = hipEventRecord(g->ev[slot], s);
+    if (report) {
+      hipError_t e = hipEventRecord(g->ev[slot], s);
       if (e != hipSuccess) return hip_fail(e, "nav_transport: hipEventRecord");
       ++chunk;
     }
@@ -861,7 +925,7 @@ extern "C" int nav_transport(gv_geom* g, int64_t n, const double* x, const doubl
                              uint32_t* out_flags, int32_t precision, void* stream) {
   const char* fn = "nav_transport";
   GV_TRY(check_common(fn, g, n));
-  if (precision != GV_FP64) return fail(GV_EINVAL, "%s: precision %d not supported yet", fn, precision);
+  GV_TRY(check_nav_precision(fn, precision));
   if (max_steps < 1 || max_steps > 4096) return fail(GV_EINVAL, "%s: max_steps %d not in [1, 4096]", fn, max_steps);
   if (n == 0) return GV_OK;
   const double* in[6] = {x, y, z, dx, dy, dz};
@@ -875,9 +939,10 @@ extern "C" int nav_transport(gv_geom* g, int64_t n, const double* x, const doubl
   DeviceGuard dgd(g->device);
   if (n >= kBasketMin && n <= (1L << 30) && g->n_lv <= 4096)
     return basket_transport(g, n, x, y, z, dx, dy, dz, start_pv, max_steps, out_pv, out_step, out_nsteps, out_flags,
-                            (hipStream_t)stream);
-  hipLaunchKernelGGL(k_transport_lane, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, g->dg, n, x, y, z,
-                     dx, dy, dz, start_pv, (int)max_steps, out_pv, out_step, out_nsteps, out_flags);
+                            precision == GV_FP32_REFINE, (hipStream_t)stream);
+  hipLaunchKernelGGL(precision == GV_FP64 ? k_transport_lane : k_transport_lane_scr, dim3(grid_for(n)), dim3(kBlock),
+                     0, (hipStream_t)stream, g->dg, n, x, y, z, dx, dy, dz, start_pv, (int)max_steps, out_pv,
+                     out_step, out_nsteps, out_flags);
   return launched(fn);
 }
 
@@ -889,7 +954,7 @@ extern "C" int gv_profile(gv_geom* g, int enable) {
 }
 
 extern "C" int gv_profile_read(gv_geom* g, double* step_ms, int64_t* step_launches, uint64_t* work) {
-  static_assert(kWorkN == 20, "gvgeom.h documents 20 work counters");
+  static_assert(kWorkN == 22, "gvgeom.h documents 22 work counters");
   if (!g) return fail(GV_EINVAL, "gv_profile_read: geometry handle is NULL");
   DeviceGuard dgd(g->device);
   double ms = 0.0;
@@ -915,3 +980,6 @@ extern "C" int gv_profile_read(gv_geom* g, double* step_ms, int64_t* step_launch
   }
   return GV_OK;
 }
+
+// ------------------------------------------------------------------ serving
+#include "gv_serve.h"

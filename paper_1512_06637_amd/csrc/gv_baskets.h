@@ -15,7 +15,7 @@
 // contiguous).  Per track and step that moves 12 bytes of indices instead of
 // the 64-byte state.
 #pragma once
-#include "gv_kernels.h"
+#include "gv_step.h"
 
 namespace gv {
 
@@ -27,11 +27,6 @@ struct alignas(64) TRec {
   int pv, zr, fl, pad;
 };
 
-// Work counters of one transport: steps, daughter bounding-box tests, then per
-// daughter solid type the lower-bound checks, the full DistanceToIn
-// evaluations of culled loops, and those of plain loops (6 types each).
-enum { kWorkSteps = 0, kWorkBox = 1, kWorkBound = 2, kWorkFull = 8, kWorkPlain = 14, kWorkN = 20 };
-
 __device__ __forceinline__ uint64_t lanemask_lt() { return __lanemask_lt(); }
 
 // Per-step control arrays.  Counts and cursors are triple-buffered: step k
@@ -41,7 +36,6 @@ __device__ __forceinline__ uint64_t lanemask_lt() { return __lanemask_lt(); }
 struct TCtl {
   int* cnt[3];    // [nlv] tracks per LV in list k % 3
   int* cur[3];    // [nlv] index-scatter cursors of list k % 3
-  int* live;      // live tracks in the newest list (read back by the host)
   unsigned long long* work;  // [kWorkN] operation counts of the current call
 };
 
@@ -176,7 +170,8 @@ __device__ __forceinline__ int wave_lds_reserve(int v, bool on, int* cnt) {
 // them per destination LV in LDS, reserves one contiguous range per LV with a
 // single global atomic, then writes them in a second pass.  Workgroup 0 also
 // publishes the live count and clears counts and cursors of list k+2.  Needs
-// 16 * nlv + 8 bytes of dynamic LDS.
+// 16 * nlv + 8 bytes of dynamic LDS.  `live` (nullable; device memory or
+// mapped pinned host memory) receives the number of entries of list k+1.
 __global__ void __launch_bounds__(1024) k_bt_reindex(const int* __restrict__ src_idx, const int* __restrict__ cnt_src,
                                                       int64_t nsrc_fixed, const int* __restrict__ nxt_lv,
                                                       int* __restrict__ dst_idx, const int* __restrict__ cnt_dst,
@@ -200,7 +195,7 @@ __global__ void __launch_bounds__(1024) k_bt_reindex(const int* __restrict__ src
     nsrc = total;
   }
   if (blockIdx.x == 0) {
-    if (threadIdx.x == 0) *live = start[nlv];
+    if (threadIdx.x == 0 && live) __hip_atomic_store(live, start[nlv], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     for (int b = threadIdx.x; b < nlv; b += blockDim.x) {
       cnt_clear[b] = 0;
       cur_clear[b] = 0;
@@ -231,171 +226,7 @@ __global__ void __launch_bounds__(1024) k_bt_reindex(const int* __restrict__ src
 }
 
 // ---------------------------------------------------------------- step
-// Daughter loop of one ComputeStep with the LV wavefront-uniform: transforms
-// and solid parameters come from scalar loads.  An LV whose daughters share one
-// solid type runs that solid's code only.
-struct Placement {
-  double R[12];
-  int par;
-};
-
-__device__ __forceinline__ Placement load_placement(const DevGeom& G, int k) {
-  Placement P;
-  CQ Y = G.dau_xf + 12 * (size_t)k;
-#pragma unroll
-  for (int j = 0; j < 12; ++j) P.R[j] = Y[j];
-  P.par = G.dau_par[k];
-  return P;
-}
-
-template <class S>
-__device__ __forceinline__ void daughters_of_type(const DevGeom& G, int off, int cnt, V3 pl, V3 dl, double& best,
-                                                  int& bestk, bool& neg) {
-  // the next placement is fetched while the current one is evaluated
-  Placement cur = load_placement(G, off);
-  for (int k = 0; k < cnt; ++k) {
-    Placement nxt = load_placement(G, off + (k + 1 < cnt ? k + 1 : k));
-    const double* R = cur.R;
-    V3 pc, dc;
-    {
-      double q0 = pl.x - R[9], q1 = pl.y - R[10], q2 = pl.z - R[11];
-      pc = V3{R[0] * q0 + R[3] * q1 + R[6] * q2, R[1] * q0 + R[4] * q1 + R[7] * q2, R[2] * q0 + R[5] * q1 + R[8] * q2};
-      dc = V3{R[0] * dl.x + R[3] * dl.y + R[6] * dl.z, R[1] * dl.x + R[4] * dl.y + R[7] * dl.z,
-              R[2] * dl.x + R[5] * dl.y + R[8] * dl.z};
-    }
-    double t = S::dist_in(G.par + cur.par, pc, dc);
-    neg = neg || t < 0.0;
-    t = fmax(t, 0.0);
-    if (t < best) {
-      best = t;
-      bestk = k;
-    }
-    cur = nxt;
-  }
-}
-
-// Lower bound of a child's DistanceToIn: its isotropic SafetyToIn (each
-// solid's formula is a lower bound of the true distance); <= 0 when inside.
-template <class S>
-__device__ __forceinline__ double lower_bound(CQ q, V3 pc) {
-  return S::safety_in(q, pc);
-}
-
-// Work counting: the first active lane adds the number of active lanes (times
-// `mult`) to a per-workgroup LDS counter, so a count stays exact inside
-// divergent loops.
-struct Work {
-  unsigned long long* c;  // [kWorkN] in LDS
-};
-__device__ __forceinline__ void count_active(unsigned long long* ctr, unsigned mult = 1) {
-  uint64_t m = __ballot(1);
-  if ((int)__lane_id() == __ffsll((unsigned long long)m) - 1)
-    atomicAdd(ctr, (unsigned long long)__popcll(m) * mult);
-}
-
-// Culled daughter loop.  A daughter can only win if its DistanceToIn is at most
-// the mother's DistanceToOut and below the best daughter found so far, and its
-// DistanceToIn is never below its padded bounding box's entry distance nor
-// below its SafetyToIn.  Pass 1 tests every daughter's bounding box against
-// each lane's ray with wavefront-uniform data and collects per-lane candidate
-// masks; pass 2 lets each lane walk its own candidates in index order, checks
-// the SafetyToIn bound, and evaluates DistanceToIn only where it can still win.
-// The selected daughter is the one the full loop would select.
-template <class S>
-__device__ __forceinline__ void daughters_culled(const DevGeom& G, int off, int cnt, V3 pl, V3 dl, double dout,
-                                                 double& best, int& bestk, bool& neg, Work& w) {
-  const V3 inv{rcp_fast(dl.x), rcp_fast(dl.y), rcp_fast(dl.z)};
-  const V3 pin{-pl.x * inv.x, -pl.y * inv.y, -pl.z * inv.z};
-  const double bound = dout + kTol;
-  for (int c0 = 0; c0 < cnt; c0 += 64) {
-    const int m = min(64, cnt - c0);
-    uint64_t cand = 0;
-    for (int k = 0; k < m; ++k) {
-      CQ B = G.dau_box + 6 * (size_t)(off + c0 + k);
-      double ax = fma(B[0], inv.x, pin.x), bx = fma(B[3], inv.x, pin.x);
-      double ay = fma(B[1], inv.y, pin.y), by = fma(B[4], inv.y, pin.y);
-      double az = fma(B[2], inv.z, pin.z), bz = fma(B[5], inv.z, pin.z);
-      double nr = fmax(fmax(fmin(ax, bx), fmin(ay, by)), fmin(az, bz));
-      double fr = fmin(fmin(fmax(ax, bx), fmax(ay, by)), fmax(az, bz));
-      // NaN-safe: an undecidable comparison keeps the daughter
-      bool out = nr > fr || fr < 0.0 || nr > bound;
-      cand |= out ? 0ull : (1ull << k);
-    }
-    count_active(&w.c[kWorkBox], (unsigned)m);
-    while (cand) {
-      const int k = __builtin_ctzll(cand);
-      cand &= cand - 1;
-      const int pk = off + c0 + k;
-      CQ Y = G.dau_xf + 12 * (size_t)pk;
-      CQ q = G.par + G.dau_par[pk];
-      V3 pc = to_child_p(Y, pl);
-      count_active(&w.c[kWorkBound + S::kType]);
-      if (lower_bound<S>(q, pc) > fmin(best, dout) + kTol) continue;
-      count_active(&w.c[kWorkFull + S::kType]);
-      V3 dc = to_child_d(Y, dl);
-      double t = S::dist_in(q, pc, dc);
-      neg = neg || t < 0.0;
-      t = fmax(t, 0.0);
-      if (t < best) {
-        best = t;
-        bestk = c0 + k;
-      }
-    }
-  }
-}
-
-constexpr int kCullMin = 8;  // LVs with fewer daughters run the plain loop
-
-__device__ __forceinline__ double step_uniform_lv(const DevGeom& G, int lv, int pv, V3 p, V3 d, int* next,
-                                                  uint32_t* flags, Work& w) {
-  CQ X = G.pv_gxf + 12 * (size_t)pv;
-  V3 pl = to_child_p(X, p), dl = to_child_d(X, d);
-  double dout = solid_dist_out(G.lv_type[lv], G.par + G.lv_par[lv], pl, dl);
-  uint32_t fl = *flags;
-  if (dout < 0.0) {
-    dout = 0.0;
-    fl |= kFlagLocateFail;
-  }
-  double best = GV_INF;
-  int bestk = -1;
-  const int off = G.lv_dau_off[lv], cnt = G.lv_dau_cnt[lv], dtype = G.lv_dau_type[lv];
-  bool neg = false;
-  if (dtype == kBox && cnt >= kCullMin) {
-    daughters_culled<Box>(G, off, cnt, pl, dl, dout, best, bestk, neg, w);
-  } else if (dtype == kTubs && cnt >= kCullMin) {
-    daughters_culled<Tubs>(G, off, cnt, pl, dl, dout, best, bestk, neg, w);
-  } else if (dtype == kBox) {
-    daughters_of_type<Box>(G, off, cnt, pl, dl, best, bestk, neg);
-    count_active(&w.c[kWorkPlain + kBox], (unsigned)cnt);
-  } else if (dtype == kTubs) {
-    daughters_of_type<Tubs>(G, off, cnt, pl, dl, best, bestk, neg);
-    count_active(&w.c[kWorkPlain + kTubs], (unsigned)cnt);
-  } else {
-    for (int k = 0; k < cnt; ++k) {
-      CQ Y = G.dau_xf + 12 * (size_t)(off + k);
-      const int clv = G.dau_lv[off + k];
-      V3 pc = to_child_p(Y, pl), dc = to_child_d(Y, dl);
-      const int ct = G.lv_type[clv];
-      double t = solid_dist_in(ct, G.par + G.lv_par[clv], pc, dc);
-      count_active(&w.c[kWorkPlain + ct]);
-      neg = neg || t < 0.0;
-      t = fmax(t, 0.0);
-      if (t < best) {
-        best = t;
-        bestk = k;
-      }
-    }
-  }
-  if (neg) fl |= kFlagLocateFail;
-  *flags = fl;
-  if (bestk >= 0 && best <= dout) {
-    *next = G.pv_child[G.pv_child_off[pv] + bestk];
-    return best;
-  }
-  *next = G.pv_parent[pv];
-  return dout;
-}
-
+template <bool F32>
 __global__ void __launch_bounds__(256) k_bt_step(DevGeom G, int k, int max_steps, const int* __restrict__ idx,
                                                   TRec* __restrict__ rec, const int* __restrict__ cnt_cur,
                                                   int* __restrict__ nxt_lv, int* __restrict__ cnt_next, TCtl C,
@@ -411,7 +242,7 @@ __global__ void __launch_bounds__(256) k_bt_step(DevGeom G, int k, int max_steps
   for (int v = threadIdx.x; v < nlv; v += blockDim.x) hist[v] = 0;
   for (int i = threadIdx.x; i < kWorkN; i += blockDim.x) wsum[i] = 0;
   block_layout(cnt_cur, nlv, start, tilep);
-  Work w{wsum};
+  LdsWork w{wsum};
   const int tiles = tilep[nlv];
   const int lane = __lane_id();
   const int wave = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave);
@@ -436,7 +267,7 @@ __global__ void __launch_bounds__(256) k_bt_step(DevGeom G, int k, int max_steps
       V3 p{r.x, r.y, r.z}, d{r.dx, r.dy, r.dz};
       uint32_t fl = (uint32_t)r.fl;
       int nx;
-      double st = step_uniform_lv(G, b, r.pv, p, d, &nx, &fl, w);
+      double st = step_culled<F32>(G, b, r.pv, p, d, &nx, &fl, w);
       p = advance(p, st, d);
       out_step[(size_t)id * max_steps + k] = st;
       out_pv[(size_t)id * (max_steps + 1) + k + 1] = nx;

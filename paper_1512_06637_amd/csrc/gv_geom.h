@@ -27,6 +27,10 @@ struct DevGeom {
   CQ pv_gxf;         // [n_pv][12] composed world <- PV transform
   CQI pv_child_off;  // [n_pv] children of a PV follow their LV's placement order
   CQI pv_child;      // [n_pv]
+  // FP32 screen tables (daughter culling in FP32 with FP64 refinement)
+  CQF lv_scr;        // [n_lv] S: max |coordinate| of a point of the LV's solid + 1 mm
+  CQF dau_box32;     // [n_place][8] dau_box widened by 128 u (S(mother) + |box|inf), rounded outward; 2 unused
+  CQF dau_scr32;     // [n_place][16] R (9), t (3), child a b c (box: dx dy dz; tube: rmin rmax dz), e
 };
 
 __device__ __forceinline__ V3 ld3(const double* x, const double* y, const double* z, int64_t i) {

@@ -54,6 +54,7 @@ struct V3 {
 // address an ordinary vector load.
 typedef const __attribute__((address_space(4))) double* CQ;
 typedef const __attribute__((address_space(4))) int* CQI;
+typedef const __attribute__((address_space(4))) float* CQF;
 
 // 1/d from the hardware reciprocal plus one Newton step: within a few ulp
 // (11 ulp worst over 2^22 random operands), i.e. 3e-15 relative, three orders

@@ -1,0 +1,414 @@
+// ComputeStep with culled daughter loops (Sec. III.A step selection).  The
+// plain step takes the minimum of DistanceToIn over every daughter; the forms
+// here reach the same daughter, the same length and the same flags with fewer
+// full evaluations, by discarding daughters that provably cannot win.  Two
+// screens do the discarding: a padded bounding-box slab test and the child's
+// SafetyToIn, each a lower bound of the child's DistanceToIn.  Every distance
+// that decides the step is computed in FP64.
+//
+// Precision FP32 + FP64 refinement runs both screens in FP32 on FP32 copies
+// of the tables, with error margins that keep them conservative, and refines
+// the surviving daughters in FP64: its outputs equal the FP64 form's bit for
+// bit.  A wavefront whose rays fall outside the range the FP32 margins were
+// sized for runs the FP64 screens for that step instead.
+#pragma once
+#include "gv_kernels.h"
+
+namespace gv {
+
+// Work counters: steps, daughter bounding-box tests, then per daughter solid
+// type the lower-bound checks, the full DistanceToIn evaluations of culled
+// loops and those of plain loops (6 types each), then the track-steps of culled
+// loops whose screens ran in FP32 and those that fell back to FP64 screens.
+enum {
+  kWorkSteps = 0,
+  kWorkBox = 1,
+  kWorkBound = 2,
+  kWorkFull = 8,
+  kWorkPlain = 14,
+  kWorkScr32 = 20,
+  kWorkScr64 = 21,
+  kWorkN = 22
+};
+
+// Exact counting inside divergent code: the first active lane adds the number
+// of active lanes (times `mult`) to an LDS counter of the workgroup.
+__device__ __forceinline__ void count_active(unsigned long long* ctr, unsigned mult = 1) {
+  uint64_t m = __ballot(1);
+  if ((int)__lane_id() == __ffsll((unsigned long long)m) - 1) atomicAdd(ctr, (unsigned long long)__popcll(m) * mult);
+}
+struct LdsWork {
+  unsigned long long* c;  // [kWorkN] in LDS
+  __device__ __forceinline__ void add(int i, unsigned mult = 1) { count_active(&c[i], mult); }
+};
+struct NoWork {
+  __device__ __forceinline__ void add(int, unsigned = 1) {}
+};
+
+// ----------------------------------------------------------- plain loop
+struct Placement {
+  double R[12];
+  int par;
+};
+
+__device__ __forceinline__ Placement load_placement(const DevGeom& G, int k) {
+  Placement P;
+  CQ Y = G.dau_xf + 12 * (size_t)k;
+#pragma unroll
+  for (int j = 0; j < 12; ++j) P.R[j] = Y[j];
+  P.par = G.dau_par[k];
+  return P;
+}
+
+template <class S>
+__device__ __forceinline__ void daughters_of_type(const DevGeom& G, int off, int cnt, V3 pl, V3 dl, double& best,
+                                                  int& bestk, bool& neg) {
+  // the next placement is fetched while the current one is evaluated
+  Placement cur = load_placement(G, off);
+  for (int k = 0; k < cnt; ++k) {
+    Placement nxt = load_placement(G, off + (k + 1 < cnt ? k + 1 : k));
+    const double* R = cur.R;
+    V3 pc, dc;
+    {
+      double q0 = pl.x - R[9], q1 = pl.y - R[10], q2 = pl.z - R[11];
+      pc = V3{R[0] * q0 + R[3] * q1 + R[6] * q2, R[1] * q0 + R[4] * q1 + R[7] * q2, R[2] * q0 + R[5] * q1 + R[8] * q2};
+      dc = V3{R[0] * dl.x + R[3] * dl.y + R[6] * dl.z, R[1] * dl.x + R[4] * dl.y + R[7] * dl.z,
+              R[2] * dl.x + R[5] * dl.y + R[8] * dl.z};
+    }
+    double t = S::dist_in(G.par + cur.par, pc, dc);
+    neg = neg || t < 0.0;
+    t = fmax(t, 0.0);
+    if (t < best) {
+      best = t;
+      bestk = k;
+    }
+    cur = nxt;
+  }
+}
+
+// ------------------------------------------------------------- screens
+constexpr float kU32 = 5.9604645e-08f;  // 2^-24, unit roundoff of FP32
+
+struct F3 {
+  float x, y, z;
+};
+__device__ __forceinline__ float max3f(float a, float b, float c) { return fmaxf(fmaxf(a, b), c); }
+
+// Per lane: which of daughters off+c0 .. off+c0+m-1 may be entered at a ray
+// parameter in [0, bound].  A daughter is dropped only when the ray provably
+// misses its padded box or meets it beyond the bound.  Undecidable (NaN)
+// comparisons keep the daughter.
+__device__ __forceinline__ uint64_t box_screen64(const DevGeom& G, int base, int m, V3 inv, V3 pin, double bound) {
+  uint64_t cand = 0;
+  for (int k = 0; k < m; ++k) {
+    CQ B = G.dau_box + 6 * (size_t)(base + k);
+    double ax = fma(B[0], inv.x, pin.x), bx = fma(B[3], inv.x, pin.x);
+    double ay = fma(B[1], inv.y, pin.y), by = fma(B[4], inv.y, pin.y);
+    double az = fma(B[2], inv.z, pin.z), bz = fma(B[5], inv.z, pin.z);
+    double nr = fmax(fmax(fmin(ax, bx), fmin(ay, by)), fmin(az, bz));
+    double fr = fmin(fmin(fmax(ax, bx), fmax(ay, by)), fmax(az, bz));
+    bool out = nr > fr || fr < 0.0 || nr > bound;
+    cand |= out ? 0ull : (1ull << k);
+  }
+  return cand;
+}
+
+// The same test in FP32.  The FP32 boxes are the FP64 ones widened by
+// delta = 128 u (S + |box|inf), S of the mother, u = 2^-24, which covers the
+// rounding of the point, of the direction over a parameter up to 4 S and of
+// the slab arithmetic's absolute part, for every point with |p|inf <= S.  The parameters'
+// remaining relative error (a few u) is covered by moving the entry down and
+// the exit up by 8 u of their size before comparing.
+__device__ __forceinline__ uint64_t box_screen32(const DevGeom& G, int base, int m, F3 inv, F3 pin, float bound) {
+  uint64_t cand = 0;
+  const float r = 8.0f * kU32;
+  for (int k = 0; k < m; ++k) {
+    CQF B = G.dau_box32 + 8 * (size_t)(base + k);
+    float ax = fmaf(B[0], inv.x, pin.x), bx = fmaf(B[3], inv.x, pin.x);
+    float ay = fmaf(B[1], inv.y, pin.y), by = fmaf(B[4], inv.y, pin.y);
+    float az = fmaf(B[2], inv.z, pin.z), bz = fmaf(B[5], inv.z, pin.z);
+    float nr = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fminf(az, bz));
+    float fr = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fmaxf(az, bz));
+    nr = fmaf(-r, fabsf(nr), nr);
+    fr = fmaf(r, fabsf(fr), fr);
+    bool out = nr > fr || fr < 0.0f || nr > bound;
+    cand |= out ? 0ull : (1ull << k);
+  }
+  return cand;
+}
+
+// FP32 lower bound of a box or tube child's SafetyToIn minus its error bound:
+// max(|x|-dx, |y|-dy, |z|-dz) for a box, max(r-rmax, rmin-r, |z|-dz) for a tube
+// (a subset of the terms of the FP64 formula, so never above it).  The point
+// goes through R and t in FP32; the error of the result stays below
+// 64 u (|p|inf + e), e = |t|inf + child extent + 1 mm.
+template <class S>
+__device__ __forceinline__ float lower_bound32(CQF Y, F3 p, float pmax) {
+  const float q0 = p.x - Y[9], q1 = p.y - Y[10], q2 = p.z - Y[11];
+  const float x = Y[0] * q0 + Y[3] * q1 + Y[6] * q2;
+  const float y = Y[1] * q0 + Y[4] * q1 + Y[7] * q2;
+  const float z = Y[2] * q0 + Y[5] * q1 + Y[8] * q2;
+  float lb;
+  if (S::kType == kBox) {
+    lb = max3f(fabsf(x) - Y[12], fabsf(y) - Y[13], fabsf(z) - Y[14]);
+  } else {
+    const float rr = sqrtf(x * x + y * y);
+    lb = max3f(rr - Y[13], Y[12] - rr, fabsf(z) - Y[14]);
+  }
+  return lb - 64.0f * kU32 * (pmax + Y[15]);
+}
+
+// ---------------------------------------------------------- culled loop
+// A daughter can only win if its DistanceToIn is at most the mother's
+// DistanceToOut (+ kTolerance, the daughter wins ties) and below the best
+// daughter found so far, and its DistanceToIn is never below its padded
+// bounding box's entry distance nor below its SafetyToIn.  Pass 1 tests every
+// daughter's box against each lane's ray (table reads are uniform when the LV
+// is) and collects per-lane candidate masks; pass 2 lets each lane walk its own
+// candidates in index order, checks the SafetyToIn bound, and evaluates
+// DistanceToIn only where it can still win.  Walking in index order with a
+// strict < keeps the lowest index among equal minima, as the plain loop does.
+template <class S, bool F32, class W>
+__device__ __forceinline__ void daughters_culled(const DevGeom& G, int lv, int off, int cnt, V3 pl, V3 dl,
+                                                 double dout, double& best, int& bestk, bool& neg, W& w) {
+  const double bound = dout + kTol;
+  bool use32 = false;
+  F3 p32{}, inv32{}, pin32{};
+  float pmax = 0.0f, bound32 = 0.0f;
+  if (F32) {
+    p32 = F3{(float)pl.x, (float)pl.y, (float)pl.z};
+    pmax = max3f(fabsf(p32.x), fabsf(p32.y), fabsf(p32.z));
+    const float sl = G.lv_scr[lv];
+    const bool safe = pmax <= sl && bound <= 4.0 * (double)sl;
+    use32 = __ballot(!safe) == 0;  // over the active lanes: all must be in range
+    w.add(use32 ? kWorkScr32 : kWorkScr64, 1);
+    if (use32) {
+      inv32 = F3{__builtin_amdgcn_rcpf((float)dl.x), __builtin_amdgcn_rcpf((float)dl.y),
+                 __builtin_amdgcn_rcpf((float)dl.z)};
+      pin32 = F3{-p32.x * inv32.x, -p32.y * inv32.y, -p32.z * inv32.z};
+      bound32 = (float)bound;
+      bound32 = fmaf(4.0f * kU32, bound32, bound32);
+    }
+  }
+  V3 inv{}, pin{};
+  if (!use32) {
+    inv = V3{rcp_fast(dl.x), rcp_fast(dl.y), rcp_fast(dl.z)};
+    pin = V3{-pl.x * inv.x, -pl.y * inv.y, -pl.z * inv.z};
+  }
+  for (int c0 = 0; c0 < cnt; c0 += 64) {
+    const int m = min(64, cnt - c0);
+    uint64_t cand = use32 ? box_screen32(G, off + c0, m, inv32, pin32, bound32)
+                          : box_screen64(G, off + c0, m, inv, pin, bound);
+    w.add(kWorkBox, (unsigned)m);
+    while (cand) {
+      const int k = __builtin_ctzll(cand);
+      cand &= cand - 1;
+      const int pk = off + c0 + k;
+      CQ Y = G.dau_xf + 12 * (size_t)pk;
+      CQ q = G.par + G.dau_par[pk];
+      const double thr = fmin(best, dout) + kTol;
+      w.add(kWorkBound + S::kType);
+      V3 pc;
+      if (use32) {
+        const float lb = lower_bound32<S>(G.dau_scr32 + 16 * (size_t)pk, p32, pmax);
+        const float t32 = (float)thr;
+        if (lb > fmaf(4.0f * kU32, t32, t32)) continue;
+        pc = to_child_p(Y, pl);
+      } else {
+        pc = to_child_p(Y, pl);
+        if (S::safety_in(q, pc) > thr) continue;
+      }
+      w.add(kWorkFull + S::kType);
+      const V3 dc = to_child_d(Y, dl);
+      double t = S::dist_in(q, pc, dc);
+      neg = neg || t < 0.0;
+      t = fmax(t, 0.0);
+      if (t < best) {
+        best = t;
+        bestk = c0 + k;
+      }
+    }
+  }
+}
+
+constexpr int kCullMin = 8;  // LVs with fewer daughters run the plain loop
+
+// One ComputeStep of a track in placed volume pv (logical volume lv) with no
+// physics limit.  Valid for any lv; fastest when lv is wavefront-uniform.
+template <bool F32, class W>
+__device__ __forceinline__ double step_culled(const DevGeom& G, int lv, int pv, V3 p, V3 d, int* next,
+                                              uint32_t* flags, W& w) {
+  CQ X = G.pv_gxf + 12 * (size_t)pv;
+  V3 pl = to_child_p(X, p), dl = to_child_d(X, d);
+  double dout = solid_dist_out(G.lv_type[lv], G.par + G.lv_par[lv], pl, dl);
+  uint32_t fl = *flags;
+  if (dout < 0.0) {
+    dout = 0.0;
+    fl |= kFlagLocateFail;
+  }
+  double best = GV_INF;
+  int bestk = -1;
+  const int off = G.lv_dau_off[lv], cnt = G.lv_dau_cnt[lv], dtype = G.lv_dau_type[lv];
+  bool neg = false;
+  if (dtype == kBox && cnt >= kCullMin) {
+    daughters_culled<Box, F32>(G, lv, off, cnt, pl, dl, dout, best, bestk, neg, w);
+  } else if (dtype == kTubs && cnt >= kCullMin) {
+    daughters_culled<Tubs, F32>(G, lv, off, cnt, pl, dl, dout, best, bestk, neg, w);
+  } else if (dtype == kBox) {
+    daughters_of_type<Box>(G, off, cnt, pl, dl, best, bestk, neg);
+    w.add(kWorkPlain + kBox, (unsigned)cnt);
+  } else if (dtype == kTubs) {
+    daughters_of_type<Tubs>(G, off, cnt, pl, dl, best, bestk, neg);
+    w.add(kWorkPlain + kTubs, (unsigned)cnt);
+  } else {
+    for (int k = 0; k < cnt; ++k) {
+      CQ Y = G.dau_xf + 12 * (size_t)(off + k);
+      const int clv = G.dau_lv[off + k];
+      V3 pc = to_child_p(Y, pl), dc = to_child_d(Y, dl);
+      const int ct = G.lv_type[clv];
+      double t = solid_dist_in(ct, G.par + G.lv_par[clv], pc, dc);
+      w.add(kWorkPlain + ct);
+      neg = neg || t < 0.0;
+      t = fmax(t, 0.0);
+      if (t < best) {
+        best = t;
+        bestk = k;
+      }
+    }
+  }
+  if (neg) fl |= kFlagLocateFail;
+  *flags = fl;
+  if (bestk >= 0 && best <= dout) {
+    *next = G.pv_child[G.pv_child_off[pv] + bestk];
+    return best;
+  }
+  *next = G.pv_parent[pv];
+  return dout;
+}
+
+// ComputeStep with a physics limit: as step_culled, then the physics length
+// wins when it is below both the daughter minimum and the exit.
+template <bool F32, class W>
+__device__ __forceinline__ double step_culled_limited(const DevGeom& G, int pv, V3 p, V3 d, double pstep, int* next,
+                                                      uint32_t* flags, W& w) {
+  int nx;
+  const double s = step_culled<F32>(G, G.pv_lv[pv], pv, p, d, &nx, flags, w);
+  // s is the daughter minimum when a daughter was chosen, else the exit
+  if (pstep < s) {
+    *next = pv;
+    return pstep;
+  }
+  *next = nx;
+  return s;
+}
+
+// NavSafety with the FP32 SafetyToIn screen: a box or tube daughter is skipped
+// when its FP32 lower bound (minus its error) exceeds both the running minimum
+// and the surface half-band by kTolerance, i.e. when the point is provably
+// outside it and it cannot lower the minimum.  Equal to nav_safety bit for bit.
+__device__ __forceinline__ double nav_safety_screened(const DevGeom& G, int pv, V3 p) {
+  const int lv = G.pv_lv[pv];
+  const V3 pl = to_child_p(G.pv_gxf + 12 * (size_t)pv, p);
+  const int t = G.lv_type[lv];
+  CQ q = G.par + G.lv_par[lv];
+  if (code_of(solid_sgn(t, q, pl)) != kInside) return 0.0;
+  double s = solid_safety_out(t, q, pl);
+  const int off = G.lv_dau_off[lv], cnt = G.lv_dau_cnt[lv], dtype = G.lv_dau_type[lv];
+  const F3 p32{(float)pl.x, (float)pl.y, (float)pl.z};
+  const float pmax = max3f(fabsf(p32.x), fabsf(p32.y), fabsf(p32.z));
+  const bool scr = dtype == kBox || dtype == kTubs;
+  for (int k = 0; k < cnt; ++k) {
+    if (scr) {
+      CQF Y = G.dau_scr32 + 16 * (size_t)(off + k);
+      const float lb = dtype == kBox ? lower_bound32<Box>(Y, p32, pmax) : lower_bound32<Tubs>(Y, p32, pmax);
+      // kTolerance above the FP64 values keeps their own rounding from mattering
+      const float t32 = (float)(fmax(s, kHalf) + kTol);
+      if (lb > fmaf(4.0f * kU32, t32, t32)) continue;
+    }
+    const int clv = G.dau_lv[off + k];
+    const V3 pc = to_child_p(G.dau_xf + 12 * (size_t)(off + k), pl);
+    CQ qc = G.par + G.lv_par[clv];
+    const int tc = G.lv_type[clv];
+    if (code_of(solid_sgn(tc, qc, pc)) != kOutside) return 0.0;
+    s = fmin(s, solid_safety_in(tc, qc, pc));
+  }
+  return fmax(s, 0.0);
+}
+
+// ------------------------------------------------- per-lane kernels (FP32 screen)
+__global__ void k_step_scr(DevGeom G, int64_t n, const double* __restrict__ x, const double* __restrict__ y,
+                           const double* __restrict__ z, const double* __restrict__ dx, const double* __restrict__ dy,
+                           const double* __restrict__ dz, const int32_t* __restrict__ pv,
+                           const double* __restrict__ pstep, double* __restrict__ out_step,
+                           int32_t* __restrict__ out_next, uint32_t* __restrict__ out_flags) {
+  NoWork w;
+  for (int64_t i = gtid(); i < n; i += gstride()) {
+    int v = pv[i];
+    uint32_t fl = 0;
+    int nx = -1;
+    double st = 0.0;
+    if (v >= 0 && v < G.n_pv) {
+      st = step_culled_limited<true>(G, v, ld3(x, y, z, i), ld3(dx, dy, dz, i), pstep ? pstep[i] : GV_INF, &nx, &fl,
+                                     w);
+    } else {
+      fl = kFlagLocateFail;
+    }
+    out_step[i] = st;
+    out_next[i] = nx;
+    if (out_flags) out_flags[i] = fl;
+  }
+}
+
+__global__ void k_nav_safety_scr(DevGeom G, int64_t n, const double* __restrict__ x, const double* __restrict__ y,
+                                 const double* __restrict__ z, const int32_t* __restrict__ pv,
+                                 double* __restrict__ out) {
+  for (int64_t i = gtid(); i < n; i += gstride()) {
+    int v = pv[i];
+    out[i] = (v >= 0 && v < G.n_pv) ? nav_safety_screened(G, v, ld3(x, y, z, i)) : 0.0;
+  }
+}
+
+// Whole-track transport, one lane per track, with the culled FP32-screened step.
+__global__ void k_transport_lane_scr(DevGeom G, int64_t n, const double* __restrict__ x,
+                                     const double* __restrict__ y, const double* __restrict__ z,
+                                     const double* __restrict__ dx, const double* __restrict__ dy,
+                                     const double* __restrict__ dz, const int32_t* __restrict__ start_pv,
+                                     int max_steps, int32_t* __restrict__ out_pv, double* __restrict__ out_step,
+                                     int32_t* __restrict__ out_nsteps, uint32_t* __restrict__ out_flags) {
+  NoWork w;
+  for (int64_t i = gtid(); i < n; i += gstride()) {
+    V3 p = ld3(x, y, z, i), d = ld3(dx, dy, dz, i);
+    uint32_t fl = 0;
+    int pv = start_pv ? start_pv[i] : locate(G, p);
+    if (pv < -1 || pv >= G.n_pv) {
+      pv = -1;
+      fl |= kFlagLocateFail;
+    }
+    int32_t* rp = out_pv + (size_t)i * (max_steps + 1);
+    double* rs = out_step + (size_t)i * max_steps;
+    rp[0] = pv;
+    int k = 0;
+    if (pv >= 0) {
+      int zero_run = 0, nx = pv;
+      while (k < max_steps) {
+        double st = step_culled<true>(G, G.pv_lv[pv], pv, p, d, &nx, &fl, w);
+        p = advance(p, st, d);
+        rs[k] = st;
+        rp[k + 1] = nx;
+        ++k;
+        if (nx < 0) break;
+        zero_run = st < kTol ? zero_run + 1 : 0;
+        if (zero_run >= 8) {
+          fl |= kFlagStuck;
+          break;
+        }
+        pv = nx;
+      }
+      if (k == max_steps && nx >= 0 && !(fl & kFlagStuck)) fl |= kFlagOverflow;
+    }
+    out_nsteps[i] = k;
+    out_flags[i] = fl;
+  }
+}
+
+}  // namespace gv

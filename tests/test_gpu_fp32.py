@@ -1,0 +1,138 @@
+"""GPU parity of the FP32-screen + FP64-refine precision (GV_FP32_REFINE) on
+the layered detector.
+
+The FP32 form only decides which daughters need an FP64 evaluation, with
+margins that keep the decision conservative, so its outputs must equal the
+FP64 form's bit for bit (steps, next volumes, flags, safeties, whole volume
+sequences); both are also compared with the oracle under the FP64 bar."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1512_06637_amd import workloads as W
+from tests.gpu_util import compare_values, cuda, host, say
+from tests.test_gpu_nav import STEP_REL, compare_transport, states
+
+pytestmark = pytest.mark.gpu
+
+BLOB = W.detector_blob()
+
+
+@pytest.fixture(scope="module")
+def geos():
+    import paper_1512_06637_amd as G
+    g = G.Geometry(BLOB)
+    og = O.Geometry(BLOB)
+    yield g, og
+    g.close()
+    og.close()
+
+
+def _step_both(g, a, pv, **kw):
+    import torch
+    import paper_1512_06637_amd as G
+    out = []
+    for prec in (G.FP64, G.FP32_REFINE):
+        fl = torch.zeros(pv.shape[0], dtype=torch.int32, device="cuda")
+        st, nx = g.step(*a, cuda(pv), out_flags=fl, precision=prec, **kw)
+        out.append((host(st), host(nx), host(fl)))
+    return out
+
+
+def test_step_and_safety_fp32(geos):
+    import paper_1512_06637_amd as G
+    g, og = geos
+    t, pv = states(og, 6000, 12)
+    a = [cuda(v) for v in t.arrays()]
+    (s64, n64, f64_), (s32, n32, f32_) = _step_both(g, a, pv)
+    assert np.array_equal(s64.view(np.int64), s32.view(np.int64))
+    assert np.array_equal(n64, n32) and np.array_equal(f64_, f32_)
+    rs, rn, rf, rd = og.step(t, pv)
+    ok = (rd & O.D_ILL) == 0
+    assert ok.mean() > 0.99
+    assert np.array_equal(n32[ok], rn[ok])
+    assert np.array_equal(f32_[ok], rf[ok].astype(np.int32))
+    assert np.all(np.abs(s32 - rs)[ok] <= STEP_REL * np.maximum(1, rs[ok]) + 1e-12)
+    # physics-limited
+    ps = np.random.default_rng(13).uniform(0, 200, t.n)
+    (s64, n64, _), (s32, n32, _) = _step_both(g, a, pv, pstep=cuda(ps))
+    assert np.array_equal(s64.view(np.int64), s32.view(np.int64)) and np.array_equal(n64, n32)
+    # safety
+    sf64 = host(g.nav_safety(*a[:3], cuda(pv), precision=G.FP64))
+    sf32 = host(g.nav_safety(*a[:3], cuda(pv), precision=G.FP32_REFINE))
+    assert np.array_equal(sf64.view(np.int64), sf32.view(np.int64))
+    _, _, bad = compare_values(sf32, og.nav_safety(t.x, t.y, t.z, pv), what="nav_safety fp32")
+    assert bad.size == 0
+
+
+def test_fp32_fallback_lanes(geos):
+    """Points outside the range the FP32 margins cover (here: outside their
+    volume, |p| beyond its extent) make their wavefront use the FP64 screens;
+    results still equal the FP64 form's, inconsistent states included."""
+    g, og = geos
+    t, pv = states(og, 3000, 14)
+    x, y, z = t.x.copy(), t.y.copy(), t.z.copy()
+    pv = pv.copy()
+    sel = np.arange(0, t.n, 5)
+    layer = 1 + 65 * (sel % 20)
+    x[sel], y[sel], z[sel] = 0.0, 0.0, 2900.0  # beyond the layers' half-length 2500
+    pv[sel] = layer
+    sel2 = np.arange(2, t.n, 11)
+    x[sel2] = 5000.0  # outside the world
+    pv[sel2] = 0
+    t2 = W.Tracks(x, y, z, t.dx, t.dy, t.dz)
+    a = [cuda(v) for v in t2.arrays()]
+    (s64, n64, f64_), (s32, n32, f32_) = _step_both(g, a, pv)
+    assert np.array_equal(s64.view(np.int64), s32.view(np.int64))
+    assert np.array_equal(n64, n32) and np.array_equal(f64_, f32_)
+    assert np.all(f32_[sel] & 4) and np.all(f32_[sel2] & 4)  # LOCATE_FAIL on the planted states
+
+
+def _same_transport(a, b):
+    ns = host(a["nsteps"])
+    assert np.array_equal(ns, host(b["nsteps"]))
+    assert np.array_equal(host(a["flags"]), host(b["flags"]))
+    k = np.arange(host(a["step"]).shape[1])[None, :]
+    m = k < ns[:, None]
+    mp = np.concatenate([np.ones((ns.shape[0], 1), bool), m], axis=1)
+    assert np.array_equal(host(a["pv"])[mp], host(b["pv"])[mp])
+    assert np.array_equal(host(a["step"])[m].view(np.int64), host(b["step"])[m].view(np.int64))
+
+
+@pytest.mark.parametrize("n", [4099, 20011])
+def test_transport_fp32_full_compare(geos, n):
+    import paper_1512_06637_amd as G
+    g, og = geos
+    t = W.config3_tracks(n)
+    say(f"[transport fp32] n={n}")
+    a = [cuda(v) for v in t.arrays()]
+    got32 = g.transport(*a, precision=G.FP32_REFINE)
+    got64 = g.transport(*a, precision=G.FP64)
+    _same_transport(got32, got64)
+    assert compare_transport(got32, og.transport(t)) > 0.99 * n
+
+
+def test_transport_fp32_full_size(geos):
+    """The benchmark's 2^20 tracks in both precisions: identical outputs; 2,000
+    sampled tracks against the oracle; the share of culled steps screened in
+    FP32 (the rest fell back to FP64 screens) is reported."""
+    import paper_1512_06637_amd as G
+    g, og = geos
+    t = W.config3_tracks()
+    say(f"[transport fp32] n={t.n}")
+    a = [cuda(v) for v in t.arrays()]
+    g.profile(True)
+    got32 = g.transport(*a, precision=G.FP32_REFINE)
+    _, _, w32 = g.profile_read()
+    got64 = g.transport(*a, precision=G.FP64)
+    _, _, w64 = g.profile_read()
+    g.profile(False)
+    _same_transport(got32, got64)
+    idx = np.sort(np.random.default_rng(15).choice(t.n, 2000, replace=False))
+    compare_transport(got32, og.transport(t.take(idx)), idx)
+    frac32 = w32[20] / max(1, w32[20] + w32[21])
+    say(f"  FP32-screened culled steps {w32[20]}, FP64 fallback {w32[21]} ({1 - frac32:.2e}); "
+        f"box tests {w32[1]} vs {w64[1]}, DistanceToIn {sum(w32[8:14])} vs {sum(w64[8:14])}")
+    assert w64[20] == 0 and w64[21] > 0
+    assert frac32 > 0.99
+    assert w32[0] == w64[0] == int(host(got32["nsteps"]).sum())
