@@ -51,6 +51,146 @@ def cpu_baseline(blob, tracks, target_s=12.0, max_s=30.0):
             "sample": f"first {done_tracks} of the 2^20 tracks ({done_steps} track-steps, {spent:.1f} s)"}
 
 
+# Algorithmic HBM bytes per track of the solid-level queries: inputs read
+# (3 or 6 doubles) and outputs written (int8 code, doubles).
+SOLID_BYTES = {"inside": 24 + 1, "safety": 24 + 8, "dist_in": 48 + 8, "dist_out": 48 + 8, "fused": 48 + 25}
+HBM_PEAK_GBS = 8000.0
+
+
+def graph_ms(fn, calls, replays):
+    """Per-call device time of `fn(c)`, c = 0 .. calls-1, captured once into a
+    HIP graph and replayed: launch overhead of the host stays out."""
+    import torch
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for c in range(calls):
+            fn(c)
+    torch.cuda.current_stream().wait_stream(side)
+    gr = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gr):
+        for c in range(calls):
+            fn(c)
+    gr.replay()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(replays):
+        gr.replay()
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / (replays * calls)
+
+
+def solids_leg(copies=8, replays=10):
+    """The six solids, 2^20 tracks each (a third inside, a third outside, a third
+    within 1e-6 mm of the surface): every query separately and fused, cycling
+    over `copies` distinct input/output sets (384 MiB of inputs, beyond the
+    256 MB last-level cache) so the bytes come from HBM."""
+    import torch
+
+    import paper_1512_06637_amd as G
+    from paper_1512_06637_amd import workloads as W
+
+    names = W.CONFIG2_SOLIDS
+    sol = W.config_solids()
+    g = G.Geometry(W.multi_solid_blob([sol[k] for k in names]))
+    res = {}
+    for lv, name in enumerate(names):
+        t = W.config2_tracks(name)
+        n = t.n
+        base = [torch.from_numpy(v).to("cuda") for v in t.arrays()]
+        sets = [[v.clone() for v in base] for _ in range(copies)]
+        outs = [{"c": torch.empty(n, dtype=torch.int8, device="cuda"),
+                 "s": torch.empty(n, dtype=torch.float64, device="cuda"),
+                 "a": torch.empty(n, dtype=torch.float64, device="cuda"),
+                 "b": torch.empty(n, dtype=torch.float64, device="cuda")} for _ in range(copies)]
+        calls = {
+            "inside": lambda c: g.inside(lv, *sets[c][:3], out=outs[c]["c"]),
+            "safety": lambda c: g.safety(lv, *sets[c][:3], out=outs[c]["s"]),
+            "dist_in": lambda c: g.distance(lv, G.TO_IN, *sets[c], out=outs[c]["a"]),
+            "dist_out": lambda c: g.distance(lv, G.TO_OUT, *sets[c], out=outs[c]["b"]),
+            "fused": lambda c: g.solid_all(lv, *sets[c], outs[c]["c"], outs[c]["s"], outs[c]["a"], outs[c]["b"]),
+        }
+        r = {}
+        for q, f in calls.items():
+            ms = graph_ms(f, copies, replays)
+            gbs = n * SOLID_BYTES[q] / (ms * 1e-3) / 1e9
+            r[q] = {"us_per_call": ms * 1e3, "tracks_per_s": n / (ms * 1e-3), "GB_s": gbs,
+                    "frac_hbm": gbs / HBM_PEAK_GBS}
+        r["separate_vs_fused_time"] = sum(r[q]["us_per_call"] for q in ("inside", "safety", "dist_in", "dist_out")) \
+            / r["fused"]["us_per_call"]
+        res[name] = r
+        del sets, outs, base
+    g.close()
+    return res
+
+
+def protocol_leg(replays=50, calls=100):
+    """The paper's measurement protocol: DistanceToOut of points inside the box
+    and the tube segment, N = 2^4 .. 2^20, per-call time over 5,000 graph-replayed
+    calls."""
+    import torch
+
+    import paper_1512_06637_amd as G
+    from paper_1512_06637_amd import workloads as W
+
+    sol = W.config_solids()
+    g = G.Geometry(W.multi_solid_blob([sol["box"], sol["tubs"]]))
+    res = {}
+    for lv, name in enumerate(("box", "tubs")):
+        pts = []
+        full = W.config1_inside_points(name, 1 << 20)
+        for e in range(4, 21, 2):
+            n = 1 << e
+            a = [torch.from_numpy(v[:n].copy()).to("cuda") for v in full.arrays()]
+            out = torch.empty(n, dtype=torch.float64, device="cuda")
+            ms = graph_ms(lambda c: g.distance(lv, G.TO_OUT, *a, out=out), calls, max(1, replays // max(1, n >> 16)))
+            pts.append({"n": n, "us_per_call": ms * 1e3, "tracks_per_s": n / (ms * 1e-3)})
+        res[name] = pts
+    g.close()
+    return res
+
+
+def cpu_baseline_solids(protocol, max_s=1.0):
+    """The oracle on the same inputs: DistanceToIn / DistanceToOut of the full
+    solid set on 2^16-track samples, and the protocol sweep's DistanceToOut for
+    each N (repeated up to `max_s` seconds)."""
+    import oracle as O
+    from paper_1512_06637_amd import workloads as W
+
+    threads = O.default_threads()
+    sol = W.config_solids()
+    full = {}
+    for name in W.CONFIG2_SOLIDS:
+        t = W.config2_tracks(name).take(slice(0, 1 << 16))
+        r = {}
+        for q, d in (("dist_in", 0), ("dist_out", 1)):
+            t0 = time.perf_counter()
+            O.distance(sol[name], d, t, threads=threads)
+            r[q + "_tracks_per_s"] = t.n / (time.perf_counter() - t0)
+        full[name] = r
+    proto = {}
+    for name, pts in protocol.items():
+        allp = W.config1_inside_points(name, 1 << 20)
+        out = []
+        for p in pts:
+            t = allp.take(slice(0, p["n"]))
+            k, t0 = 0, time.perf_counter()
+            while True:
+                O.distance(sol[name], 1, t, threads=threads)
+                k += 1
+                el = time.perf_counter() - t0
+                if el > max_s or (k >= 3 and el > 0.05):
+                    break
+            cpu = k * p["n"] / el
+            out.append({"n": p["n"], "tracks_per_s": cpu, "gpu_speedup": p["tracks_per_s"] / cpu})
+        proto[name] = out
+    return {"kind": "oracle", "cores": threads, "solids_sample": "first 2^16 tracks of each solid's set",
+            "solids": full, "protocol": proto}
+
+
 def fp32_leg(g, a, ref, max_steps, args, ms64):
     """The same workload with precision FP32_REFINE (FP32 daughter screens, FP64
     distances): time per call, whether every output equals the FP64 run's, and
@@ -99,6 +239,9 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-screen + FP64-refine leg")
+    ap.add_argument("--no-solids", action="store_true", help="skip the solid-level legs")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first copy 256 MiB device to device (a kernel of known traffic for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -112,6 +255,12 @@ def main():
     from paper_1512_06637_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        src = torch.ones(1 << 25, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     blob = W.detector_blob()
     tracks = W.config3_tracks(args.n)
     g = G.Geometry(blob)
@@ -186,8 +335,14 @@ def main():
     if not args.no_fp32:
         res["fp32_refine"] = fp32_leg(g, a, out, max_steps, args, ms)
     g.close()
+    del out, a
+    if not args.no_solids:
+        res["solids"] = solids_leg()
+        res["protocol"] = protocol_leg()
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(blob, tracks)
+        if not args.no_solids:
+            res["cpu_baseline_solids"] = cpu_baseline_solids(res["protocol"])
     print(json.dumps(res), flush=True)
 
 

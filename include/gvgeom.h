@@ -219,8 +219,11 @@ int gv_server_create(gv_geom* g, int32_t slots, int64_t hbm_budget, int32_t nstr
  * GV_FP32_REFINE).  `in` (host, layout above) is copied into pinned staging
  * before the call returns; `out` (host, layout above) must stay valid until
  * gv_server_poll returns this basket's *ticket, and is written then.
- * GV_EAGAIN: all slots taken or no contiguous room in an arena now (nothing
- * admitted; poll and retry).  GV_EINVAL: the basket can never fit the budget. */
+ * GV_EAGAIN: all slots taken or no contiguous room in an arena (nothing
+ * admitted); slots and room come back only through gv_server_poll or
+ * gv_server_drain, so poll and retry.  GV_EINVAL: the basket can never fit the
+ * budget.  The basket is launched at once if a stream is idle (as last seen by
+ * a poll), else with the next round. */
 int gv_server_submit(gv_server* s, int32_t kind, int32_t precision, int64_t n, const void* in, void* out,
                      uint64_t* ticket);
 

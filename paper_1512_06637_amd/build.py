@@ -19,7 +19,7 @@ def hipcc() -> str:
 
 def build(verbose: bool = False) -> str:
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-           # packed FP32 ops stay off in device code (toolchain notes)
+           # no packed FP32 instructions in device code
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas",
            "-o", LIB + ".tmp"] + [os.path.join(CSRC, s) for s in SOURCES]

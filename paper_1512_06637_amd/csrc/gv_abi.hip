@@ -50,7 +50,7 @@ struct gv_geom {
   TRec* rec = nullptr;      // [cap] track records
   int* idx[2] = {nullptr, nullptr};  // bucketed slot lists
   TCtl ctl{};
-  int* nxt_lv = nullptr;    // [cap] next LV per list entry
+  int* nxt_lv = nullptr;    // [cap] next bucket per list entry (start bucket per track at the start)
   int* h_live = nullptr;  // [2] pinned, mapped host copies of the live count
   int* d_live = nullptr;  // device address of h_live
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -359,6 +359,35 @@ extern "C" int geom_load(const void* blob, size_t nbytes, gv_geom** out) {
         Y[15] = up32(tmax + lv_ext[clv] + 1.0);
       }
     }
+    // identity placements skip their transform; groups of 8 consecutive
+    // daughters get the union of their boxes (FP64 and FP32) for a first test
+    std::vector<int> dau_ident(n_place, 0), lv_grp(n_lv, -1);
+    std::vector<double> grp_box;
+    std::vector<float> grp_box32;
+    for (int k = 0; k < n_place; ++k) {
+      const double* X = &dau_xf[12 * (size_t)k];
+      const double I[12] = {1, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0};
+      bool id = true;
+      for (int j = 0; j < 12; ++j) id = id && X[j] == I[j];
+      dau_ident[k] = id ? 1 : 0;
+    }
+    for (int i = 0; i < n_lv; ++i) {
+      if (lv_dcnt[i] < kGroupMin) continue;
+      lv_grp[i] = (int)(grp_box.size() / 6);
+      for (int g0 = 0; g0 < lv_dcnt[i]; g0 += kGroup) {
+        double lo[3] = {HUGE_VAL, HUGE_VAL, HUGE_VAL}, hi[3] = {-HUGE_VAL, -HUGE_VAL, -HUGE_VAL};
+        float lo32[3] = {HUGE_VALF, HUGE_VALF, HUGE_VALF}, hi32[3] = {-HUGE_VALF, -HUGE_VALF, -HUGE_VALF};
+        for (int k = lv_doff[i] + g0; k < lv_doff[i] + std::min(lv_dcnt[i], g0 + kGroup); ++k)
+          for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], dau_box[6 * (size_t)k + a]);
+            hi[a] = std::max(hi[a], dau_box[6 * (size_t)k + 3 + a]);
+            lo32[a] = std::min(lo32[a], dau_box32[8 * (size_t)k + a]);
+            hi32[a] = std::max(hi32[a], dau_box32[8 * (size_t)k + 3 + a]);
+          }
+        grp_box.insert(grp_box.end(), {lo[0], lo[1], lo[2], hi[0], hi[1], hi[2]});
+        grp_box32.insert(grp_box32.end(), {lo32[0], lo32[1], lo32[2], hi32[0], hi32[1], hi32[2], 0.0f, 0.0f});
+      }
+    }
     // count the tree first (depth and size limits also reject cycles)
     std::vector<long> subtree(n_lv, -1);
     std::vector<int> state(n_lv, 0), height(n_lv, 0);
@@ -441,7 +470,9 @@ extern "C" int geom_load(const void* blob, size_t nbytes, gv_geom** out) {
         {T.pv_child_off.data(), T.pv_child_off.size() * 4, 0}, {T.pv_child.data(), T.pv_child.size() * 4, 0},
         {lv_dtype.data(), lv_dtype.size() * 4, 0}, {dau_par.data(), dau_par.size() * 4, 0},
         {dau_box.data(), dau_box.size() * 8, 0},   {lv_scr.data(), lv_scr.size() * 4, 0},
-        {dau_box32.data(), dau_box32.size() * 4, 0}, {dau_scr32.data(), dau_scr32.size() * 4, 0}};
+        {dau_box32.data(), dau_box32.size() * 4, 0}, {dau_scr32.data(), dau_scr32.size() * 4, 0},
+        {dau_ident.data(), dau_ident.size() * 4, 0}, {lv_grp.data(), lv_grp.size() * 4, 0},
+        {grp_box.data(), grp_box.size() * 8, 0},     {grp_box32.data(), grp_box32.size() * 4, 0}};
     size_t total = 0;
     for (auto& p : parts) {
       p.off = total;
@@ -491,6 +522,10 @@ extern "C" int geom_load(const void* blob, size_t nbytes, gv_geom** out) {
     D.lv_scr = (CQF)(base + parts[15].off);
     D.dau_box32 = (CQF)(base + parts[16].off);
     D.dau_scr32 = (CQF)(base + parts[17].off);
+    D.dau_ident = (CQI)(base + parts[18].off);
+    D.lv_grp = (CQI)(base + parts[19].off);
+    D.grp_box = (CQ)(base + parts[20].off);
+    D.grp_box32 = (CQF)(base + parts[21].off);
     g->n_lv = n_lv;
     g->n_pv = (int)npv;
     g->n_place = n_place;
@@ -787,13 +822,17 @@ namespace {
 
 size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// Bits of the coarse direction cell in a bucket key (LV << bits | cell): 16
+// cells while LVs x cells <= 4096, else 4 cells, else none.
+int coarse_bits(int n_lv) { return n_lv <= 256 ? 4 : n_lv <= 1024 ? 2 : 0; }
+
 // Track records, two bucketed index lists, the next-LV array, and per-LV
 // counters and layouts.  Allocated with hipMalloc on first use and kept in the
 // handle.
 int ensure_workspace(gv_geom* g, int64_t n) {
   if (g->ws && g->ws_tracks >= n) return GV_OK;
   int64_t cap = n < 4096 ? 4096 : n;
-  int nl = g->n_lv;
+  int nl = g->n_lv << coarse_bits(g->n_lv);
   size_t total = al256(sizeof(TRec) * (size_t)cap) + 3 * al256(4 * (size_t)cap) + 6 * al256(4 * (size_t)nl) +
                  al256(8 * kWorkN);
   if (g->ws) {
@@ -853,18 +892,19 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
                      double* out_step, int32_t* out_nsteps, uint32_t* out_flags, bool fp32, hipStream_t s) {
   const char* fn = "nav_transport";
   GV_TRY(ensure_workspace(g, n));
-  const int nl = g->n_lv;
+  const int cb = coarse_bits(g->n_lv);
+  const int nl = g->n_lv << cb;  // buckets: (LV, coarse direction cell)
   const unsigned sg = stream_grid(n);
-  const size_t lds_ix = 16 * (size_t)nl + 8, lds_step = 12 * (size_t)nl + 8;
+  const size_t lds_ix = 12 * (size_t)nl + 4, lds_step = 12 * (size_t)nl + 8;
   const unsigned rg = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 4095) / 4096, 256));
   TCtl& C = g->ctl;
   hipLaunchKernelGGL(k_bt_clear, dim3(1), dim3(kBlock), 0, s, C, nl);
   GV_TRY(launched(fn));
-  hipLaunchKernelGGL(k_bt_init, dim3(sg), dim3(kBlock), 0, s, g->dg, n, x, y, z, dx, dy, dz, start_pv, max_steps,
-                     out_pv, out_nsteps, out_flags, g->rec, g->nxt_lv, C);
+  hipLaunchKernelGGL(k_bt_init, dim3(sg), dim3(kBlock), 4 * (size_t)nl, s, g->dg, n, x, y, z, dx, dy, dz, start_pv, max_steps,
+                     out_pv, out_nsteps, out_flags, g->rec, g->nxt_lv, cb, C);
   GV_TRY(launched(fn));
-  hipLaunchKernelGGL(k_bt_reindex, dim3(rg), dim3(1024), lds_ix, s, (const int*)nullptr, (const int*)nullptr, n,
-                     (const int*)g->nxt_lv, g->idx[0], (const int*)C.cnt[0], C.cur[0], C.cnt[1], C.cur[1],
+  hipLaunchKernelGGL(k_bt_reindex, dim3(rg), dim3(1024), lds_ix, s, (const int*)nullptr, (const int*)nullptr, 0, n,
+                     (const int*)g->nxt_lv, 0, g->idx[0], (const int*)C.cnt[0], C.cur[0], C.cnt[1], C.cur[1],
                      (int*)nullptr, nl);
   GV_TRY(launched(fn));
   const int64_t max_tiles = n / kWave + nl + 1;
@@ -891,7 +931,7 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
       (void)hipEventRecord(pe[0], s);
     }
     hipLaunchKernelGGL(fp32 ? k_bt_step<true> : k_bt_step<false>, dim3(step_grid), dim3(kBlock), lds_step, s, g->dg,
-                       k, max_steps, (const int*)g->idx[c], g->rec, (const int*)C.cnt[k0], g->nxt_lv, C.cnt[k1], C,
+                       k, max_steps, cb, (const int*)g->idx[c], g->rec, (const int*)C.cnt[k0], g->nxt_lv, C.cnt[k1], C,
                        out_pv, out_step, out_nsteps, out_flags);
     GV_TRY(launched(fn));
     if (pe) (void)hipEventRecord(pe[1], s);
@@ -905,8 +945,8 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
       if (((volatile int*)g->h_live)[slot] == 0) break;
     }
     hipLaunchKernelGGL(k_bt_reindex, dim3(rg), dim3(1024), lds_ix, s, (const int*)g->idx[c], (const int*)C.cnt[k0],
-                       (int64_t)0, (const int*)g->nxt_lv, g->idx[c ^ 1], (const int*)C.cnt[k1], C.cur[k1], C.cnt[k2],
-                       C.cur[k2], report ? g->d_live + slot : (int*)nullptr, nl);
+                       nl, (int64_t)0, (const int*)g->nxt_lv, 0, g->idx[c ^ 1], (const int*)C.cnt[k1], C.cur[k1],
+                       C.cnt[k2], C.cur[k2], report ? g->d_live + slot : (int*)nullptr, nl);
     GV_TRY(launched(fn));
     if (report) {
       hipError_t e = hipEventRecord(g->ev[slot], s);

@@ -3,14 +3,17 @@
 // volume are collected and processed together, Sec. II.A item 1 and Sec. III.C).
 //
 // Track states stay in place (one 64-byte record per track, slot = track id);
-// what is regrouped is a list of slot indices with one contiguous bucket per LV.
-// A wavefront takes a tile of 64 consecutive list entries of one bucket, so its
-// LV -- the mother solid and the whole daughter table -- is wavefront-uniform:
-// the daughter loop reads transforms and solid parameters with scalar loads into
-// SGPRs and the lanes never diverge on the solid type.  After the step each
-// wavefront adds its tracks to the per-LV counts of the next step; a
-// one-workgroup kernel turns the counts into the next bucket layout, and an
-// index-scatter kernel writes each live slot index into its new bucket
+// what is regrouped is a list of slot indices with one contiguous bucket per
+// (LV, coarse direction cell).  A wavefront takes a tile of 64 consecutive list
+// entries of one bucket, so its LV -- the mother solid and the whole daughter
+// table -- is wavefront-uniform: the daughter loop reads transforms and solid
+// parameters with scalar loads into SGPRs and the lanes never diverge on the
+// solid type.  The direction cell keeps a tile's rays within one cone of
+// directions, so they tend to meet the same daughters (the group screen of the
+// culled loop then skips most daughters for the whole wavefront).  After the
+// step each workgroup adds its tracks to the bucket counts of the next step;
+// the next step's workgroups each turn those counts into the bucket layout,
+// and an index kernel writes each live slot index into its new bucket
 // (workgroup-aggregated atomics keep one workgroup's writes to a bucket
 // contiguous).  Per track and step that moves 12 bytes of indices instead of
 // the 64-byte state.
@@ -21,11 +24,14 @@ namespace gv {
 
 constexpr int kWave = 64;
 
-// one 64-byte record per track
+// One 64-byte record per track (one cache line), read and rewritten whole
+// every step.
 struct alignas(64) TRec {
   double x, y, z, dx, dy, dz;
-  int pv, zr, fl, pad;
+  int pv, zr, fl;
+  int cc;  // coarse direction cell (fixed along the straight track)
 };
+static_assert(sizeof(TRec) == 64, "record layout");
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return __lanemask_lt(); }
 
@@ -54,8 +60,9 @@ __device__ __forceinline__ void wave_count(int v, bool on, int* cnt) {
 // Bucket layout of a list from its per-LV counts, computed by the first
 // wavefront of the workgroup into LDS: start[b] (exclusive prefix, start[nlv] =
 // total) and tile[b] (exclusive prefix of ceil(count/64), tile[nlv] = number
-// of tiles).  Chunks of 64 LVs, a shuffle scan per chunk.  All threads of the
-// workgroup must call it (it ends with a barrier); any block size works.
+// of tiles; tile may be NULL).  Chunks of 64 LVs, a shuffle scan per chunk.
+// All threads of the workgroup must call it (it ends with a barrier); any block
+// size works.
 __device__ void block_layout(const int* __restrict__ cnt, int nlv, int* start, int* tile) {
   if (threadIdx.x < kWave) {
     const int lane = threadIdx.x;
@@ -75,14 +82,14 @@ __device__ void block_layout(const int* __restrict__ cnt, int nlv, int* start, i
       }
       if (b < nlv) {
         start[b] = carry + s - c;
-        tile[b] = tcarry + ts - tc;
+        if (tile) tile[b] = tcarry + ts - tc;
       }
       carry += __shfl(s, kWave - 1);
       tcarry += __shfl(ts, kWave - 1);
     }
     if (lane == 0) {
       start[nlv] = carry;
-      tile[nlv] = tcarry;
+      if (tile) tile[nlv] = tcarry;
     }
   }
   __syncthreads();
@@ -100,23 +107,47 @@ __global__ void k_bt_clear(TCtl C, int nlv) {
 }
 
 // ---------------------------------------------------------------- init
+// Coarse direction cell of a unit direction: the octahedral map onto
+// [-1, 1]^2 cut into 2^(cb/2) x 2^(cb/2) cells (cb even, <= 4).  Tracks of one
+// bucket then share a cone of directions.
+__device__ __forceinline__ int dir_cell(double dx, double dy, double dz, int cb) {
+  const double a = fabs(dx) + fabs(dy) + fabs(dz);
+  double u = dx / a, v = dy / a;
+  if (dz < 0.0) {
+    const double uu = (1.0 - fabs(v)) * (u < 0.0 ? -1.0 : 1.0), vv = (1.0 - fabs(u)) * (v < 0.0 ? -1.0 : 1.0);
+    u = uu;
+    v = vv;
+  }
+  const int side = 1 << (cb / 2), m = side - 1;
+  const int iu = min(m, max(0, (int)((u + 1.0) * (0.5 * side))));
+  const int iv = min(m, max(0, (int)((v + 1.0) * (0.5 * side))));
+  return iv * side + iu;
+}
+
 // Start volume of every track (given or located), entry 0 of its sequence, its
-// record, and the counts of the first layout.  Tracks that start outside the
-// world finish here with zero steps.  List position = track id.
+// record, and its start bucket (LV, coarse direction cell) into key with the
+// bucket counts of the first list (per-workgroup LDS histogram, 4 nb bytes of
+// dynamic LDS).  Tracks that start outside the world finish here with zero steps
+// and get bucket -1.
 __global__ void k_bt_init(DevGeom G, int64_t n, const double* __restrict__ x, const double* __restrict__ y,
                           const double* __restrict__ z, const double* __restrict__ dx, const double* __restrict__ dy,
                           const double* __restrict__ dz, const int32_t* __restrict__ start_pv, int max_steps,
                           int32_t* __restrict__ out_pv, int32_t* __restrict__ out_nsteps,
-                          uint32_t* __restrict__ out_flags, TRec* __restrict__ rec, int* __restrict__ nxt_lv, TCtl C) {
+                          uint32_t* __restrict__ out_flags, TRec* __restrict__ rec, int* __restrict__ key, int cb,
+                          TCtl C) {
+  extern __shared__ int hist[];
+  const int nb = G.n_lv << cb;
+  for (int v = threadIdx.x; v < nb; v += blockDim.x) hist[v] = 0;
+  __syncthreads();
   int64_t stride = gstride();
   int64_t nround = ((n + stride - 1) / stride) * stride;
   for (int64_t i = gtid(); i < nround; i += stride) {
     bool act = i < n;
-    int v = -1, lv = -1;
+    int bk = -1;
     if (act) {
       uint32_t fl = 0;
       V3 p = ld3(x, y, z, i);
-      v = start_pv ? start_pv[i] : locate(G, p);
+      int v = start_pv ? start_pv[i] : locate(G, p);
       if (v < -1 || v >= G.n_pv) {
         v = -1;
         fl = kFlagLocateFail;
@@ -126,7 +157,6 @@ __global__ void k_bt_init(DevGeom G, int64_t n, const double* __restrict__ x, co
         out_nsteps[i] = 0;
         out_flags[i] = fl;
       } else {
-        lv = G.pv_lv[v];
         TRec r;
         r.x = p.x;
         r.y = p.y;
@@ -137,13 +167,17 @@ __global__ void k_bt_init(DevGeom G, int64_t n, const double* __restrict__ x, co
         r.pv = v;
         r.zr = 0;
         r.fl = 0;
-        r.pad = 0;
+        r.cc = dir_cell(r.dx, r.dy, r.dz, cb);
         rec[i] = r;
+        bk = G.pv_lv[v] << cb | r.cc;
       }
-      nxt_lv[i] = lv;
+      key[i] = bk;
     }
-    wave_count(lv >= 0 ? lv : 0, lv >= 0, C.cnt[0]);
+    wave_count(bk >= 0 ? bk : 0, bk >= 0, hist);
   }
+  __syncthreads();
+  for (int v = threadIdx.x; v < nb; v += blockDim.x)
+    if (hist[v]) atomicAdd(&C.cnt[0][v], hist[v]);
 }
 
 // wavefront-aggregated reservation in an LDS counter array: returns, for lanes
@@ -164,78 +198,89 @@ __device__ __forceinline__ int wave_lds_reserve(int v, bool on, int* cnt) {
   return pos;
 }
 
-// Writes the slot index of every live entry of list k (positions [0, total of
-// counts k), or [0, n) with identity slots for the first list) into its bucket
-// of list k+1.  Each workgroup owns one contiguous range of entries: it counts
-// them per destination LV in LDS, reserves one contiguous range per LV with a
-// single global atomic, then writes them in a second pass.  Workgroup 0 also
-// publishes the live count and clears counts and cursors of list k+2.  Needs
-// 16 * nlv + 8 bytes of dynamic LDS.  `live` (nullable; device memory or
-// mapped pinned host memory) receives the number of entries of list k+1.
+// Writes the slot index of every live entry of a list into its bucket of the
+// next list.  The source is list k (positions [0, sum of cnt_src[0..nsrc_bins)),
+// slots src_idx) or, with cnt_src NULL, positions [0, nsrc_fixed) with slots
+// src_idx (identity if NULL).  The destination bucket of position j is key[j],
+// or key[slot] with `gather`; negative keys are dropped.  Each workgroup owns
+// one contiguous range of positions: it counts them per bucket in LDS, reserves
+// one contiguous range per bucket with a single global atomic, then writes them
+// in a second pass, so a workgroup's entries keep their order in each bucket.
+// Workgroup 0 clears cnt_clear/cur_clear (nullable) and stores the number of
+// entries of the new list into `live` (nullable; device memory or mapped pinned
+// host memory).  Needs 12 * nb + 4 bytes of dynamic LDS.
 __global__ void __launch_bounds__(1024) k_bt_reindex(const int* __restrict__ src_idx, const int* __restrict__ cnt_src,
-                                                      int64_t nsrc_fixed, const int* __restrict__ nxt_lv,
-                                                      int* __restrict__ dst_idx, const int* __restrict__ cnt_dst,
-                                                      int* __restrict__ cur_dst, int* __restrict__ cnt_clear,
-                                                      int* __restrict__ cur_clear, int* __restrict__ live, int nlv) {
+                                                      int nsrc_bins, int64_t nsrc_fixed, const int* __restrict__ key,
+                                                      int gather, int* __restrict__ dst_idx,
+                                                      const int* __restrict__ cnt_dst, int* __restrict__ cur_dst,
+                                                      int* __restrict__ cnt_clear, int* __restrict__ cur_clear,
+                                                      int* __restrict__ live, int nb) {
   extern __shared__ int lds[];
   int* cnt = lds;
-  int* base = lds + nlv;
-  int* start = lds + 2 * nlv;     // nlv + 1 entries
-  int* tile = lds + 3 * nlv + 1;  // nlv + 1 entries (unused here)
-  block_layout(cnt_dst, nlv, start, tile);
+  int* base = lds + nb;
+  int* start = lds + 2 * nb;  // nb + 1 entries
+  block_layout(cnt_dst, nb, start, nullptr);
   int64_t nsrc = nsrc_fixed;
   if (cnt_src) {
     __shared__ int total;
     if (threadIdx.x == 0) total = 0;
     __syncthreads();
     int acc = 0;
-    for (int b = threadIdx.x; b < nlv; b += blockDim.x) acc += cnt_src[b];
+    for (int b = threadIdx.x; b < nsrc_bins; b += blockDim.x) acc += cnt_src[b];
     atomicAdd(&total, acc);
     __syncthreads();
     nsrc = total;
   }
   if (blockIdx.x == 0) {
-    if (threadIdx.x == 0 && live) __hip_atomic_store(live, start[nlv], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    for (int b = threadIdx.x; b < nlv; b += blockDim.x) {
-      cnt_clear[b] = 0;
-      cur_clear[b] = 0;
+    if (threadIdx.x == 0 && live) __hip_atomic_store(live, start[nb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+      if (cnt_clear) cnt_clear[b] = 0;
+      if (cur_clear) cur_clear[b] = 0;
     }
   }
   const int64_t per = ((nsrc + gridDim.x - 1) / gridDim.x + blockDim.x - 1) / blockDim.x * blockDim.x;
   const int64_t j0 = (int64_t)blockIdx.x * per, j1 = min(nsrc, j0 + per);
   if (j0 >= j1) return;  // the whole workgroup leaves together
-  for (int b = threadIdx.x; b < nlv; b += blockDim.x) cnt[b] = 0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) cnt[b] = 0;
   __syncthreads();
   // every thread runs the same number of rounds (the round's first entry is < j1)
   for (int64_t j = j0 + threadIdx.x; j - threadIdx.x < j1; j += blockDim.x) {
-    const int v = j < j1 ? nxt_lv[j] : -1;
+    int v = -1;
+    if (j < j1) v = key[gather ? src_idx[j] : j];
     (void)wave_lds_reserve(v >= 0 ? v : 0, v >= 0, cnt);
   }
   __syncthreads();
-  for (int b = threadIdx.x; b < nlv; b += blockDim.x) {
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
     int c = cnt[b];
     base[b] = c ? start[b] + atomicAdd(&cur_dst[b], c) : 0;
     cnt[b] = 0;
   }
   __syncthreads();
   for (int64_t j = j0 + threadIdx.x; j - threadIdx.x < j1; j += blockDim.x) {
-    const int v = j < j1 ? nxt_lv[j] : -1;
+    int v = -1, slot = 0;
+    if (j < j1) {
+      slot = src_idx ? src_idx[j] : (int)j;
+      v = key[gather ? slot : j];
+    }
     const int r = wave_lds_reserve(v >= 0 ? v : 0, v >= 0, cnt);
-    if (v >= 0) dst_idx[base[v] + r] = src_idx ? src_idx[j] : (int)j;
+    if (v >= 0) dst_idx[base[v] + r] = slot;
   }
 }
 
 // ---------------------------------------------------------------- step
+#ifndef GV_STEP_WAVES_PER_EU
+#define GV_STEP_WAVES_PER_EU 1
+#endif
 template <bool F32>
-__global__ void __launch_bounds__(256) k_bt_step(DevGeom G, int k, int max_steps, const int* __restrict__ idx,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GV_STEP_WAVES_PER_EU))) k_bt_step(DevGeom G, int k, int max_steps, int cb, const int* __restrict__ idx,
                                                   TRec* __restrict__ rec, const int* __restrict__ cnt_cur,
                                                   int* __restrict__ nxt_lv, int* __restrict__ cnt_next, TCtl C,
                                                   int32_t* __restrict__ out_pv, double* __restrict__ out_step,
                                                   int32_t* __restrict__ out_nsteps, uint32_t* __restrict__ out_flags) {
-  // dynamic LDS: next-LV histogram [nlv], this list's layout start/tile [nlv+1] each
+  // dynamic LDS: next-bucket histogram [nb], this list's layout start/tile [nb+1] each
   extern __shared__ int lds[];
   __shared__ unsigned long long wsum[kWorkN];
-  const int nlv = G.n_lv;
+  const int nlv = G.n_lv << cb;  // buckets: (LV, coarse direction cell)
   int* hist = lds;
   int* start = lds + nlv;
   int* tilep = lds + 2 * nlv + 1;
@@ -267,7 +312,7 @@ __global__ void __launch_bounds__(256) k_bt_step(DevGeom G, int k, int max_steps
       V3 p{r.x, r.y, r.z}, d{r.dx, r.dy, r.dz};
       uint32_t fl = (uint32_t)r.fl;
       int nx;
-      double st = step_culled<F32>(G, b, r.pv, p, d, &nx, &fl, w);
+      double st = step_culled<F32>(G, b >> cb, r.pv, p, d, &nx, &fl, w);
       p = advance(p, st, d);
       out_step[(size_t)id * max_steps + k] = st;
       out_pv[(size_t)id * (max_steps + 1) + k + 1] = nx;
@@ -285,13 +330,16 @@ __global__ void __launch_bounds__(256) k_bt_step(DevGeom G, int k, int max_steps
         out_nsteps[id] = k + 1;
         out_flags[id] = fl;
       } else {
-        rec[id].x = p.x;
-        rec[id].y = p.y;
-        rec[id].z = p.z;
-        rec[id].pv = nx;
-        rec[id].zr = zr;
-        rec[id].fl = (int)fl;
-        nlv_out = G.pv_lv[nx];
+        // the whole 64-byte record in one go: full-line writes need no
+        // read-modify-write of the line
+        r.x = p.x;
+        r.y = p.y;
+        r.z = p.z;
+        r.pv = nx;
+        r.zr = zr;
+        r.fl = (int)fl;
+        rec[id] = r;
+        nlv_out = G.pv_lv[nx] << cb | r.cc;
       }
       nxt_lv[e] = nlv_out;
     }

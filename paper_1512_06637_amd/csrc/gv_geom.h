@@ -31,6 +31,11 @@ struct DevGeom {
   CQF lv_scr;        // [n_lv] S: max |coordinate| of a point of the LV's solid + 1 mm
   CQF dau_box32;     // [n_place][8] dau_box widened by 128 u (S(mother) + |box|inf), rounded outward; 2 unused
   CQF dau_scr32;     // [n_place][16] R (9), t (3), child a b c (box: dx dy dz; tube: rmin rmax dz), e
+  // daughter groups: 8 consecutive daughters of an LV with >= 16 daughters
+  CQI dau_ident;     // [n_place] 1 when the placement is the identity (R = I, t = 0)
+  CQI lv_grp;        // [n_lv] index of the LV's first group box, -1 without groups
+  CQ grp_box;        // [n_grp][6] union of the group's padded daughter boxes (lo xyz, hi xyz)
+  CQF grp_box32;     // [n_grp][8] union of the group's FP32 boxes; 2 unused
 };
 
 __device__ __forceinline__ V3 ld3(const double* x, const double* y, const double* z, int64_t i) {

@@ -331,7 +331,7 @@ extern "C" int gv_server_submit(gv_server* s, int32_t kind, int32_t precision, i
   if (gv::RingAlloc::round_up(li) > s->rin.capacity() || gv::RingAlloc::round_up(lo) > s->rout.capacity())
     return fail(GV_EINVAL, "%s: a basket of %lld tracks never fits the HBM budget", fn, (long long)n);
   DeviceGuard dgd(s->device);
-  GV_TRY(server_progress(s, false));
+  // no completion here: slots and arena space come back only in poll/drain
   if (s->admitted >= s->slots) return fail(GV_EAGAIN, "%s: all %d slots busy", fn, s->slots);
   const size_t oi = s->rin.alloc(li);
   if (oi == gv::RingAlloc::npos) return fail(GV_EAGAIN, "%s: input arena full", fn);

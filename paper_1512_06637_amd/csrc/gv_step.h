@@ -94,45 +94,69 @@ struct F3 {
 };
 __device__ __forceinline__ float max3f(float a, float b, float c) { return fmaxf(fmaxf(a, b), c); }
 
-// Per lane: which of daughters off+c0 .. off+c0+m-1 may be entered at a ray
-// parameter in [0, bound].  A daughter is dropped only when the ray provably
-// misses its padded box or meets it beyond the bound.  Undecidable (NaN)
-// comparisons keep the daughter.
-__device__ __forceinline__ uint64_t box_screen64(const DevGeom& G, int base, int m, V3 inv, V3 pin, double bound) {
-  uint64_t cand = 0;
-  for (int k = 0; k < m; ++k) {
-    CQ B = G.dau_box + 6 * (size_t)(base + k);
-    double ax = fma(B[0], inv.x, pin.x), bx = fma(B[3], inv.x, pin.x);
-    double ay = fma(B[1], inv.y, pin.y), by = fma(B[4], inv.y, pin.y);
-    double az = fma(B[2], inv.z, pin.z), bz = fma(B[5], inv.z, pin.z);
-    double nr = fmax(fmax(fmin(ax, bx), fmin(ay, by)), fmin(az, bz));
-    double fr = fmin(fmin(fmax(ax, bx), fmax(ay, by)), fmax(az, bz));
-    bool out = nr > fr || fr < 0.0 || nr > bound;
-    cand |= out ? 0ull : (1ull << k);
-  }
-  return cand;
+// Whether a lane's ray may enter a padded box at a parameter in [0, bound]:
+// false only when the ray provably misses the box or meets it beyond the
+// bound.  Undecidable (NaN) comparisons keep the box.
+__device__ __forceinline__ bool box_hit64(CQ B, V3 inv, V3 pin, double bound) {
+  const double ax = fma(B[0], inv.x, pin.x), bx = fma(B[3], inv.x, pin.x);
+  const double ay = fma(B[1], inv.y, pin.y), by = fma(B[4], inv.y, pin.y);
+  const double az = fma(B[2], inv.z, pin.z), bz = fma(B[5], inv.z, pin.z);
+  const double nr = fmax(fmax(fmin(ax, bx), fmin(ay, by)), fmin(az, bz));
+  const double fr = fmin(fmin(fmax(ax, bx), fmax(ay, by)), fmax(az, bz));
+  return !(nr > fr || fr < 0.0 || nr > bound);
 }
 
 // The same test in FP32.  The FP32 boxes are the FP64 ones widened by
 // delta = 128 u (S + |box|inf), S of the mother, u = 2^-24, which covers the
 // rounding of the point, of the direction over a parameter up to 4 S and of
-// the slab arithmetic's absolute part, for every point with |p|inf <= S.  The parameters'
-// remaining relative error (a few u) is covered by moving the entry down and
-// the exit up by 8 u of their size before comparing.
-__device__ __forceinline__ uint64_t box_screen32(const DevGeom& G, int base, int m, F3 inv, F3 pin, float bound) {
-  uint64_t cand = 0;
+// the slab arithmetic's absolute part, for every point with |p|inf <= S.  The
+// parameters' remaining relative error (a few u) is covered by moving the
+// entry down and the exit up by 8 u of their size before comparing.
+__device__ __forceinline__ bool box_hit32(CQF B, F3 inv, F3 pin, float bound) {
   const float r = 8.0f * kU32;
-  for (int k = 0; k < m; ++k) {
-    CQF B = G.dau_box32 + 8 * (size_t)(base + k);
-    float ax = fmaf(B[0], inv.x, pin.x), bx = fmaf(B[3], inv.x, pin.x);
-    float ay = fmaf(B[1], inv.y, pin.y), by = fmaf(B[4], inv.y, pin.y);
-    float az = fmaf(B[2], inv.z, pin.z), bz = fmaf(B[5], inv.z, pin.z);
-    float nr = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fminf(az, bz));
-    float fr = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fmaxf(az, bz));
-    nr = fmaf(-r, fabsf(nr), nr);
-    fr = fmaf(r, fabsf(fr), fr);
-    bool out = nr > fr || fr < 0.0f || nr > bound;
-    cand |= out ? 0ull : (1ull << k);
+  const float ax = fmaf(B[0], inv.x, pin.x), bx = fmaf(B[3], inv.x, pin.x);
+  const float ay = fmaf(B[1], inv.y, pin.y), by = fmaf(B[4], inv.y, pin.y);
+  const float az = fmaf(B[2], inv.z, pin.z), bz = fmaf(B[5], inv.z, pin.z);
+  float nr = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fminf(az, bz));
+  float fr = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fmaxf(az, bz));
+  nr = fmaf(-r, fabsf(nr), nr);
+  fr = fmaf(r, fabsf(fr), fr);
+  return !(nr > fr || fr < 0.0f || nr > bound);
+}
+
+// Group size of the two-level box screen and the daughter count from which an
+// LV gets group boxes (placement order is assumed to carry spatial locality;
+// a group box is the union of its members' boxes, so the screen stays exact).
+constexpr int kGroup = 8, kGroupMin = 16;
+
+// Pass 1 over daughters c0 .. c0+m-1 (m <= 64) of an LV: per lane, the bit mask
+// of daughters whose box the ray may enter within the bound, and in `any` the
+// union over the wavefront's active lanes (wavefront-uniform).  With groups, a
+// group whose box no lane enters skips its members' tests.
+template <class Hit, class HitG, class W>
+__device__ __forceinline__ uint64_t box_screen(int c0, int m, int grp, Hit hit, HitG hitg, uint64_t& any, W& w) {
+  uint64_t cand = 0;
+  any = 0;
+  if (grp < 0) {
+    for (int k = 0; k < m; ++k) {
+      const bool h = hit(c0 + k);
+      cand |= h ? (1ull << k) : 0ull;
+      any |= __ballot(h) ? (1ull << k) : 0ull;
+    }
+    w.add(kWorkBox, (unsigned)m);
+    return cand;
+  }
+  for (int g0 = 0; g0 < m; g0 += kGroup) {
+    const bool gh = hitg(grp + (c0 + g0) / kGroup);
+    w.add(kWorkBox);
+    if (__ballot(gh) == 0) continue;
+    const int mm = min(kGroup, m - g0);
+    for (int k = 0; k < mm; ++k) {
+      const bool h = gh && hit(c0 + g0 + k);
+      cand |= h ? (1ull << (g0 + k)) : 0ull;
+      any |= __ballot(h) ? (1ull << (g0 + k)) : 0ull;
+    }
+    w.add(kWorkBox, (unsigned)mm);
   }
   return cand;
 }
@@ -164,10 +188,10 @@ __device__ __forceinline__ float lower_bound32(CQF Y, F3 p, float pmax) {
 // daughter found so far, and its DistanceToIn is never below its padded
 // bounding box's entry distance nor below its SafetyToIn.  Pass 1 tests every
 // daughter's box against each lane's ray (table reads are uniform when the LV
-// is) and collects per-lane candidate masks; pass 2 lets each lane walk its own
+// is) and collects per-lane candidate masks; pass 2 takes each lane's
 // candidates in index order, checks the SafetyToIn bound, and evaluates
-// DistanceToIn only where it can still win.  Walking in index order with a
-// strict < keeps the lowest index among equal minima, as the plain loop does.
+// DistanceToIn only where it can still win.  Index order with a strict < keeps
+// the lowest index among equal minima, as the plain loop does.
 template <class S, bool F32, class W>
 __device__ __forceinline__ void daughters_culled(const DevGeom& G, int lv, int off, int cnt, V3 pl, V3 dl,
                                                  double dout, double& best, int& bestk, bool& neg, W& w) {
@@ -195,31 +219,42 @@ __device__ __forceinline__ void daughters_culled(const DevGeom& G, int lv, int o
     inv = V3{rcp_fast(dl.x), rcp_fast(dl.y), rcp_fast(dl.z)};
     pin = V3{-pl.x * inv.x, -pl.y * inv.y, -pl.z * inv.z};
   }
+  const int grp = G.lv_grp[lv];
   for (int c0 = 0; c0 < cnt; c0 += 64) {
     const int m = min(64, cnt - c0);
-    uint64_t cand = use32 ? box_screen32(G, off + c0, m, inv32, pin32, bound32)
-                          : box_screen64(G, off + c0, m, inv, pin, bound);
-    w.add(kWorkBox, (unsigned)m);
+    uint64_t cand, any;
+    if (use32) {
+      cand = box_screen(
+          c0, m, grp, [&](int k) { return box_hit32(G.dau_box32 + 8 * (size_t)(off + k), inv32, pin32, bound32); },
+          [&](int gi) { return box_hit32(G.grp_box32 + 8 * (size_t)gi, inv32, pin32, bound32); }, any, w);
+    } else {
+      cand = box_screen(
+          c0, m, grp, [&](int k) { return box_hit64(G.dau_box + 6 * (size_t)(off + k), inv, pin, bound); },
+          [&](int gi) { return box_hit64(G.grp_box + 6 * (size_t)gi, inv, pin, bound); }, any, w);
+    }
+    (void)any;
     while (cand) {
       const int k = __builtin_ctzll(cand);
       cand &= cand - 1;
       const int pk = off + c0 + k;
       CQ Y = G.dau_xf + 12 * (size_t)pk;
       CQ q = G.par + G.dau_par[pk];
+      const bool ident = G.dau_ident[pk] != 0;  // then the child frame is the mother's
       const double thr = fmin(best, dout) + kTol;
       w.add(kWorkBound + S::kType);
-      V3 pc;
+      V3 pc = pl;
       if (use32) {
         const float lb = lower_bound32<S>(G.dau_scr32 + 16 * (size_t)pk, p32, pmax);
         const float t32 = (float)thr;
         if (lb > fmaf(4.0f * kU32, t32, t32)) continue;
-        pc = to_child_p(Y, pl);
+        if (!ident) pc = to_child_p(Y, pl);
       } else {
-        pc = to_child_p(Y, pl);
+        if (!ident) pc = to_child_p(Y, pl);
         if (S::safety_in(q, pc) > thr) continue;
       }
       w.add(kWorkFull + S::kType);
-      const V3 dc = to_child_d(Y, dl);
+      V3 dc = dl;
+      if (!ident) dc = to_child_d(Y, dl);
       double t = S::dist_in(q, pc, dc);
       neg = neg || t < 0.0;
       t = fmax(t, 0.0);

@@ -50,3 +50,20 @@ def test_null_handle_and_negative_n_are_rejected():
     assert L.nav_transport(None, -1, *([None] * 7), 128, *([None] * 4), 0, None) == G.GV_EINVAL
     assert L.geom_free(None) == G.GV_OK
     assert L.geom_load(None, 0, None) == G.GV_EINVAL
+
+
+def test_server_argument_checks_need_no_gpu():
+    """The serving entry points reject bad handles and arguments on the host."""
+    L = G.lib()
+    h = C.c_void_p()
+    assert L.gv_server_create(None, 64, 256 << 20, 2, C.byref(h)) == G.GV_EINVAL
+    assert L.gv_server_create(None, 64, 256 << 20, 2, None) == G.GV_EINVAL
+    cnt = C.c_int32(0)
+    assert L.gv_server_submit(None, 0, 0, 10, None, None, None) == G.GV_EINVAL
+    assert L.gv_server_poll(None, 0, None, None, C.byref(cnt)) == G.GV_EINVAL
+    assert L.gv_server_drain(None) == G.GV_EINVAL
+    assert L.gv_server_stats(None, None) == G.GV_EINVAL
+    assert L.gv_server_destroy(None) == G.GV_OK
+    t0 = L.gv_now()
+    assert L.gv_now() >= t0 > 0.0
+
