@@ -895,7 +895,7 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
   const int cb = coarse_bits(g->n_lv);
   const int nl = g->n_lv << cb;  // buckets: (LV, coarse direction cell)
   const unsigned sg = stream_grid(n);
-  const size_t lds_ix = 12 * (size_t)nl + 4, lds_step = 12 * (size_t)nl + 8;
+  const size_t lds_ix = 12 * (size_t)nl + 4, lds_step = 4 * (size_t)nl + 12 * (size_t)g->n_lv + 8;
   const unsigned rg = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 4095) / 4096, 256));
   TCtl& C = g->ctl;
   hipLaunchKernelGGL(k_bt_clear, dim3(1), dim3(kBlock), 0, s, C, nl);
@@ -907,13 +907,14 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
                      (const int*)g->nxt_lv, 0, g->idx[0], (const int*)C.cnt[0], C.cur[0], C.cnt[1], C.cur[1],
                      (int*)nullptr, nl);
   GV_TRY(launched(fn));
-  const int64_t max_tiles = n / kWave + nl + 1;
+  const int64_t max_tiles = n / kWave + g->n_lv + 1;
   const unsigned step_grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((max_tiles + 3) / 4, 1024));
-  // The host enqueues steps in chunks; once the live count that the index
-  // kernel at the end of an earlier chunk stored into pinned host memory is
-  // zero, the remaining steps are not enqueued.  Two chunks stay in flight, so
-  // the device never waits for this check.
-  constexpr int kChunk = 8;
+  // The host enqueues steps in chunks of kChunk; at a chunk's end the index
+  // kernel stores the live count into pinned host memory.  Before enqueueing
+  // the end of chunk m the host waits for the count stored at the end of chunk
+  // m-1 and stops once it is zero, so at most about two chunks of empty steps
+  // are launched, and the device still has a chunk queued while the host looks.
+  constexpr int kChunk = 4;
   int chunk = 0;
   for (int k = 0; k < max_steps; ++k) {
     const int c = k & 1, k0 = k % 3, k1 = (k + 1) % 3, k2 = (k + 2) % 3;
@@ -938,11 +939,12 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
     if (k + 1 == max_steps) break;
     const bool report = (k + 1) % kChunk == 0;
     const int slot = chunk & 1;
-    if (report && chunk >= 2) {
-      // the count stored two chunks ago: wait for its kernel, then look
-      hipError_t e = hipEventSynchronize(g->ev[slot]);
+    if (report && chunk >= 1) {
+      // the count stored at the end of the previous chunk (the other slot)
+      const int prev = slot ^ 1;
+      hipError_t e = hipEventSynchronize(g->ev[prev]);
       if (e != hipSuccess) return hip_fail(e, "nav_transport: hipEventSynchronize");
-      if (((volatile int*)g->h_live)[slot] == 0) break;
+      if (((volatile int*)g->h_live)[prev] == 0) break;
     }
     hipLaunchKernelGGL(k_bt_reindex, dim3(rg), dim3(1024), lds_ix, s, (const int*)g->idx[c], (const int*)C.cnt[k0],
                        nl, (int64_t)0, (const int*)g->nxt_lv, 0, g->idx[c ^ 1], (const int*)C.cnt[k1], C.cur[k1],

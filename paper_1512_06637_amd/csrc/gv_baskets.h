@@ -4,9 +4,10 @@
 //
 // Track states stay in place (one 64-byte record per track, slot = track id);
 // what is regrouped is a list of slot indices with one contiguous bucket per
-// (LV, coarse direction cell).  A wavefront takes a tile of 64 consecutive list
-// entries of one bucket, so its LV -- the mother solid and the whole daughter
-// table -- is wavefront-uniform: the daughter loop reads transforms and solid
+// (LV, coarse direction cell), the cells of one LV next to each other.  A
+// wavefront takes a tile of 64 consecutive list entries of one LV's range, so
+// its LV -- the mother solid and the whole daughter table -- is
+// wavefront-uniform: the daughter loop reads transforms and solid
 // parameters with scalar loads into SGPRs and the lanes never diverge on the
 // solid type.  The direction cell keeps a tile's rays within one cone of
 // directions, so they tend to meet the same daughters (the group screen of the
@@ -57,13 +58,13 @@ __device__ __forceinline__ void wave_count(int v, bool on, int* cnt) {
   }
 }
 
-// Bucket layout of a list from its per-LV counts, computed by the first
-// wavefront of the workgroup into LDS: start[b] (exclusive prefix, start[nlv] =
-// total) and tile[b] (exclusive prefix of ceil(count/64), tile[nlv] = number
-// of tiles; tile may be NULL).  Chunks of 64 LVs, a shuffle scan per chunk.
-// All threads of the workgroup must call it (it ends with a barrier); any block
-// size works.
-__device__ void block_layout(const int* __restrict__ cnt, int nlv, int* start, int* tile) {
+// Bucket layout of a list from its per-bucket counts `cnt` (in LDS), computed
+// by the first wavefront of the workgroup: start[b] (exclusive prefix,
+// start[nlv] = total) and tile[b] (exclusive prefix of ceil(count/64),
+// tile[nlv] = number of tiles; tile may be NULL).  Chunks of 64 buckets, a
+// shuffle scan per chunk.  All threads of the workgroup must call it (it ends
+// with a barrier); any block size works.
+__device__ void block_layout(const int* cnt, int nlv, int* start, int* tile) {
   if (threadIdx.x < kWave) {
     const int lane = threadIdx.x;
     int carry = 0, tcarry = 0;
@@ -92,6 +93,13 @@ __device__ void block_layout(const int* __restrict__ cnt, int nlv, int* start, i
       if (tile) tile[nlv] = tcarry;
     }
   }
+  __syncthreads();
+}
+
+// Copies n counts from global memory into LDS with every thread of the
+// workgroup (one round trip), then a barrier.
+__device__ __forceinline__ void stage_counts(const int* __restrict__ src, int n, int* dst) {
+  for (int b = threadIdx.x; b < n; b += blockDim.x) dst[b] = src[b];
   __syncthreads();
 }
 
@@ -219,7 +227,8 @@ __global__ void __launch_bounds__(1024) k_bt_reindex(const int* __restrict__ src
   int* cnt = lds;
   int* base = lds + nb;
   int* start = lds + 2 * nb;  // nb + 1 entries
-  block_layout(cnt_dst, nb, start, nullptr);
+  stage_counts(cnt_dst, nb, base);  // base is free until the layout is done
+  block_layout(base, nb, start, nullptr);
   int64_t nsrc = nsrc_fixed;
   if (cnt_src) {
     __shared__ int total;
@@ -277,23 +286,36 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GV_STE
                                                   int* __restrict__ nxt_lv, int* __restrict__ cnt_next, TCtl C,
                                                   int32_t* __restrict__ out_pv, double* __restrict__ out_step,
                                                   int32_t* __restrict__ out_nsteps, uint32_t* __restrict__ out_flags) {
-  // dynamic LDS: next-bucket histogram [nb], this list's layout start/tile [nb+1] each
+  // Dynamic LDS: next-bucket histogram [nb], this list's per-LV counts [nlv]
+  // and per-LV layout start/tile [nlv+1] each.  The list is ordered by
+  // bucket = (LV, coarse direction cell), so each LV's entries are contiguous
+  // and ordered by direction cell; tiles cover whole LV ranges (a tile may
+  // span two neighbouring cells) so that cells add no partial tiles.
   extern __shared__ int lds[];
   __shared__ unsigned long long wsum[kWorkN];
-  const int nlv = G.n_lv << cb;  // buckets: (LV, coarse direction cell)
+  const int nlv = G.n_lv, nb = nlv << cb;
   int* hist = lds;
-  int* start = lds + nlv;
-  int* tilep = lds + 2 * nlv + 1;
-  for (int v = threadIdx.x; v < nlv; v += blockDim.x) hist[v] = 0;
+  int* lvc = lds + nb;
+  int* start = lvc + nlv;
+  int* tilep = start + nlv + 1;
   for (int i = threadIdx.x; i < kWorkN; i += blockDim.x) wsum[i] = 0;
-  block_layout(cnt_cur, nlv, start, tilep);
+  stage_counts(cnt_cur, nb, hist);  // hist is free until the layout is done
+  for (int v = threadIdx.x; v < nlv; v += blockDim.x) {
+    int c = 0;
+    for (int q = 0; q < (1 << cb); ++q) c += hist[v << cb | q];
+    lvc[v] = c;
+  }
+  __syncthreads();
+  block_layout(lvc, nlv, start, tilep);
+  for (int v = threadIdx.x; v < nb; v += blockDim.x) hist[v] = 0;
+  __syncthreads();
   LdsWork w{wsum};
   const int tiles = tilep[nlv];
   const int lane = __lane_id();
   const int wave = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave);
   const int nwaves = (int)(gridDim.x * (int64_t)blockDim.x / kWave);
   for (int t = wave; t < tiles; t += nwaves) {
-    // bucket of tile t: largest b with tile[b] <= t (wavefront-uniform search)
+    // LV of tile t: largest b with tile[b] <= t (wavefront-uniform search)
     int lo = 0, hi = nlv - 1;
     while (lo < hi) {
       int mid = (lo + hi + 1) >> 1;
@@ -312,7 +334,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GV_STE
       V3 p{r.x, r.y, r.z}, d{r.dx, r.dy, r.dz};
       uint32_t fl = (uint32_t)r.fl;
       int nx;
-      double st = step_culled<F32>(G, b >> cb, r.pv, p, d, &nx, &fl, w);
+      double st = step_culled<F32>(G, b, r.pv, p, d, &nx, &fl, w);
       p = advance(p, st, d);
       out_step[(size_t)id * max_steps + k] = st;
       out_pv[(size_t)id * (max_steps + 1) + k + 1] = nx;
@@ -347,7 +369,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GV_STE
     wave_count(nlv_out >= 0 ? nlv_out : 0, nlv_out >= 0, hist);
   }
   __syncthreads();
-  for (int v = threadIdx.x; v < nlv; v += blockDim.x)
+  for (int v = threadIdx.x; v < nb; v += blockDim.x)
     if (hist[v]) atomicAdd(&cnt_next[v], hist[v]);
   for (int i = threadIdx.x; i < kWorkN; i += blockDim.x)
     if (wsum[i]) atomicAdd(&C.work[i], wsum[i]);
