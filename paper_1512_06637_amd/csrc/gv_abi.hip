@@ -51,6 +51,11 @@ struct gv_geom {
   int* idx[2] = {nullptr, nullptr};  // bucketed slot lists
   TCtl ctl{};
   int* nxt_lv = nullptr;    // [cap] next bucket per list entry (start bucket per track at the start)
+  int* slot_id = nullptr;   // [cap] track id of each slot
+  void* ob = nullptr;       // staged outputs: ob_step [ob_steps][cap] double, then ob_pv [ob_steps][cap] int
+  double* ob_step = nullptr;
+  int* ob_pv = nullptr;
+  int64_t ob_cap = 0, ob_steps = 0;
   int* h_live = nullptr;  // [2] pinned, mapped host copies of the live count
   int* d_live = nullptr;  // device address of h_live
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -550,6 +555,7 @@ extern "C" int geom_free(gv_geom* g) {
   if (dev != g->device) (void)hipSetDevice(g->device);
   hipError_t e = hipDeviceSynchronize();
   if (g->ws) (void)hipFree(g->ws);
+  if (g->ob) (void)hipFree(g->ob);
   if (g->dmem) (void)hipFree(g->dmem);
   if (g->h_live) (void)hipHostFree(g->h_live);
   for (auto& ev : g->prof_ev) (void)hipEventDestroy(ev);
@@ -833,8 +839,8 @@ int ensure_workspace(gv_geom* g, int64_t n) {
   if (g->ws && g->ws_tracks >= n) return GV_OK;
   int64_t cap = n < 4096 ? 4096 : n;
   int nl = g->n_lv << coarse_bits(g->n_lv);
-  size_t total = al256(sizeof(TRec) * (size_t)cap) + 3 * al256(4 * (size_t)cap) + 6 * al256(4 * (size_t)nl) +
-                 al256(8 * kWorkN);
+  size_t total = al256(sizeof(TRec) * (size_t)cap) + 4 * al256(4 * (size_t)cap) + 6 * al256(4 * (size_t)nl) +
+                 al256(8 * kWorkN) + al256(4);
   if (g->ws) {
     (void)hipDeviceSynchronize();
     (void)hipFree(g->ws);
@@ -859,11 +865,13 @@ int ensure_workspace(gv_geom* g, int64_t n) {
   g->idx[0] = (int*)take(4 * cap);
   g->idx[1] = (int*)take(4 * cap);
   g->nxt_lv = (int*)take(4 * cap);
+  g->slot_id = (int*)take(4 * cap);
   for (int s = 0; s < 3; ++s) {
     g->ctl.cnt[s] = (int*)take(4 * nl);
     g->ctl.cur[s] = (int*)take(4 * nl);
   }
   g->ctl.work = (unsigned long long*)take(8 * kWorkN);
+  g->ctl.nlive = (int*)take(4);
   if (!g->h_live) {
     e = hipHostMalloc((void**)&g->h_live, 2 * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent);
     if (e != hipSuccess) return hip_fail(e, "nav_transport: hipHostMalloc");
@@ -878,6 +886,36 @@ int ensure_workspace(gv_geom* g, int64_t n) {
   g->ws_bytes = total;
   g->ws_tracks = cap;
   return GV_OK;
+}
+
+// Step-major output staging for `steps` steps of the workspace's tracks, kept
+// in the handle and grown on demand; up to kStageMaxBytes.  Returns false (and
+// leaves ob_step NULL) when it would be larger, and the step kernel then writes
+// the rows directly.
+constexpr size_t kStageMaxBytes = (size_t)8 << 30;
+bool ensure_staging(gv_geom* g, int64_t steps) {
+  const int64_t cap = g->ws_tracks;
+  const size_t bytes = (size_t)cap * (size_t)steps * 12;
+  if (bytes > kStageMaxBytes) return false;
+  if (g->ob && g->ob_cap >= cap && g->ob_steps >= steps) return true;
+  if (g->ob) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(g->ob);
+    g->ob = nullptr;
+    g->ob_step = nullptr;
+    g->ob_pv = nullptr;
+    g->ob_cap = g->ob_steps = 0;
+  }
+  if (hipMalloc(&g->ob, al256((size_t)cap * steps * 8) + (size_t)cap * steps * 4) != hipSuccess) {
+    (void)hipGetLastError();
+    g->ob = nullptr;
+    return false;
+  }
+  g->ob_step = (double*)g->ob;
+  g->ob_pv = (int*)((char*)g->ob + al256((size_t)cap * steps * 8));
+  g->ob_cap = cap;
+  g->ob_steps = steps;
+  return true;
 }
 
 constexpr int64_t kBasketMin = 8192;  // smaller batches use one lane per track
@@ -900,13 +938,20 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
   TCtl& C = g->ctl;
   hipLaunchKernelGGL(k_bt_clear, dim3(1), dim3(kBlock), 0, s, C, nl);
   GV_TRY(launched(fn));
-  hipLaunchKernelGGL(k_bt_init, dim3(sg), dim3(kBlock), 4 * (size_t)nl, s, g->dg, n, x, y, z, dx, dy, dz, start_pv, max_steps,
-                     out_pv, out_nsteps, out_flags, g->rec, g->nxt_lv, cb, C);
+  hipLaunchKernelGGL(k_bt_init, dim3(sg), dim3(kBlock), 4 * (size_t)nl, s, g->dg, n, x, y, z, dx, dy, dz, start_pv,
+                     max_steps, out_pv, out_nsteps, out_flags, g->nxt_lv, cb, C);
   GV_TRY(launched(fn));
+  // live track ids in bucket order (into idx[1]), then slots in that order
   hipLaunchKernelGGL(k_bt_reindex, dim3(rg), dim3(1024), lds_ix, s, (const int*)nullptr, (const int*)nullptr, 0, n,
-                     (const int*)g->nxt_lv, 0, g->idx[0], (const int*)C.cnt[0], C.cur[0], C.cnt[1], C.cur[1],
+                     (const int*)g->nxt_lv, 0, g->idx[1], (const int*)C.cnt[0], C.cur[0], C.cnt[1], C.cur[1],
                      (int*)nullptr, nl);
   GV_TRY(launched(fn));
+  hipLaunchKernelGGL(k_bt_place, dim3(sg), dim3(kBlock), 0, s, (const int*)g->idx[1], x, y, z, dx, dy, dz,
+                     (const int32_t*)out_pv, max_steps, cb, nl, g->rec, g->slot_id, g->idx[0], C);
+  GV_TRY(launched(fn));
+  const bool staged = ensure_staging(g, max_steps);
+  double* ob_step = staged ? g->ob_step : nullptr;
+  int* ob_pv = staged ? g->ob_pv : nullptr;
   const int64_t max_tiles = n / kWave + g->n_lv + 1;
   const unsigned step_grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((max_tiles + 3) / 4, 1024));
   // The host enqueues steps in chunks of kChunk; at a chunk's end the index
@@ -915,7 +960,7 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
   // m-1 and stops once it is zero, so at most about two chunks of empty steps
   // are launched, and the device still has a chunk queued while the host looks.
   constexpr int kChunk = 4;
-  int chunk = 0;
+  int chunk = 0, launched_steps = 0;
   for (int k = 0; k < max_steps; ++k) {
     const int c = k & 1, k0 = k % 3, k1 = (k + 1) % 3, k2 = (k + 2) % 3;
     hipEvent_t* pe = nullptr;
@@ -933,8 +978,9 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
     }
     hipLaunchKernelGGL(fp32 ? k_bt_step<true> : k_bt_step<false>, dim3(step_grid), dim3(kBlock), lds_step, s, g->dg,
                        k, max_steps, cb, (const int*)g->idx[c], g->rec, (const int*)C.cnt[k0], g->nxt_lv, C.cnt[k1], C,
-                       out_pv, out_step, out_nsteps, out_flags);
+                       out_pv, out_step, out_nsteps, out_flags, (const int*)g->slot_id, ob_step, ob_pv, g->ob_cap);
     GV_TRY(launched(fn));
+    launched_steps = k + 1;
     if (pe) (void)hipEventRecord(pe[1], s);
     if (k + 1 == max_steps) break;
     const bool report = (k + 1) % kChunk == 0;
@@ -955,6 +1001,12 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
       if (e != hipSuccess) return hip_fail(e, "nav_transport: hipEventRecord");
       ++chunk;
     }
+  }
+  if (staged && launched_steps > 0) {
+    const dim3 eg((unsigned)((n + 63) / 64), (unsigned)((launched_steps + 63) / 64));
+    hipLaunchKernelGGL(k_bt_emit, eg, dim3(256), 0, s, (const double*)ob_step, (const int*)ob_pv, g->ob_cap,
+                       (const int*)g->slot_id, C, max_steps, (const int32_t*)out_nsteps, out_step, out_pv);
+    GV_TRY(launched(fn));
   }
   return GV_OK;
 }

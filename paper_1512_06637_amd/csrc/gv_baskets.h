@@ -44,6 +44,7 @@ struct TCtl {
   int* cnt[3];    // [nlv] tracks per LV in list k % 3
   int* cur[3];    // [nlv] index-scatter cursors of list k % 3
   unsigned long long* work;  // [kWorkN] operation counts of the current call
+  int* nlive;                // live tracks at the start (slots in use)
 };
 
 // wavefront-aggregated histogram update: one atomic per distinct LV in the wave
@@ -132,17 +133,16 @@ __device__ __forceinline__ int dir_cell(double dx, double dy, double dz, int cb)
   return iv * side + iu;
 }
 
-// Start volume of every track (given or located), entry 0 of its sequence, its
-// record, and its start bucket (LV, coarse direction cell) into key with the
-// bucket counts of the first list (per-workgroup LDS histogram, 4 nb bytes of
-// dynamic LDS).  Tracks that start outside the world finish here with zero steps
-// and get bucket -1.
+// Start volume of every track (given or located), entry 0 of its sequence,
+// and its start bucket (LV, coarse direction cell) into key, with the bucket
+// counts of the first list (per-workgroup LDS histogram, 4 nb bytes of dynamic
+// LDS).  Tracks that start outside the world finish here with zero steps and
+// get bucket -1.
 __global__ void k_bt_init(DevGeom G, int64_t n, const double* __restrict__ x, const double* __restrict__ y,
                           const double* __restrict__ z, const double* __restrict__ dx, const double* __restrict__ dy,
                           const double* __restrict__ dz, const int32_t* __restrict__ start_pv, int max_steps,
                           int32_t* __restrict__ out_pv, int32_t* __restrict__ out_nsteps,
-                          uint32_t* __restrict__ out_flags, TRec* __restrict__ rec, int* __restrict__ key, int cb,
-                          TCtl C) {
+                          uint32_t* __restrict__ out_flags, int* __restrict__ key, int cb, TCtl C) {
   extern __shared__ int hist[];
   const int nb = G.n_lv << cb;
   for (int v = threadIdx.x; v < nb; v += blockDim.x) hist[v] = 0;
@@ -165,19 +165,7 @@ __global__ void k_bt_init(DevGeom G, int64_t n, const double* __restrict__ x, co
         out_nsteps[i] = 0;
         out_flags[i] = fl;
       } else {
-        TRec r;
-        r.x = p.x;
-        r.y = p.y;
-        r.z = p.z;
-        r.dx = dx[i];
-        r.dy = dy[i];
-        r.dz = dz[i];
-        r.pv = v;
-        r.zr = 0;
-        r.fl = 0;
-        r.cc = dir_cell(r.dx, r.dy, r.dz, cb);
-        rec[i] = r;
-        bk = G.pv_lv[v] << cb | r.cc;
+        bk = G.pv_lv[v] << cb | dir_cell(dx[i], dy[i], dz[i], cb);
       }
       key[i] = bk;
     }
@@ -186,6 +174,80 @@ __global__ void k_bt_init(DevGeom G, int64_t n, const double* __restrict__ x, co
   __syncthreads();
   for (int v = threadIdx.x; v < nb; v += blockDim.x)
     if (hist[v]) atomicAdd(&C.cnt[0][v], hist[v]);
+}
+
+// Slots: the live tracks renumbered in the order of the first list (ordered by
+// bucket), so the tracks of a tile are mostly consecutive slots and their
+// records and staged outputs are read and written in contiguous runs.  Slot s
+// takes track perm[s]: its record, slot_id[s] = track id, and entry s of the
+// first list.  Also stores the number of live tracks.
+__global__ void k_bt_place(const int* __restrict__ perm, const double* __restrict__ x, const double* __restrict__ y,
+                           const double* __restrict__ z, const double* __restrict__ dx,
+                           const double* __restrict__ dy, const double* __restrict__ dz,
+                           const int32_t* __restrict__ out_pv, int max_steps, int cb, int nb, TRec* __restrict__ rec,
+                           int* __restrict__ slot_id, int* __restrict__ list0, TCtl C) {
+  __shared__ int total;
+  if (threadIdx.x == 0) total = 0;
+  __syncthreads();
+  int acc = 0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += C.cnt[0][b];
+  atomicAdd(&total, acc);
+  __syncthreads();
+  const int64_t nl = total;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *C.nlive = (int)nl;
+  for (int64_t sl = gtid(); sl < nl; sl += gstride()) {
+    const int id = perm[sl];
+    TRec r;
+    r.x = x[id];
+    r.y = y[id];
+    r.z = z[id];
+    r.dx = dx[id];
+    r.dy = dy[id];
+    r.dz = dz[id];
+    r.pv = out_pv[(size_t)id * (max_steps + 1)];
+    r.zr = 0;
+    r.fl = 0;
+    r.cc = dir_cell(r.dx, r.dy, r.dz, cb);
+    rec[sl] = r;
+    slot_id[sl] = id;
+    list0[sl] = (int)sl;
+  }
+}
+
+// Outputs staged step-major by slot (entry k * cap + s) go to the caller's
+// row-per-track arrays: a workgroup moves a tile of 64 slots x 64 steps through
+// LDS, so both the staged reads and the row writes are contiguous.  Entries
+// past a track's step count are not written.
+__global__ void __launch_bounds__(256) k_bt_emit(const double* __restrict__ ob_step, const int* __restrict__ ob_pv,
+                                                 int64_t cap, const int* __restrict__ slot_id, TCtl C,
+                                                 int max_steps, const int32_t* __restrict__ out_nsteps,
+                                                 double* __restrict__ out_step, int32_t* __restrict__ out_pv) {
+  __shared__ double ts[64][65];
+  __shared__ int tp[64][65];
+  const int64_t s0 = (int64_t)blockIdx.x * 64;
+  const int k0 = blockIdx.y * 64;
+  const int64_t nl = *C.nlive;
+  if (s0 >= nl) return;  // the whole workgroup leaves together
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int r = wv; r < 64; r += 4) {  // row r = step k0 + r, lanes = slots
+    const int k = k0 + r;
+    const int64_t sl = s0 + lane;
+    if (k < max_steps && sl < nl) {
+      ts[lane][r] = ob_step[(size_t)k * cap + sl];
+      tp[lane][r] = ob_pv[(size_t)k * cap + sl];
+    }
+  }
+  __syncthreads();
+  for (int r = wv; r < 64; r += 4) {  // row r = slot s0 + r, lanes = steps
+    const int64_t sl = s0 + r;
+    if (sl >= nl) break;
+    const int id = slot_id[sl];
+    const int k = k0 + lane;
+    if (k < out_nsteps[id]) {
+      out_step[(size_t)id * max_steps + k] = ts[r][lane];
+      out_pv[(size_t)id * (max_steps + 1) + k + 1] = tp[r][lane];
+    }
+  }
 }
 
 // wavefront-aggregated reservation in an LDS counter array: returns, for lanes
@@ -285,7 +347,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GV_STE
                                                   TRec* __restrict__ rec, const int* __restrict__ cnt_cur,
                                                   int* __restrict__ nxt_lv, int* __restrict__ cnt_next, TCtl C,
                                                   int32_t* __restrict__ out_pv, double* __restrict__ out_step,
-                                                  int32_t* __restrict__ out_nsteps, uint32_t* __restrict__ out_flags) {
+                                                  int32_t* __restrict__ out_nsteps, uint32_t* __restrict__ out_flags,
+                                                  const int* __restrict__ slot_id, double* __restrict__ ob_step,
+                                                  int* __restrict__ ob_pv, int64_t cap) {
   // Dynamic LDS: next-bucket histogram [nb], this list's per-LV counts [nlv]
   // and per-LV layout start/tile [nlv+1] each.  The list is ordered by
   // bucket = (LV, coarse direction cell), so each LV's entries are contiguous
@@ -329,15 +393,21 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GV_STE
     const int e = start[b] + within;
     int nlv_out = -1;
     if (act) {
-      const int id = idx[e];
-      TRec r = rec[id];
+      const int sl = idx[e];
+      const int id = slot_id[sl];
+      TRec r = rec[sl];
       V3 p{r.x, r.y, r.z}, d{r.dx, r.dy, r.dz};
       uint32_t fl = (uint32_t)r.fl;
       int nx;
       double st = step_culled<F32>(G, b, r.pv, p, d, &nx, &fl, w);
       p = advance(p, st, d);
-      out_step[(size_t)id * max_steps + k] = st;
-      out_pv[(size_t)id * (max_steps + 1) + k + 1] = nx;
+      if (ob_step) {  // staged by slot, moved to the rows at the end
+        ob_step[(size_t)k * cap + sl] = st;
+        ob_pv[(size_t)k * cap + sl] = nx;
+      } else {
+        out_step[(size_t)id * max_steps + k] = st;
+        out_pv[(size_t)id * (max_steps + 1) + k + 1] = nx;
+      }
       int zr = st < kTol ? r.zr + 1 : 0;
       bool done = nx < 0;
       if (!done && zr >= 8) {
@@ -360,7 +430,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GV_STE
         r.pv = nx;
         r.zr = zr;
         r.fl = (int)fl;
-        rec[id] = r;
+        rec[sl] = r;
         nlv_out = G.pv_lv[nx] << cb | r.cc;
       }
       nxt_lv[e] = nlv_out;
