@@ -1003,9 +1003,9 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
     }
   }
   if (staged && launched_steps > 0) {
-    const dim3 eg((unsigned)((n + 63) / 64), (unsigned)((launched_steps + 63) / 64));
-    hipLaunchKernelGGL(k_bt_emit, eg, dim3(256), 0, s, (const double*)ob_step, (const int*)ob_pv, g->ob_cap,
-                       (const int*)g->slot_id, C, max_steps, (const int32_t*)out_nsteps, out_step, out_pv);
+    hipLaunchKernelGGL(k_bt_emit, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, (const double*)ob_step,
+                       (const int*)ob_pv, g->ob_cap, (const int*)g->slot_id, C, max_steps, launched_steps,
+                       (const int32_t*)out_nsteps, out_step, out_pv);
     GV_TRY(launched(fn));
   }
   return GV_OK;

@@ -215,37 +215,49 @@ __global__ void k_bt_place(const int* __restrict__ perm, const double* __restric
 }
 
 // Outputs staged step-major by slot (entry k * cap + s) go to the caller's
-// row-per-track arrays: a workgroup moves a tile of 64 slots x 64 steps through
-// LDS, so both the staged reads and the row writes are contiguous.  Entries
-// past a track's step count are not written.
+// row-per-track arrays: a workgroup takes 64 slots and moves them through LDS
+// 64 steps at a time, so both the staged reads (64 slots of one step) and the
+// row writes (64 steps of one track) are contiguous.  Only the kmax steps that
+// were run are read; entries past a track's step count are not written.
 __global__ void __launch_bounds__(256) k_bt_emit(const double* __restrict__ ob_step, const int* __restrict__ ob_pv,
                                                  int64_t cap, const int* __restrict__ slot_id, TCtl C,
-                                                 int max_steps, const int32_t* __restrict__ out_nsteps,
+                                                 int max_steps, int kmax, const int32_t* __restrict__ out_nsteps,
                                                  double* __restrict__ out_step, int32_t* __restrict__ out_pv) {
   __shared__ double ts[64][65];
   __shared__ int tp[64][65];
+  __shared__ int sid[64], sns[64];
   const int64_t s0 = (int64_t)blockIdx.x * 64;
-  const int k0 = blockIdx.y * 64;
   const int64_t nl = *C.nlive;
   if (s0 >= nl) return;  // the whole workgroup leaves together
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int r = wv; r < 64; r += 4) {  // row r = step k0 + r, lanes = slots
-    const int k = k0 + r;
-    const int64_t sl = s0 + lane;
-    if (k < max_steps && sl < nl) {
-      ts[lane][r] = ob_step[(size_t)k * cap + sl];
-      tp[lane][r] = ob_pv[(size_t)k * cap + sl];
+  if (threadIdx.x < 64) {
+    const int64_t sl = s0 + threadIdx.x;
+    int id = 0, ns = 0;
+    if (sl < nl) {
+      id = slot_id[sl];
+      ns = out_nsteps[id];
     }
+    sid[threadIdx.x] = id;
+    sns[threadIdx.x] = ns;
   }
-  __syncthreads();
-  for (int r = wv; r < 64; r += 4) {  // row r = slot s0 + r, lanes = steps
-    const int64_t sl = s0 + r;
-    if (sl >= nl) break;
-    const int id = slot_id[sl];
-    const int k = k0 + lane;
-    if (k < out_nsteps[id]) {
-      out_step[(size_t)id * max_steps + k] = ts[r][lane];
-      out_pv[(size_t)id * (max_steps + 1) + k + 1] = tp[r][lane];
+  for (int k0 = 0; k0 < kmax; k0 += 64) {
+    __syncthreads();
+    for (int r = wv; r < 64; r += 4) {  // row r = step k0 + r, lanes = slots
+      const int k = k0 + r;
+      const int64_t sl = s0 + lane;
+      if (k < kmax && sl < nl) {
+        ts[lane][r] = ob_step[(size_t)k * cap + sl];
+        tp[lane][r] = ob_pv[(size_t)k * cap + sl];
+      }
+    }
+    __syncthreads();
+    for (int r = wv; r < 64; r += 4) {  // row r = slot s0 + r, lanes = steps
+      const int k = k0 + lane;
+      if (k < sns[r]) {
+        const int id = sid[r];
+        out_step[(size_t)id * max_steps + k] = ts[r][lane];
+        out_pv[(size_t)id * (max_steps + 1) + k + 1] = tp[r][lane];
+      }
     }
   }
 }
