@@ -57,6 +57,36 @@ SOLID_BYTES = {"inside": 24 + 1, "safety": 24 + 8, "dist_in": 48 + 8, "dist_out"
 HBM_PEAK_GBS = 8000.0
 
 
+def kernel_sources_sha256():
+    """Hash of the HIP sources and the C-ABI header (file names and bytes)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_1512_06637_amd", "csrc", "*")))
+    files.append(os.path.join(ROOT, "include", "gvgeom.h"))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(path=os.path.join(ROOT, "profiles", "k_bt_step_detector_2p20_traffic.txt")):
+    """HBM bytes per k_bt_step launch from the committed counter summary, or
+    None when the kernel sources changed since the counters were taken."""
+    try:
+        txt = open(path).read()
+    except OSError:
+        return None
+    sha = val = None
+    for line in txt.splitlines():
+        if "sha256" in line:
+            sha = line.split("sha256")[1].split()[0]
+        if line.startswith("traffic_bytes_per_launch:"):
+            val = float(line.split(":")[1])
+    return val if sha == kernel_sources_sha256() else None
+
+
 def graph_ms(fn, calls, replays):
     """Per-call device time of `fn(c)`, c = 0 .. calls-1, captured once into a
     HIP graph and replayed: launch overhead of the host stays out."""
@@ -324,7 +354,7 @@ def main():
                    "steps_world_layer_module": [world, layer, module]},
         "roofline": {"bound": "alu", "kernel": "k_bt_step", "achieved": achieved / 1e12,
                      "peak": R.PEAK_FP64_OPS / 1e12, "unit": "TOP/s (FP64 lane-ops)",
-                     "frac": achieved / R.PEAK_FP64_OPS, "traffic": None,
+                     "frac": achieved / R.PEAK_FP64_OPS, "traffic": measured_traffic(),
                      "launches_per_transport": launches / args.steps, "avg_launch_ms": launch_ms,
                      "kernel_ms_per_transport": step_ms, "ops_per_transport": ops},
         "work": {"plain_navigator_ops": ops_plain, "culled_ops": ops, "daughter_box_tests": work[1],

@@ -785,7 +785,7 @@ extern "C" int basket_step(gv_geom* g, int64_t n, const double* x, const double*
   GV_TRY(check_i32(fn, "out_next_pv", out_next_pv));
   GV_TRY(check_i32(fn, "out_flags", out_flags, true));
   DeviceGuard dgd(g->device);
-  hipLaunchKernelGGL(precision == GV_FP64 ? k_step : k_step_scr, dim3(grid_for(n)), dim3(kBlock), 0,
+  hipLaunchKernelGGL(precision == GV_FP64 ? k_step_nav<false> : k_step_nav<true>, dim3(grid_for(n)), dim3(kBlock), 0,
                      (hipStream_t)stream, g->dg, n, x, y, z, dx, dy, dz, pv, pstep, out_step, out_next_pv, out_flags);
   return launched(fn);
 }
@@ -1034,7 +1034,8 @@ extern "C" int nav_transport(gv_geom* g, int64_t n, const double* x, const doubl
   if (n >= kBasketMin && n <= (1L << 30) && g->n_lv <= 4096)
     return basket_transport(g, n, x, y, z, dx, dy, dz, start_pv, max_steps, out_pv, out_step, out_nsteps, out_flags,
                             precision == GV_FP32_REFINE, (hipStream_t)stream);
-  hipLaunchKernelGGL(precision == GV_FP64 ? k_transport_lane : k_transport_lane_scr, dim3(grid_for(n)), dim3(kBlock),
+  hipLaunchKernelGGL(precision == GV_FP64 ? k_transport_lane<false> : k_transport_lane<true>, dim3(grid_for(n)),
+                     dim3(kBlock),
                      0, (hipStream_t)stream, g->dg, n, x, y, z, dx, dy, dz, start_pv, (int)max_steps, out_pv,
                      out_step, out_nsteps, out_flags);
   return launched(fn);

@@ -55,48 +55,6 @@ __device__ __forceinline__ V3 to_child_d(CQ X, V3 d) {
 
 constexpr uint32_t kFlagOverflow = 1u, kFlagStuck = 2u, kFlagLocateFail = 4u;
 
-// One ComputeStep for a track in placed volume pv.  Returns the step length;
-// *next receives the next PV (pv itself when the physics length wins, a
-// daughter, the parent, or -1 on leaving the world).
-__device__ __forceinline__ double compute_step(const DevGeom& G, int pv, V3 p, V3 d, double pstep, int* next,
-                                               uint32_t* flags) {
-  int lv = G.pv_lv[pv];
-  CQ X = G.pv_gxf + 12 * (size_t)pv;
-  V3 pl = to_child_p(X, p), dl = to_child_d(X, d);
-  double dout = solid_dist_out(G.lv_type[lv], G.par + G.lv_par[lv], pl, dl);
-  if (dout < 0.0) {
-    dout = 0.0;
-    *flags |= kFlagLocateFail;
-  }
-  double best = GV_INF;
-  int bestk = -1;
-  int off = G.lv_dau_off[lv], cnt = G.lv_dau_cnt[lv];
-  for (int k = 0; k < cnt; ++k) {
-    CQ Y = G.dau_xf + 12 * (size_t)(off + k);
-    int clv = G.dau_lv[off + k];
-    V3 pc = to_child_p(Y, pl), dc = to_child_d(Y, dl);
-    double t = solid_dist_in(G.lv_type[clv], G.par + G.lv_par[clv], pc, dc);
-    if (t < 0.0) {
-      t = 0.0;
-      *flags |= kFlagLocateFail;
-    }
-    if (t < best) {
-      best = t;
-      bestk = k;
-    }
-  }
-  if (pstep < best && pstep < dout) {
-    *next = pv;
-    return pstep;
-  }
-  if (bestk >= 0 && best <= dout) {
-    *next = G.pv_child[G.pv_child_off[pv] + bestk];
-    return best;
-  }
-  *next = G.pv_parent[pv];
-  return dout;
-}
-
 __device__ __forceinline__ int locate(const DevGeom& G, V3 p) {
   int lv0 = G.pv_lv[0];
   if (code_of(solid_sgn(G.lv_type[lv0], G.par + G.lv_par[lv0], p)) == kOutside) return -1;

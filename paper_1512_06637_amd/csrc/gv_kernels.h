@@ -79,27 +79,6 @@ __global__ void k_locate(DevGeom G, int64_t n, const double* __restrict__ x, con
   for (int64_t i = gtid(); i < n; i += gstride()) out[i] = locate(G, ld3(x, y, z, i));
 }
 
-__global__ void k_step(DevGeom G, int64_t n, const double* __restrict__ x, const double* __restrict__ y,
-                       const double* __restrict__ z, const double* __restrict__ dx, const double* __restrict__ dy,
-                       const double* __restrict__ dz, const int32_t* __restrict__ pv,
-                       const double* __restrict__ pstep, double* __restrict__ out_step,
-                       int32_t* __restrict__ out_next, uint32_t* __restrict__ out_flags) {
-  for (int64_t i = gtid(); i < n; i += gstride()) {
-    int v = pv[i];
-    uint32_t fl = 0;
-    int nx = -1;
-    double st = 0.0;
-    if (v >= 0 && v < G.n_pv) {
-      st = compute_step(G, v, ld3(x, y, z, i), ld3(dx, dy, dz, i), pstep ? pstep[i] : GV_INF, &nx, &fl);
-    } else {
-      fl = kFlagLocateFail;
-    }
-    out_step[i] = st;
-    out_next[i] = nx;
-    if (out_flags) out_flags[i] = fl;
-  }
-}
-
 __global__ void k_nav_safety(DevGeom G, int64_t n, const double* __restrict__ x, const double* __restrict__ y,
                              const double* __restrict__ z, const int32_t* __restrict__ pv, double* __restrict__ out) {
   for (int64_t i = gtid(); i < n; i += gstride()) {
@@ -127,48 +106,6 @@ __global__ void k_nav_inside(DevGeom G, int64_t n, const double* __restrict__ x,
 __device__ __forceinline__ V3 advance(V3 p, double s, V3 d) {
 #pragma clang fp contract(off)
   return V3{p.x + s * d.x, p.y + s * d.y, p.z + s * d.z};
-}
-
-// Whole-track transport, one lane per track, until the track leaves the world.
-__global__ void k_transport_lane(DevGeom G, int64_t n, const double* __restrict__ x, const double* __restrict__ y,
-                                 const double* __restrict__ z, const double* __restrict__ dx,
-                                 const double* __restrict__ dy, const double* __restrict__ dz,
-                                 const int32_t* __restrict__ start_pv, int max_steps, int32_t* __restrict__ out_pv,
-                                 double* __restrict__ out_step, int32_t* __restrict__ out_nsteps,
-                                 uint32_t* __restrict__ out_flags) {
-  for (int64_t i = gtid(); i < n; i += gstride()) {
-    V3 p = ld3(x, y, z, i), d = ld3(dx, dy, dz, i);
-    uint32_t fl = 0;
-    int pv = start_pv ? start_pv[i] : locate(G, p);
-    if (pv < -1 || pv >= G.n_pv) {
-      pv = -1;
-      fl |= kFlagLocateFail;
-    }
-    int32_t* rp = out_pv + (size_t)i * (max_steps + 1);
-    double* rs = out_step + (size_t)i * max_steps;
-    rp[0] = pv;
-    int k = 0;
-    if (pv >= 0) {
-      int zero_run = 0, nx = pv;
-      while (k < max_steps) {
-        double st = compute_step(G, pv, p, d, GV_INF, &nx, &fl);
-        p = advance(p, st, d);
-        rs[k] = st;
-        rp[k + 1] = nx;
-        ++k;
-        if (nx < 0) break;
-        zero_run = st < kTol ? zero_run + 1 : 0;
-        if (zero_run >= 8) {
-          fl |= kFlagStuck;
-          break;
-        }
-        pv = nx;
-      }
-      if (k == max_steps && nx >= 0 && !(fl & kFlagStuck)) fl |= kFlagOverflow;
-    }
-    out_nsteps[i] = k;
-    out_flags[i] = fl;
-  }
 }
 
 }  // namespace gv

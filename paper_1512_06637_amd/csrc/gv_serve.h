@@ -74,7 +74,8 @@ __global__ void __launch_bounds__(256) k_serve(DevGeom G, const SDesc* __restric
       int nx = -1;
       double st = 0.0;
       if (v >= 0 && v < G.n_pv) {
-        st = prec == 0 ? compute_step(G, v, p, d, ps, &nx, &fl) : step_culled_limited<true>(G, v, p, d, ps, &nx, &fl, w);
+        st = prec == 0 ? step_culled_limited<false>(G, v, p, d, ps, &nx, &fl, w)
+                       : step_culled_limited<true>(G, v, p, d, ps, &nx, &fl, w);
       } else {
         fl = kFlagLocateFail;
       }

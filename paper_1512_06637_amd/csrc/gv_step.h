@@ -370,8 +370,10 @@ __device__ __forceinline__ double nav_safety_screened(const DevGeom& G, int pv, 
   return fmax(s, 0.0);
 }
 
-// ------------------------------------------------- per-lane kernels (FP32 screen)
-__global__ void k_step_scr(DevGeom G, int64_t n, const double* __restrict__ x, const double* __restrict__ y,
+// --------------------------------------------------------- per-lane kernels
+// ComputeStep for every track of a basket, each lane in its own volume.
+template <bool F32>
+__global__ void k_step_nav(DevGeom G, int64_t n, const double* __restrict__ x, const double* __restrict__ y,
                            const double* __restrict__ z, const double* __restrict__ dx, const double* __restrict__ dy,
                            const double* __restrict__ dz, const int32_t* __restrict__ pv,
                            const double* __restrict__ pstep, double* __restrict__ out_step,
@@ -383,8 +385,8 @@ __global__ void k_step_scr(DevGeom G, int64_t n, const double* __restrict__ x, c
     int nx = -1;
     double st = 0.0;
     if (v >= 0 && v < G.n_pv) {
-      st = step_culled_limited<true>(G, v, ld3(x, y, z, i), ld3(dx, dy, dz, i), pstep ? pstep[i] : GV_INF, &nx, &fl,
-                                     w);
+      st = step_culled_limited<F32>(G, v, ld3(x, y, z, i), ld3(dx, dy, dz, i), pstep ? pstep[i] : GV_INF, &nx, &fl,
+                                    w);
     } else {
       fl = kFlagLocateFail;
     }
@@ -403,8 +405,10 @@ __global__ void k_nav_safety_scr(DevGeom G, int64_t n, const double* __restrict_
   }
 }
 
-// Whole-track transport, one lane per track, with the culled FP32-screened step.
-__global__ void k_transport_lane_scr(DevGeom G, int64_t n, const double* __restrict__ x,
+// Whole-track transport, one lane per track, until the track leaves the world
+// (used for batches too small to fill the device with per-volume tiles).
+template <bool F32>
+__global__ void k_transport_lane(DevGeom G, int64_t n, const double* __restrict__ x,
                                      const double* __restrict__ y, const double* __restrict__ z,
                                      const double* __restrict__ dx, const double* __restrict__ dy,
                                      const double* __restrict__ dz, const int32_t* __restrict__ start_pv,
@@ -426,7 +430,7 @@ __global__ void k_transport_lane_scr(DevGeom G, int64_t n, const double* __restr
     if (pv >= 0) {
       int zero_run = 0, nx = pv;
       while (k < max_steps) {
-        double st = step_culled<true>(G, G.pv_lv[pv], pv, p, d, &nx, &fl, w);
+        double st = step_culled<F32>(G, G.pv_lv[pv], pv, p, d, &nx, &fl, w);
         p = advance(p, st, d);
         rs[k] = st;
         rp[k + 1] = nx;

@@ -182,13 +182,15 @@ def main():
     ap.add_argument("--loads", type=float, nargs="+", default=[0.5, 0.8, 0.95])
     ap.add_argument("--budget-mib", type=int, default=256)
     ap.add_argument("--no-serial", action="store_true")
+    ap.add_argument("--streams", type=int, default=2)
+    ap.add_argument("--slots", type=int, default=64)
     args = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
     g = Geometry(W.detector_blob())
     t0 = time.perf_counter()
     r = run(g, loads=args.loads, n_baskets=args.baskets, serial=not args.no_serial,
-            hbm_budget=args.budget_mib << 20)
+            hbm_budget=args.budget_mib << 20, nstreams=args.streams, slots=args.slots)
     r["wall_s"] = time.perf_counter() - t0
     g.close()
     print(json.dumps(r), flush=True)
