@@ -55,6 +55,11 @@ def lib():
             "orc_nav_inside": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, C.c_int]),
             "orc_transport": (C.c_int, [_P, _I64] + [_P] * 7 + [C.c_int] + [_P] * 5 + [C.c_int]),
             "orc_max_threads": (C.c_int, []),
+            "orc_philox": (None, [_P, _P, _P]),
+            "orc_uniform": (C.c_double, [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32]),
+            "orc_phys_length": (C.c_int, [C.c_int, C.c_int, _P, _P, _I64, _P, C.c_uint64, _P, _P, _P, _P]),
+            "orc_transport_phys": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P, _I64] + [_P] * 7
+                                   + [C.c_int, C.c_uint64] + [_P] * 6 + [C.c_int]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -229,3 +234,53 @@ class Geometry:
                                  _ptr(ns), _ptr(fl), _ptr(dg), threads or default_threads())
         assert rc == 0
         return {"pv": pv, "step": stp, "nsteps": ns, "flags": fl, "diag": dg}
+
+    def transport_phys(self, tracks, materials, seed, start_pv=None, max_steps=128, threads=None):
+        """Physics-limited transport (materials: dict density[n_mat], sigma[n_mat][n_proc],
+        lv_mat[n_lv]); adds proc[n, max_steps] (int8: process of a physics-limited
+        step, -1 for a boundary step; -2 past the last step)."""
+        a = [_f64(v) for v in tracks.arrays()]
+        n = a[0].shape[0]
+        den = _f64(materials["density"])
+        sig = np.ascontiguousarray(materials["sigma"], np.float64)
+        lvm = np.ascontiguousarray(materials["lv_mat"], np.int32)
+        sp = None if start_pv is None else np.ascontiguousarray(start_pv, np.int32)
+        pv = np.full((n, max_steps + 1), -2, np.int32)
+        stp = np.full((n, max_steps), np.nan, np.float64)
+        pr = np.full((n, max_steps), -2, np.int8)
+        ns = np.zeros(n, np.int32)
+        fl = np.zeros(n, np.uint32)
+        dg = np.zeros(n, np.uint32)
+        rc = lib().orc_transport_phys(self._h, den.shape[0], sig.shape[1], _ptr(den), _ptr(sig), _ptr(lvm), n,
+                                      *[_ptr(v) for v in a], _ptr(sp), max_steps, int(seed), _ptr(pv), _ptr(stp),
+                                      _ptr(pr), _ptr(ns), _ptr(fl), _ptr(dg), threads or default_threads())
+        assert rc == 0
+        return {"pv": pv, "step": stp, "proc": pr, "nsteps": ns, "flags": fl, "diag": dg}
+
+
+def philox4x32_10(ctr, key):
+    """One Philox4x32-10 block: four 32-bit words from counter[4] and key[2]."""
+    c = np.ascontiguousarray(ctr, np.uint32)
+    k = np.ascontiguousarray(key, np.uint32)
+    o = np.zeros(4, np.uint32)
+    lib().orc_philox(_ptr(c), _ptr(k), _ptr(o))
+    return o
+
+
+def uniform(seed, track, step, proc):
+    return lib().orc_uniform(int(seed), int(track), int(step), int(proc))
+
+
+def phys_length(materials, mat, seed, track, step):
+    """Shortest sampled interaction length (and its process) per entry."""
+    den = _f64(materials["density"])
+    sig = np.ascontiguousarray(materials["sigma"], np.float64)
+    mat = np.ascontiguousarray(mat, np.int32)
+    tr = np.ascontiguousarray(track, np.uint32)
+    st = np.ascontiguousarray(step, np.uint32)
+    out = np.empty(mat.shape[0], np.float64)
+    pr = np.empty(mat.shape[0], np.int32)
+    rc = lib().orc_phys_length(den.shape[0], sig.shape[1], _ptr(den), _ptr(sig), mat.shape[0], _ptr(mat), int(seed),
+                               _ptr(tr), _ptr(st), _ptr(out), _ptr(pr))
+    assert rc == 0
+    return out, pr

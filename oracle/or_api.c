@@ -207,4 +207,56 @@ int orc_transport(void* h, int64_t n, const double* x, const double* y, const do
   return 0;
 }
 
+/* Philox4x32-10 block (for its known-answer checks) and the uniform draw */
+void orc_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out) { or_philox4x32_10(ctr, key, out); }
+double orc_uniform(uint64_t seed, uint32_t track, uint32_t step, uint32_t proc) {
+  return or_uniform(seed, track, step, proc);
+}
+
+/* Shortest sampled interaction length for each (material, track, step) triple */
+int orc_phys_length(int n_mat, int n_proc, const double* density, const double* sigma, int64_t n,
+                    const int32_t* mat, uint64_t seed, const uint32_t* track, const uint32_t* step, double* out,
+                    int32_t* out_proc) {
+  or_phys ph = {n_mat, n_proc, density, sigma, NULL};
+  for (int64_t i = 0; i < n; ++i) {
+    if (mat[i] < 0 || mat[i] >= n_mat) return -1;
+    int pr = -1;
+    out[i] = or_phys_length(&ph, mat[i], seed, track[i], step[i], &pr);
+    out_proc[i] = pr;
+  }
+  return 0;
+}
+
+/* Physics-limited transport; track i draws with counter track = i.
+ * out_proc: n x max_steps int8 (nullable): process of a physics-limited step,
+ * -1 for a step that ends on a boundary. */
+int orc_transport_phys(void* h, int n_mat, int n_proc, const double* density, const double* sigma,
+                       const int32_t* lv_mat, int64_t n, const double* x, const double* y, const double* z,
+                       const double* dx, const double* dy, const double* dz, const int32_t* start_pv, int max_steps,
+                       uint64_t seed, int32_t* out_pv, double* out_step, int8_t* out_proc, int32_t* out_nsteps,
+                       uint32_t* out_flags, uint32_t* out_diag, int nthreads) {
+  or_geom* g = (or_geom*)h;
+  if (max_steps < 1 || n_mat < 1 || n_proc < 1) return -1;
+  for (int i = 0; i < g->n_lv; ++i)
+    if (lv_mat[i] < 0 || lv_mat[i] >= n_mat) return -1;
+  if (start_pv)
+    for (int64_t i = 0; i < n; ++i)
+      if (start_pv[i] < -1 || start_pv[i] >= g->n_pv) return -1;
+  or_phys ph = {n_mat, n_proc, density, sigma, lv_mat};
+#pragma omp parallel for schedule(static, 256) num_threads(nthr(nthreads))
+  for (int64_t i = 0; i < n; ++i) {
+    double p[3] = {x[i], y[i], z[i]}, d[3] = {dx[i], dy[i], dz[i]};
+    unsigned fl = 0, dg = 0;
+    int pv0 = start_pv ? start_pv[i] : or_locate(g, p);
+    int32_t* rp = out_pv + (size_t)i * (max_steps + 1);
+    double* rs = out_step + (size_t)i * max_steps;
+    int8_t* rq = out_proc ? out_proc + (size_t)i * max_steps : NULL;
+    int k = or_transport_phys(g, &ph, p, d, pv0, max_steps, seed, (uint32_t)i, rp, rs, rq, &fl, &dg);
+    out_nsteps[i] = k;
+    if (out_flags) out_flags[i] = fl;
+    if (out_diag) out_diag[i] = dg;
+  }
+  return 0;
+}
+
 int orc_max_threads(void) { return omp_get_max_threads(); }

@@ -116,4 +116,19 @@ int or_transport(const or_geom* g, const double p0[3], const double d[3], int st
                  int max_steps, int32_t* out_pv, double* out_step, unsigned* flags,
                  unsigned* diag);
 
+/* ------------------------------------------------------ physics-limited steps */
+typedef struct {
+  int n_mat, n_proc;
+  const double* density; /* [n_mat] number density n of each material */
+  const double* sigma;   /* [n_mat][n_proc] cross section of each process */
+  const int* lv_mat;     /* [n_lv] material of each logical volume */
+} or_phys;
+
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+double or_uniform(uint64_t seed, uint32_t track, uint32_t step, uint32_t proc);
+double or_phys_length(const or_phys* ph, int mat, uint64_t seed, uint32_t track, uint32_t step, int* proc);
+int or_transport_phys(const or_geom* g, const or_phys* ph, const double p0[3], const double d[3],
+                      int start_pv, int max_steps, uint64_t seed, uint32_t track, int32_t* out_pv,
+                      double* out_step, int8_t* out_proc, unsigned* flags, unsigned* diag);
+
 #endif

@@ -217,6 +217,22 @@ def detector_description():
     return lvs, info
 
 
+def detector_materials() -> dict:
+    """Synthetic materials of the layered detector for physics-limited steps:
+    number density n and cross sections sigma of three processes per material,
+    so that the mean free paths 1 / (n sigma) are 2e5, 5e5, 1e6 mm in the world,
+    5e3, 2e4, 1e5 mm in the layers and 60, 150, 400 mm in the modules."""
+    density = np.array([1.0, 1.0, 8.0])
+    sigma = np.array([[5e-6, 2e-6, 1e-6],
+                      [2e-4, 5e-5, 1e-5],
+                      [1.0 / 480.0, 1.0 / 1200.0, 1.0 / 3200.0]])
+    lv_mat = np.array([0] + [1, 2] * N_LAYERS, np.int32)  # world, then (layer, module) per layer
+    return {"density": density, "sigma": sigma, "lv_mat": lv_mat}
+
+
+PHYS_SEED = SEED_BASE + 6  # key of the physics draws of the detector workload
+
+
 def detector_blob() -> bytes:
     return make_blob(detector_description()[0])
 
