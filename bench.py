@@ -221,6 +221,46 @@ def cpu_baseline_solids(protocol, max_s=1.0):
             "solids": full, "protocol": proto}
 
 
+def phys_leg(g, a, args, max_steps=256):
+    """Physics-limited transport of the same tracks (synthetic materials: mean
+    free paths 60-400 mm in the modules, 5e3-1e5 mm in the layers, 2e5-1e6 mm
+    in the world), with and without the safety short-cut."""
+    import torch
+
+    from paper_1512_06637_amd import workloads as W
+
+    m = W.detector_materials()
+    g.set_materials(m["density"], m["sigma"], m["lv_mat"])
+    n = a[0].shape[0]
+    out = {"pv": torch.empty((n, max_steps + 1), dtype=torch.int32, device="cuda"),
+           "step": torch.empty((n, max_steps), dtype=torch.float64, device="cuda"),
+           "proc": torch.empty((n, max_steps), dtype=torch.int8, device="cuda"),
+           "nsteps": torch.empty(n, dtype=torch.int32, device="cuda"),
+           "flags": torch.empty(n, dtype=torch.int32, device="cuda")}
+    res = {}
+    for short in (True, False):
+        for _ in range(args.warmup):
+            g.transport_phys(*a, W.PHYS_SEED, max_steps=max_steps, out=out, shortcut=short)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(args.steps):
+            g.transport_phys(*a, W.PHYS_SEED, max_steps=max_steps, out=out, shortcut=short)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.steps
+        g.profile(True)
+        g.transport_phys(*a, W.PHYS_SEED, max_steps=max_steps, out=out, shortcut=short)
+        _, _, work = g.profile_read()
+        g.profile(False)
+        total = int(out["nsteps"].sum())
+        res["shortcut" if short else "no_shortcut"] = {
+            "ms_per_step": ms, "track_steps_per_s": total / (ms * 1e-3), "track_steps": total,
+            "physics_limited_steps": work[22], "shortcut_steps": work[23]}
+    return res
+
+
 def fp32_leg(g, a, ref, max_steps, args, ms64):
     """The same workload with precision FP32_REFINE (FP32 daughter screens, FP64
     distances): time per call, whether every output equals the FP64 run's, and
@@ -270,6 +310,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-screen + FP64-refine leg")
     ap.add_argument("--no-solids", action="store_true", help="skip the solid-level legs")
+    ap.add_argument("--no-phys", action="store_true", help="skip the physics-limited transport leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 256 MiB device to device (a kernel of known traffic for counter scaling)")
     args = ap.parse_args()
@@ -364,6 +405,8 @@ def main():
     }
     if not args.no_fp32:
         res["fp32_refine"] = fp32_leg(g, a, out, max_steps, args, ms)
+    if not args.no_phys:
+        res["physics_limited"] = phys_leg(g, a, args)
     g.close()
     del out, a
     if not args.no_solids:

@@ -168,6 +168,38 @@ int nav_transport(gv_geom* g, int64_t n, const double* x, const double* y, const
                   int32_t max_steps, int32_t* out_pv, double* out_step, int32_t* out_nsteps,
                   uint32_t* out_flags, int32_t precision, void* stream);
 
+/* ------------------------------------------------- physics-limited transport */
+/* Materials for physics-limited steps: n_mat materials with number density
+ * density[m] and, for each of n_proc (1..16) processes, a cross section
+ * sigma[m][p] (host arrays, row-major), and the material of every logical
+ * volume, lv_material[n_lv].  The mean free path of process p in material m is
+ * 1 / (density[m] sigma[m][p]) (Sec. II, Eq. (1)); units such that it comes out
+ * in mm.  Copied to the device; replaces earlier tables.  Errors: GV_EINVAL for
+ * negative or non-finite values or a material index out of range. */
+int geom_set_materials(gv_geom* g, int32_t n_mat, int32_t n_proc, const double* density, const double* sigma,
+                       const int32_t* lv_material);
+
+#define GV_PHYS_SAFETY_SHORTCUT 1 /* nav_transport_phys option */
+
+/* Transport with physics-limited steps (Sec. II: the process with the shortest
+ * sampled interaction length acts unless the border is nearer; the lengths are
+ * drawn again in every volume).  At step k of track i every process p draws
+ * s_p = -ln(u) / (density sigma_p) of the current volume's material, u in
+ * (0, 1) from Philox4x32-10 (Salmon et al., SC'11) with counter (i, k, p, 0) and
+ * key (seed & 0xffffffff, seed >> 32), u = ((w0 << 32 | w1) >> 11 + 0.5) 2^-53
+ * of the first two output words; the shortest is the proposed step of
+ * basket_step.  The direction does not change (no physics action).  Outputs as
+ * nav_transport, plus out_proc [n][max_steps] int8 (nullable): the process of
+ * a physics-limited step, -1 for a step that ends on a boundary.  Option
+ * GV_PHYS_SAFETY_SHORTCUT takes a physics step without any geometry when it is
+ * shorter (by kTolerance) than the distance still to go along the unchanged
+ * direction to the boundary found by the last full step; the outputs do not
+ * change.  GV_ESTATE without materials. */
+int nav_transport_phys(gv_geom* g, int64_t n, const double* x, const double* y, const double* z,
+                       const double* dx, const double* dy, const double* dz, const int32_t* start_pv,
+                       int32_t max_steps, uint64_t seed, int32_t* out_pv, double* out_step, int8_t* out_proc,
+                       int32_t* out_nsteps, uint32_t* out_flags, int32_t options, int32_t precision, void* stream);
+
 /* ------------------------------------------------------------ measurement */
 
 /* Kernel timing for measurement.  While enabled, nav_transport records a pair
@@ -175,11 +207,12 @@ int nav_transport(gv_geom* g, int64_t n, const double* x, const double* y, const
  * kernel.  gv_profile_read waits for those events and returns the summed
  * kernel milliseconds and the number of launches since the last read (then
  * forgets them), and, if `work` is not NULL, the operation counts of the last
- * basket transport (host array of 22 uint64: [0] steps taken, [1] daughter
+ * basket transport (host array of 24 uint64: [0] steps taken, [1] daughter
  * bounding-box tests, [2+t] daughter lower-bound checks, [8+t] daughter
  * DistanceToIn evaluations in culled loops, [14+t] DistanceToIn evaluations in
  * plain loops, t = daughter solid type 0..5, [20] track-steps of culled loops
- * screened in FP32, [21] those screened in FP64).  Reading synchronises the
+ * screened in FP32, [21] those screened in FP64, [22] physics-limited steps,
+ * [23] of which taken by the safety short-cut).  Reading synchronises the
  * device. */
 int gv_profile(gv_geom* g, int enable);
 int gv_profile_read(gv_geom* g, double* step_ms, int64_t* step_launches, uint64_t* work);

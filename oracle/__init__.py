@@ -59,7 +59,7 @@ def lib():
             "orc_uniform": (C.c_double, [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32]),
             "orc_phys_length": (C.c_int, [C.c_int, C.c_int, _P, _P, _I64, _P, C.c_uint64, _P, _P, _P, _P]),
             "orc_transport_phys": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P, _I64] + [_P] * 7
-                                   + [C.c_int, C.c_uint64] + [_P] * 6 + [C.c_int]),
+                                   + [C.c_int, C.c_uint64] + [_P] * 7 + [C.c_int]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -235,10 +235,11 @@ class Geometry:
         assert rc == 0
         return {"pv": pv, "step": stp, "nsteps": ns, "flags": fl, "diag": dg}
 
-    def transport_phys(self, tracks, materials, seed, start_pv=None, max_steps=128, threads=None):
+    def transport_phys(self, tracks, materials, seed, start_pv=None, max_steps=128, track_id=None, threads=None):
         """Physics-limited transport (materials: dict density[n_mat], sigma[n_mat][n_proc],
         lv_mat[n_lv]); adds proc[n, max_steps] (int8: process of a physics-limited
-        step, -1 for a boundary step; -2 past the last step)."""
+        step, -1 for a boundary step; -2 past the last step).  track_id: the
+        counters of the tracks' draws (default 0 .. n-1)."""
         a = [_f64(v) for v in tracks.arrays()]
         n = a[0].shape[0]
         den = _f64(materials["density"])
@@ -251,8 +252,10 @@ class Geometry:
         ns = np.zeros(n, np.int32)
         fl = np.zeros(n, np.uint32)
         dg = np.zeros(n, np.uint32)
+        tid = None if track_id is None else np.ascontiguousarray(track_id, np.uint32)
         rc = lib().orc_transport_phys(self._h, den.shape[0], sig.shape[1], _ptr(den), _ptr(sig), _ptr(lvm), n,
-                                      *[_ptr(v) for v in a], _ptr(sp), max_steps, int(seed), _ptr(pv), _ptr(stp),
+                                      *[_ptr(v) for v in a], _ptr(sp), max_steps, int(seed), _ptr(tid), _ptr(pv),
+                                      _ptr(stp),
                                       _ptr(pr), _ptr(ns), _ptr(fl), _ptr(dg), threads or default_threads())
         assert rc == 0
         return {"pv": pv, "step": stp, "proc": pr, "nsteps": ns, "flags": fl, "diag": dg}

@@ -227,13 +227,14 @@ int orc_phys_length(int n_mat, int n_proc, const double* density, const double* 
   return 0;
 }
 
-/* Physics-limited transport; track i draws with counter track = i.
+/* Physics-limited transport; track i draws with counter track = track_id[i]
+ * (track_id NULL: i), so a sample of a batch draws what it drew in the batch.
  * out_proc: n x max_steps int8 (nullable): process of a physics-limited step,
  * -1 for a step that ends on a boundary. */
 int orc_transport_phys(void* h, int n_mat, int n_proc, const double* density, const double* sigma,
                        const int32_t* lv_mat, int64_t n, const double* x, const double* y, const double* z,
                        const double* dx, const double* dy, const double* dz, const int32_t* start_pv, int max_steps,
-                       uint64_t seed, int32_t* out_pv, double* out_step, int8_t* out_proc, int32_t* out_nsteps,
+                       uint64_t seed, const uint32_t* track_id, int32_t* out_pv, double* out_step, int8_t* out_proc, int32_t* out_nsteps,
                        uint32_t* out_flags, uint32_t* out_diag, int nthreads) {
   or_geom* g = (or_geom*)h;
   if (max_steps < 1 || n_mat < 1 || n_proc < 1) return -1;
@@ -251,7 +252,8 @@ int orc_transport_phys(void* h, int n_mat, int n_proc, const double* density, co
     int32_t* rp = out_pv + (size_t)i * (max_steps + 1);
     double* rs = out_step + (size_t)i * max_steps;
     int8_t* rq = out_proc ? out_proc + (size_t)i * max_steps : NULL;
-    int k = or_transport_phys(g, &ph, p, d, pv0, max_steps, seed, (uint32_t)i, rp, rs, rq, &fl, &dg);
+    const uint32_t tid = track_id ? track_id[i] : (uint32_t)i;
+    int k = or_transport_phys(g, &ph, p, d, pv0, max_steps, seed, tid, rp, rs, rq, &fl, &dg);
     out_nsteps[i] = k;
     if (out_flags) out_flags[i] = fl;
     if (out_diag) out_diag[i] = dg;

@@ -21,7 +21,8 @@ OUTSIDE, SURFACE, INSIDE = 0, 1, 2
 TO_IN, TO_OUT = 0, 1
 SAFETY_AUTO, SAFETY_IN, SAFETY_OUT = 0, 1, 2
 FP64, FP32_REFINE = 0, 1
-WORK_N = 22  # work counters returned by gv_profile_read
+WORK_N = 24  # work counters returned by gv_profile_read
+PHYS_SAFETY_SHORTCUT = 1
 FLAG_OVERFLOW, FLAG_STUCK, FLAG_LOCATE_FAIL = 1, 2, 4
 
 _P = C.c_void_p
@@ -42,6 +43,8 @@ _SIGS = {
     "nav_transport": [_P, _I64] + [_P] * 7 + [_I32] + [_P] * 4 + [_I32, _P],
     "gv_profile": [_P, C.c_int],
     "gv_profile_read": [_P, _P, _P, _P],
+    "geom_set_materials": [_P, _I32, _I32, _P, _P, _P],
+    "nav_transport_phys": [_P, _I64] + [_P] * 7 + [_I32, C.c_uint64] + [_P] * 5 + [_I32, _I32, _P],
     "gv_server_create": [_P, _I32, _I64, _I32, C.POINTER(_P)],
     "gv_server_submit": [_P, _I32, _I32, _I64, _P, _P, _P],
     "gv_server_poll": [_P, _I32, _P, _P, _P],
@@ -250,12 +253,48 @@ class Geometry:
         """(step-kernel ms, launches, work counts: [0] steps, [1] bounding-box tests,
         [2+t] lower-bound checks, [8+t] culled DistanceToIn, [14+t] plain DistanceToIn,
         t = daughter solid type, [20] culled track-steps screened in FP32, [21] culled
-        track-steps screened in FP64)."""
+        track-steps screened in FP64, [22] physics-limited steps, [23] of which taken
+        by the safety short-cut)."""
         ms = C.c_double(0.0)
         launches = C.c_int64(0)
         work = (C.c_uint64 * WORK_N)()
         _check("gv_profile_read", lib().gv_profile_read(self._h, C.byref(ms), C.byref(launches), work))
         return ms.value, launches.value, list(work)
+
+    def set_materials(self, density, sigma, lv_material):
+        """Materials for physics-limited transport (host arrays)."""
+        import numpy as np
+        den = np.ascontiguousarray(density, np.float64)
+        sig = np.ascontiguousarray(sigma, np.float64)
+        lvm = np.ascontiguousarray(lv_material, np.int32)
+        if sig.ndim != 2 or sig.shape[0] != den.shape[0]:
+            raise ValueError("sigma must be [n_mat][n_proc]")
+        _check("geom_set_materials", lib().geom_set_materials(
+            self._h, den.shape[0], sig.shape[1], C.c_void_p(den.ctypes.data), C.c_void_p(sig.ctypes.data),
+            C.c_void_p(lvm.ctypes.data)))
+
+    def transport_phys(self, x, y, z, dx, dy, dz, seed, start_pv=None, max_steps=128, out=None, shortcut=True,
+                       precision=FP64):
+        """Physics-limited transport; dict as transport() plus proc [n, max_steps] int8."""
+        torch = _torch()
+        n = _n(x, y, z, dx, dy, dz, start_pv)
+        f64 = torch.float64
+        if out is None:
+            out = {
+                "pv": torch.full((n, max_steps + 1), -2, dtype=torch.int32, device=x.device),
+                "step": torch.full((n, max_steps), float("nan"), dtype=f64, device=x.device),
+                "proc": torch.full((n, max_steps), -2, dtype=torch.int8, device=x.device),
+                "nsteps": torch.empty(n, dtype=torch.int32, device=x.device),
+                "flags": torch.empty(n, dtype=torch.int32, device=x.device),
+            }
+        a = [_dev(v, f64, nm) for v, nm in zip((x, y, z, dx, dy, dz), ("x", "y", "z", "dx", "dy", "dz"))]
+        _check("nav_transport_phys", lib().nav_transport_phys(
+            self._h, n, *a, _opt(start_pv, torch.int32, "start_pv"), max_steps, int(seed),
+            _dev(out["pv"], torch.int32, "pv", n * (max_steps + 1)), _dev(out["step"], f64, "step", n * max_steps),
+            _opt(out.get("proc"), torch.int8, "proc", n * max_steps), _dev(out["nsteps"], torch.int32, "nsteps", n),
+            _dev(out["flags"], torch.int32, "flags", n), PHYS_SAFETY_SHORTCUT if shortcut else 0, precision,
+            _stream()))
+        return out
 
     def transport(self, x, y, z, dx, dy, dz, start_pv=None, max_steps=128, out=None, precision=FP64):
         """Returns dict(pv [n, max_steps+1] int32, step [n, max_steps] f64, nsteps, flags)."""

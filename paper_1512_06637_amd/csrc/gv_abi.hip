@@ -55,6 +55,8 @@ struct gv_geom {
   void* ob = nullptr;       // staged outputs: ob_step [ob_steps][cap] double, then ob_pv [ob_steps][cap] int
   double* ob_step = nullptr;
   int* ob_pv = nullptr;
+  int8_t* ob_proc = nullptr;
+  void* mat_mem = nullptr;  // device material tables (geom_set_materials)
   int64_t ob_cap = 0, ob_steps = 0;
   int* h_live = nullptr;  // [2] pinned, mapped host copies of the live count
   int* d_live = nullptr;  // device address of h_live
@@ -556,6 +558,7 @@ extern "C" int geom_free(gv_geom* g) {
   hipError_t e = hipDeviceSynchronize();
   if (g->ws) (void)hipFree(g->ws);
   if (g->ob) (void)hipFree(g->ob);
+  if (g->mat_mem) (void)hipFree(g->mat_mem);
   if (g->dmem) (void)hipFree(g->dmem);
   if (g->h_live) (void)hipHostFree(g->h_live);
   for (auto& ev : g->prof_ev) (void)hipEventDestroy(ev);
@@ -895,7 +898,7 @@ int ensure_workspace(gv_geom* g, int64_t n) {
 constexpr size_t kStageMaxBytes = (size_t)8 << 30;
 bool ensure_staging(gv_geom* g, int64_t steps) {
   const int64_t cap = g->ws_tracks;
-  const size_t bytes = (size_t)cap * (size_t)steps * 12;
+  const size_t bytes = (size_t)cap * (size_t)steps * 13;
   if (bytes > kStageMaxBytes) return false;
   if (g->ob && g->ob_cap >= cap && g->ob_steps >= steps) return true;
   if (g->ob) {
@@ -904,15 +907,18 @@ bool ensure_staging(gv_geom* g, int64_t steps) {
     g->ob = nullptr;
     g->ob_step = nullptr;
     g->ob_pv = nullptr;
+    g->ob_proc = nullptr;
     g->ob_cap = g->ob_steps = 0;
   }
-  if (hipMalloc(&g->ob, al256((size_t)cap * steps * 8) + (size_t)cap * steps * 4) != hipSuccess) {
+  const size_t b8 = al256((size_t)cap * steps * 8), b4 = al256((size_t)cap * steps * 4);
+  if (hipMalloc(&g->ob, b8 + b4 + (size_t)cap * steps) != hipSuccess) {
     (void)hipGetLastError();
     g->ob = nullptr;
     return false;
   }
   g->ob_step = (double*)g->ob;
-  g->ob_pv = (int*)((char*)g->ob + al256((size_t)cap * steps * 8));
+  g->ob_pv = (int*)((char*)g->ob + b8);
+  g->ob_proc = (int8_t*)((char*)g->ob + b8 + b4);
   g->ob_cap = cap;
   g->ob_steps = steps;
   return true;
@@ -927,7 +933,8 @@ unsigned stream_grid(int64_t n) {
 
 int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, const double* z, const double* dx,
                      const double* dy, const double* dz, const int32_t* start_pv, int max_steps, int32_t* out_pv,
-                     double* out_step, int32_t* out_nsteps, uint32_t* out_flags, bool fp32, hipStream_t s) {
+                     double* out_step, int32_t* out_nsteps, uint32_t* out_flags, bool fp32, bool phys,
+                     PhysArgs P, int8_t* out_proc, hipStream_t s) {
   const char* fn = "nav_transport";
   GV_TRY(ensure_workspace(g, n));
   const int cb = coarse_bits(g->n_lv);
@@ -952,6 +959,9 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
   const bool staged = ensure_staging(g, max_steps);
   double* ob_step = staged ? g->ob_step : nullptr;
   int* ob_pv = staged ? g->ob_pv : nullptr;
+  int8_t* ob_proc = staged && phys && out_proc ? g->ob_proc : nullptr;
+  const auto step_kernel = fp32 ? (phys ? k_bt_step<true, true> : k_bt_step<true, false>)
+                                : (phys ? k_bt_step<false, true> : k_bt_step<false, false>);
   const int64_t max_tiles = n / kWave + g->n_lv + 1;
   const unsigned step_grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((max_tiles + 3) / 4, 1024));
   // The host enqueues steps in chunks of kChunk; at a chunk's end the index
@@ -976,9 +986,10 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
       g->prof_used += 2;
       (void)hipEventRecord(pe[0], s);
     }
-    hipLaunchKernelGGL(fp32 ? k_bt_step<true> : k_bt_step<false>, dim3(step_grid), dim3(kBlock), lds_step, s, g->dg,
-                       k, max_steps, cb, (const int*)g->idx[c], g->rec, (const int*)C.cnt[k0], g->nxt_lv, C.cnt[k1], C,
-                       out_pv, out_step, out_nsteps, out_flags, (const int*)g->slot_id, ob_step, ob_pv, g->ob_cap);
+    hipLaunchKernelGGL(step_kernel, dim3(step_grid), dim3(kBlock), lds_step, s, g->dg, k, max_steps, cb,
+                       (const int*)g->idx[c], g->rec, (const int*)C.cnt[k0], g->nxt_lv, C.cnt[k1], C, out_pv,
+                       out_step, out_nsteps, out_flags, (const int*)g->slot_id, ob_step, ob_pv, g->ob_cap, P,
+                       ob_proc, out_proc);
     GV_TRY(launched(fn));
     launched_steps = k + 1;
     if (pe) (void)hipEventRecord(pe[1], s);
@@ -1003,9 +1014,10 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
     }
   }
   if (staged && launched_steps > 0) {
-    hipLaunchKernelGGL(k_bt_emit, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, (const double*)ob_step,
-                       (const int*)ob_pv, g->ob_cap, (const int*)g->slot_id, C, max_steps, launched_steps,
-                       (const int32_t*)out_nsteps, out_step, out_pv);
+    hipLaunchKernelGGL(ob_proc ? k_bt_emit<true> : k_bt_emit<false>, dim3((unsigned)((n + 63) / 64)), dim3(256), 0,
+                       s, (const double*)ob_step,
+                       (const int*)ob_pv, (const int8_t*)ob_proc, g->ob_cap, (const int*)g->slot_id, C, max_steps,
+                       launched_steps, (const int32_t*)out_nsteps, out_step, out_pv, out_proc);
     GV_TRY(launched(fn));
   }
   return GV_OK;
@@ -1013,14 +1025,17 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
 
 }  // namespace
 
-extern "C" int nav_transport(gv_geom* g, int64_t n, const double* x, const double* y, const double* z,
-                             const double* dx, const double* dy, const double* dz, const int32_t* start_pv,
-                             int32_t max_steps, int32_t* out_pv, double* out_step, int32_t* out_nsteps,
-                             uint32_t* out_flags, int32_t precision, void* stream) {
-  const char* fn = "nav_transport";
+namespace {
+
+int transport_common(const char* fn, gv_geom* g, int64_t n, const double* x, const double* y, const double* z,
+                     const double* dx, const double* dy, const double* dz, const int32_t* start_pv,
+                     int32_t max_steps, int32_t* out_pv, double* out_step, int32_t* out_nsteps,
+                     uint32_t* out_flags, int32_t precision, bool phys, PhysArgs P, int8_t* out_proc,
+                     void* stream) {
   GV_TRY(check_common(fn, g, n));
   GV_TRY(check_nav_precision(fn, precision));
   if (max_steps < 1 || max_steps > 4096) return fail(GV_EINVAL, "%s: max_steps %d not in [1, 4096]", fn, max_steps);
+  if (phys && g->dg.n_mat < 1) return fail(GV_ESTATE, "%s: no materials (geom_set_materials first)", fn);
   if (n == 0) return GV_OK;
   const double* in[6] = {x, y, z, dx, dy, dz};
   const char* nm[6] = {"x", "y", "z", "dx", "dy", "dz"};
@@ -1031,14 +1046,78 @@ extern "C" int nav_transport(gv_geom* g, int64_t n, const double* x, const doubl
   GV_TRY(check_i32(fn, "out_nsteps", out_nsteps));
   GV_TRY(check_i32(fn, "out_flags", out_flags));
   DeviceGuard dgd(g->device);
+  const bool fp32 = precision == GV_FP32_REFINE;
   if (n >= kBasketMin && n <= (1L << 30) && g->n_lv <= 4096)
     return basket_transport(g, n, x, y, z, dx, dy, dz, start_pv, max_steps, out_pv, out_step, out_nsteps, out_flags,
-                            precision == GV_FP32_REFINE, (hipStream_t)stream);
-  hipLaunchKernelGGL(precision == GV_FP64 ? k_transport_lane<false> : k_transport_lane<true>, dim3(grid_for(n)),
-                     dim3(kBlock),
-                     0, (hipStream_t)stream, g->dg, n, x, y, z, dx, dy, dz, start_pv, (int)max_steps, out_pv,
-                     out_step, out_nsteps, out_flags);
+                            fp32, phys, P, out_proc, (hipStream_t)stream);
+  const auto lane = fp32 ? (phys ? k_transport_lane<true, true> : k_transport_lane<true, false>)
+                         : (phys ? k_transport_lane<false, true> : k_transport_lane<false, false>);
+  hipLaunchKernelGGL(lane, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, g->dg, n, x, y, z, dx, dy, dz,
+                     start_pv, (int)max_steps, out_pv, out_step, out_nsteps, out_flags, P, out_proc);
   return launched(fn);
+}
+
+}  // namespace
+
+extern "C" int nav_transport(gv_geom* g, int64_t n, const double* x, const double* y, const double* z,
+                             const double* dx, const double* dy, const double* dz, const int32_t* start_pv,
+                             int32_t max_steps, int32_t* out_pv, double* out_step, int32_t* out_nsteps,
+                             uint32_t* out_flags, int32_t precision, void* stream) {
+  return transport_common("nav_transport", g, n, x, y, z, dx, dy, dz, start_pv, max_steps, out_pv, out_step,
+                          out_nsteps, out_flags, precision, false, PhysArgs{0, 0}, nullptr, stream);
+}
+
+extern "C" int nav_transport_phys(gv_geom* g, int64_t n, const double* x, const double* y, const double* z,
+                                  const double* dx, const double* dy, const double* dz, const int32_t* start_pv,
+                                  int32_t max_steps, uint64_t seed, int32_t* out_pv, double* out_step,
+                                  int8_t* out_proc, int32_t* out_nsteps, uint32_t* out_flags, int32_t options,
+                                  int32_t precision, void* stream) {
+  if (options & ~GV_PHYS_SAFETY_SHORTCUT) return fail(GV_EINVAL, "nav_transport_phys: options %d", options);
+  return transport_common("nav_transport_phys", g, n, x, y, z, dx, dy, dz, start_pv, max_steps, out_pv, out_step,
+                          out_nsteps, out_flags, precision, true,
+                          PhysArgs{seed, (options & GV_PHYS_SAFETY_SHORTCUT) ? 1 : 0}, out_proc, stream);
+}
+
+extern "C" int geom_set_materials(gv_geom* g, int32_t n_mat, int32_t n_proc, const double* density,
+                                  const double* sigma, const int32_t* lv_material) {
+  const char* fn = "geom_set_materials";
+  if (!g) return fail(GV_EINVAL, "%s: geometry handle is NULL", fn);
+  if (n_mat < 1 || n_mat > 65536) return fail(GV_EINVAL, "%s: n_mat %d not in [1, 65536]", fn, n_mat);
+  if (n_proc < 1 || n_proc > kMaxProc) return fail(GV_EINVAL, "%s: n_proc %d not in [1, %d]", fn, n_proc, kMaxProc);
+  if (!density || !sigma || !lv_material) return fail(GV_EINVAL, "%s: NULL table", fn);
+  std::vector<double> rate((size_t)n_mat * n_proc);
+  for (int m = 0; m < n_mat; ++m) {
+    if (!(density[m] >= 0.0) || !std::isfinite(density[m])) return fail(GV_EINVAL, "%s: density[%d]", fn, m);
+    for (int i = 0; i < n_proc; ++i) {
+      const double sg = sigma[(size_t)m * n_proc + i];
+      if (!(sg >= 0.0) || !std::isfinite(sg)) return fail(GV_EINVAL, "%s: sigma[%d][%d]", fn, m, i);
+      rate[(size_t)m * n_proc + i] = density[m] * sg;  // n sigma = 1 / lambda (1/mm)
+    }
+  }
+  for (int l = 0; l < g->n_lv; ++l)
+    if (lv_material[l] < 0 || lv_material[l] >= n_mat) return fail(GV_EINVAL, "%s: lv_material[%d]", fn, l);
+  DeviceGuard dgd(g->device);
+  const size_t br = al256(rate.size() * 8), total = br + 4 * (size_t)g->n_lv;
+  void* mem = nullptr;
+  hipError_t e = hipMalloc(&mem, total);
+  if (e != hipSuccess) return fail(GV_ENOMEM, "%s: hipMalloc(%zu): %s", fn, total, hipGetErrorString(e));
+  e = hipMemcpy(mem, rate.data(), rate.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy((char*)mem + br, lv_material, 4 * (size_t)g->n_lv, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(mem);
+    return hip_fail(e, "geom_set_materials: hipMemcpy");
+  }
+  if (g->mat_mem) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(g->mat_mem);
+  }
+  g->mat_mem = mem;
+  g->dg.n_mat = n_mat;
+  g->dg.n_proc = n_proc;
+  g->dg.mat_rate = (CQ)mem;
+  g->dg.lv_mat = (CQI)((char*)mem + br);
+  t_err.clear();
+  return GV_OK;
 }
 
 // ------------------------------------------------------------ measurement
@@ -1049,7 +1128,7 @@ extern "C" int gv_profile(gv_geom* g, int enable) {
 }
 
 extern "C" int gv_profile_read(gv_geom* g, double* step_ms, int64_t* step_launches, uint64_t* work) {
-  static_assert(kWorkN == 22, "gvgeom.h documents 22 work counters");
+  static_assert(kWorkN == 24, "gvgeom.h documents 24 work counters");
   if (!g) return fail(GV_EINVAL, "gv_profile_read: geometry handle is NULL");
   DeviceGuard dgd(g->device);
   double ms = 0.0;

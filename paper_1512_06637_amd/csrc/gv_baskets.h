@@ -19,6 +19,7 @@
 // contiguous).  Per track and step that moves 12 bytes of indices instead of
 // the 64-byte state.
 #pragma once
+#include "gv_phys.h"
 #include "gv_step.h"
 
 namespace gv {
@@ -29,10 +30,15 @@ constexpr int kWave = 64;
 // every step.
 struct alignas(64) TRec {
   double x, y, z, dx, dy, dz;
-  int pv, zr, fl;
-  int cc;  // coarse direction cell (fixed along the straight track)
+  double safe;  // physics-limited transport: lower bound of the distance to the volume's boundaries
+  int pv;
+  int zfc;  // zero-length steps in a row (bits 0-7) | flags (8-15) | coarse direction cell (16-31)
 };
 static_assert(sizeof(TRec) == 64, "record layout");
+__device__ __forceinline__ int zfc_pack(int zr, uint32_t fl, int cc) { return zr | (int)(fl << 8) | (cc << 16); }
+__device__ __forceinline__ int zfc_zr(int v) { return v & 0xff; }
+__device__ __forceinline__ uint32_t zfc_fl(int v) { return (uint32_t)(v >> 8) & 0xffu; }
+__device__ __forceinline__ int zfc_cc(int v) { return (v >> 16) & 0xffff; }
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return __lanemask_lt(); }
 
@@ -204,10 +210,9 @@ __global__ void k_bt_place(const int* __restrict__ perm, const double* __restric
     r.dx = dx[id];
     r.dy = dy[id];
     r.dz = dz[id];
+    r.safe = 0.0;
     r.pv = out_pv[(size_t)id * (max_steps + 1)];
-    r.zr = 0;
-    r.fl = 0;
-    r.cc = dir_cell(r.dx, r.dy, r.dz, cb);
+    r.zfc = zfc_pack(0, 0u, dir_cell(r.dx, r.dy, r.dz, cb));
     rec[sl] = r;
     slot_id[sl] = id;
     list0[sl] = (int)sl;
@@ -218,13 +223,17 @@ __global__ void k_bt_place(const int* __restrict__ perm, const double* __restric
 // row-per-track arrays: a workgroup takes 64 slots and moves them through LDS
 // 64 steps at a time, so both the staged reads (64 slots of one step) and the
 // row writes (64 steps of one track) are contiguous.  Only the kmax steps that
-// were run are read; entries past a track's step count are not written.
+// were run are read; entries past a track's step count are not written.  The
+// process indices of physics-limited transport move along when staged.
+template <bool PROC>
 __global__ void __launch_bounds__(256) k_bt_emit(const double* __restrict__ ob_step, const int* __restrict__ ob_pv,
-                                                 int64_t cap, const int* __restrict__ slot_id, TCtl C,
-                                                 int max_steps, int kmax, const int32_t* __restrict__ out_nsteps,
-                                                 double* __restrict__ out_step, int32_t* __restrict__ out_pv) {
+                                                 const int8_t* __restrict__ ob_proc, int64_t cap,
+                                                 const int* __restrict__ slot_id, TCtl C, int max_steps, int kmax,
+                                                 const int32_t* __restrict__ out_nsteps, double* __restrict__ out_step,
+                                                 int32_t* __restrict__ out_pv, int8_t* __restrict__ out_proc) {
   __shared__ double ts[64][65];
   __shared__ int tp[64][65];
+  __shared__ int8_t tq[PROC ? 64 : 1][65];
   __shared__ int sid[64], sns[64];
   const int64_t s0 = (int64_t)blockIdx.x * 64;
   const int64_t nl = *C.nlive;
@@ -248,6 +257,7 @@ __global__ void __launch_bounds__(256) k_bt_emit(const double* __restrict__ ob_s
       if (k < kmax && sl < nl) {
         ts[lane][r] = ob_step[(size_t)k * cap + sl];
         tp[lane][r] = ob_pv[(size_t)k * cap + sl];
+        if (PROC) tq[lane][r] = ob_proc[(size_t)k * cap + sl];
       }
     }
     __syncthreads();
@@ -257,6 +267,7 @@ __global__ void __launch_bounds__(256) k_bt_emit(const double* __restrict__ ob_s
         const int id = sid[r];
         out_step[(size_t)id * max_steps + k] = ts[r][lane];
         out_pv[(size_t)id * (max_steps + 1) + k + 1] = tp[r][lane];
+        if (PROC) out_proc[(size_t)id * max_steps + k] = tq[r][lane];
       }
     }
   }
@@ -354,14 +365,15 @@ __global__ void __launch_bounds__(1024) k_bt_reindex(const int* __restrict__ src
 #ifndef GV_STEP_WAVES_PER_EU
 #define GV_STEP_WAVES_PER_EU 1
 #endif
-template <bool F32>
+template <bool F32, bool PHYS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GV_STEP_WAVES_PER_EU))) k_bt_step(DevGeom G, int k, int max_steps, int cb, const int* __restrict__ idx,
                                                   TRec* __restrict__ rec, const int* __restrict__ cnt_cur,
                                                   int* __restrict__ nxt_lv, int* __restrict__ cnt_next, TCtl C,
                                                   int32_t* __restrict__ out_pv, double* __restrict__ out_step,
                                                   int32_t* __restrict__ out_nsteps, uint32_t* __restrict__ out_flags,
                                                   const int* __restrict__ slot_id, double* __restrict__ ob_step,
-                                                  int* __restrict__ ob_pv, int64_t cap) {
+                                                  int* __restrict__ ob_pv, int64_t cap, PhysArgs P,
+                                                  int8_t* __restrict__ ob_proc, int8_t* __restrict__ out_proc) {
   // Dynamic LDS: next-bucket histogram [nb], this list's per-LV counts [nlv]
   // and per-LV layout start/tile [nlv+1] each.  The list is ordered by
   // bucket = (LV, coarse direction cell), so each LV's entries are contiguous
@@ -409,18 +421,25 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GV_STE
       const int id = slot_id[sl];
       TRec r = rec[sl];
       V3 p{r.x, r.y, r.z}, d{r.dx, r.dy, r.dz};
-      uint32_t fl = (uint32_t)r.fl;
-      int nx;
-      double st = step_culled<F32>(G, b, r.pv, p, d, &nx, &fl, w);
-      p = advance(p, st, d);
+      uint32_t fl = zfc_fl(r.zfc);
+      int nx, proc = -1;
+      double st;
+      if (PHYS) {
+        st = step_physics<F32>(G, b, r.pv, p, d, (uint32_t)id, k, P, r.safe, &nx, &proc, &fl, w);
+      } else {
+        st = step_culled<F32>(G, b, r.pv, p, d, &nx, &fl, w);
+        p = advance(p, st, d);
+      }
       if (ob_step) {  // staged by slot, moved to the rows at the end
         ob_step[(size_t)k * cap + sl] = st;
         ob_pv[(size_t)k * cap + sl] = nx;
+        if (PHYS && ob_proc) ob_proc[(size_t)k * cap + sl] = (int8_t)proc;
       } else {
         out_step[(size_t)id * max_steps + k] = st;
         out_pv[(size_t)id * (max_steps + 1) + k + 1] = nx;
+        if (PHYS && out_proc) out_proc[(size_t)id * max_steps + k] = (int8_t)proc;
       }
-      int zr = st < kTol ? r.zr + 1 : 0;
+      int zr = st < kTol ? zfc_zr(r.zfc) + 1 : 0;
       bool done = nx < 0;
       if (!done && zr >= 8) {
         fl |= kFlagStuck;
@@ -440,10 +459,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GV_STE
         r.y = p.y;
         r.z = p.z;
         r.pv = nx;
-        r.zr = zr;
-        r.fl = (int)fl;
+        r.zfc = zfc_pack(zr, fl, zfc_cc(r.zfc));
         rec[sl] = r;
-        nlv_out = G.pv_lv[nx] << cb | r.cc;
+        nlv_out = G.pv_lv[nx] << cb | zfc_cc(r.zfc);
       }
       nxt_lv[e] = nlv_out;
     }

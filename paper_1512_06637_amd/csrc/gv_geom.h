@@ -36,6 +36,10 @@ struct DevGeom {
   CQI lv_grp;        // [n_lv] index of the LV's first group box, -1 without groups
   CQ grp_box;        // [n_grp][6] union of the group's padded daughter boxes (lo xyz, hi xyz)
   CQF grp_box32;     // [n_grp][8] union of the group's FP32 boxes; 2 unused
+  // materials for physics-limited steps (geom_set_materials); n_mat 0 if unset
+  int n_mat, n_proc;
+  CQ mat_rate;       // [n_mat][n_proc] n sigma = 1 / mean free path, 1/mm
+  CQI lv_mat;        // [n_lv] material of each LV
 };
 
 __device__ __forceinline__ V3 ld3(const double* x, const double* y, const double* z, int64_t i) {

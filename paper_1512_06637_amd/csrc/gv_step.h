@@ -13,13 +13,16 @@
 // sized for runs the FP64 screens for that step instead.
 #pragma once
 #include "gv_kernels.h"
+#include "gv_phys.h"
 
 namespace gv {
 
 // Work counters: steps, daughter bounding-box tests, then per daughter solid
 // type the lower-bound checks, the full DistanceToIn evaluations of culled
 // loops and those of plain loops (6 types each), then the track-steps of culled
-// loops whose screens ran in FP32 and those that fell back to FP64 screens.
+// loops whose screens ran in FP32 and those that fell back to FP64 screens,
+// then the physics-limited steps and those of them taken by the safety
+// short-cut.
 enum {
   kWorkSteps = 0,
   kWorkBox = 1,
@@ -28,7 +31,9 @@ enum {
   kWorkPlain = 14,
   kWorkScr32 = 20,
   kWorkScr64 = 21,
-  kWorkN = 22
+  kWorkPhys = 22,   // physics-limited steps
+  kWorkShort = 23,  // of which taken without geometry (safety short-cut)
+  kWorkN = 24
 };
 
 // Exact counting inside divergent code: the first active lane adds the number
@@ -337,6 +342,56 @@ __device__ __forceinline__ double step_culled_limited(const DevGeom& G, int pv, 
   return s;
 }
 
+// Physics-limited ComputeStep (physics-limited transport).  `safe` is kept per
+// track: the distance still to go along the ray to the boundary found by the
+// last full ComputeStep.  The direction does not change at a physics step, so
+// that boundary stays the first one on the ray; when the proposed physics length
+// is below the distance still to go (by kTolerance, so that the rounding of the
+// difference cannot matter) the step is physics-limited for sure and is taken
+// without any geometry (the short-cut), and the distance shrinks by the step.
+// Otherwise the full ComputeStep runs and, if physics wins, the distance is its
+// geometric step minus the physics step; after a boundary step it is 0.  The
+// short-cut never changes a result.
+struct PhysArgs {
+  uint64_t seed;
+  int shortcut;
+};
+
+template <bool F32, class W>
+__device__ __forceinline__ double step_physics(const DevGeom& G, int lv, int pv, V3& p, V3 d, uint32_t track, int k,
+                                               const PhysArgs& P, double& safe, int* next, int* proc,
+                                               uint32_t* flags, W& w) {
+  int pr = -1;
+  const double ps = physics_length(G.mat_rate, G.n_proc, G.lv_mat[lv], P.seed, track, (uint32_t)k, &pr);
+  if (P.shortcut && ps + kTol < safe) {
+    w.add(kWorkPhys);
+    w.add(kWorkShort);
+    safe -= ps;
+    *next = pv;
+    *proc = pr;
+    p = advance(p, ps, d);
+    return ps;
+  }
+  int nx;
+  const double sg = step_culled<F32>(G, lv, pv, p, d, &nx, flags, w);  // min(best daughter, exit)
+  double st;
+  if (ps < sg) {
+    w.add(kWorkPhys);
+    st = ps;
+    *next = pv;
+    *proc = pr;
+    p = advance(p, st, d);
+    safe = P.shortcut ? sg - ps : 0.0;
+  } else {
+    st = sg;
+    *next = nx;
+    *proc = -1;
+    p = advance(p, st, d);
+    safe = 0.0;
+  }
+  return st;
+}
+
 // NavSafety with the FP32 SafetyToIn screen: a box or tube daughter is skipped
 // when its FP32 lower bound (minus its error) exceeds both the running minimum
 // and the surface half-band by kTolerance, i.e. when the point is provably
@@ -406,14 +461,15 @@ __global__ void k_nav_safety_scr(DevGeom G, int64_t n, const double* __restrict_
 }
 
 // Whole-track transport, one lane per track, until the track leaves the world
-// (used for batches too small to fill the device with per-volume tiles).
-template <bool F32>
-__global__ void k_transport_lane(DevGeom G, int64_t n, const double* __restrict__ x,
-                                     const double* __restrict__ y, const double* __restrict__ z,
-                                     const double* __restrict__ dx, const double* __restrict__ dy,
-                                     const double* __restrict__ dz, const int32_t* __restrict__ start_pv,
-                                     int max_steps, int32_t* __restrict__ out_pv, double* __restrict__ out_step,
-                                     int32_t* __restrict__ out_nsteps, uint32_t* __restrict__ out_flags) {
+// (used for batches too small to fill the device with per-volume tiles);
+// with PHYS, physics-limited steps (track index = counter of the draws).
+template <bool F32, bool PHYS>
+__global__ void k_transport_lane(DevGeom G, int64_t n, const double* __restrict__ x, const double* __restrict__ y,
+                                 const double* __restrict__ z, const double* __restrict__ dx,
+                                 const double* __restrict__ dy, const double* __restrict__ dz,
+                                 const int32_t* __restrict__ start_pv, int max_steps, int32_t* __restrict__ out_pv,
+                                 double* __restrict__ out_step, int32_t* __restrict__ out_nsteps,
+                                 uint32_t* __restrict__ out_flags, PhysArgs P, int8_t* __restrict__ out_proc) {
   NoWork w;
   for (int64_t i = gtid(); i < n; i += gstride()) {
     V3 p = ld3(x, y, z, i), d = ld3(dx, dy, dz, i);
@@ -429,9 +485,17 @@ __global__ void k_transport_lane(DevGeom G, int64_t n, const double* __restrict_
     int k = 0;
     if (pv >= 0) {
       int zero_run = 0, nx = pv;
+      double safe = 0.0;
       while (k < max_steps) {
-        double st = step_culled<F32>(G, G.pv_lv[pv], pv, p, d, &nx, &fl, w);
-        p = advance(p, st, d);
+        double st;
+        if (PHYS) {
+          int proc;
+          st = step_physics<F32>(G, G.pv_lv[pv], pv, p, d, (uint32_t)i, k, P, safe, &nx, &proc, &fl, w);
+          if (out_proc) out_proc[(size_t)i * max_steps + k] = (int8_t)proc;
+        } else {
+          st = step_culled<F32>(G, G.pv_lv[pv], pv, p, d, &nx, &fl, w);
+          p = advance(p, st, d);
+        }
         rs[k] = st;
         rp[k + 1] = nx;
         ++k;
