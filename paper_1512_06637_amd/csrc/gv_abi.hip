@@ -3,7 +3,9 @@
 // caller's stream.  No exception or abort crosses the boundary.
 #include <hip/hip_runtime.h>
 
+#include <immintrin.h>
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -58,9 +60,11 @@ struct gv_geom {
   int8_t* ob_proc = nullptr;
   void* mat_mem = nullptr;  // device material tables (geom_set_materials)
   int64_t ob_cap = 0, ob_steps = 0;
-  int* h_live = nullptr;  // [2] pinned, mapped host copies of the live count
-  int* d_live = nullptr;  // device address of h_live
-  hipEvent_t ev[2] = {nullptr, nullptr};
+  // live count of the transport loop: one pinned, mapped word (tag << 32 |
+  // count) that the index kernel stores at a chunk's end and the host polls
+  unsigned long long* h_live = nullptr;
+  unsigned long long* d_live = nullptr;  // device address of h_live
+  uint32_t live_tag = 0;                 // tag of the last stored count
   // kernel timing for measurement (gv_profile)
   bool prof = false;
   std::vector<hipEvent_t> prof_ev;  // pairs around step-kernel launches
@@ -562,8 +566,6 @@ extern "C" int geom_free(gv_geom* g) {
   if (g->dmem) (void)hipFree(g->dmem);
   if (g->h_live) (void)hipHostFree(g->h_live);
   for (auto& ev : g->prof_ev) (void)hipEventDestroy(ev);
-  for (auto& ev : g->ev)
-    if (ev) (void)hipEventDestroy(ev);
   if (dev != g->device && dev >= 0) (void)hipSetDevice(dev);
   delete g;
   if (e != hipSuccess) return hip_fail(e, "geom_free: hipDeviceSynchronize");
@@ -876,19 +878,49 @@ int ensure_workspace(gv_geom* g, int64_t n) {
   g->ctl.work = (unsigned long long*)take(8 * kWorkN);
   g->ctl.nlive = (int*)take(4);
   if (!g->h_live) {
-    e = hipHostMalloc((void**)&g->h_live, 2 * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent);
+    e = hipHostMalloc((void**)&g->h_live, sizeof(unsigned long long), hipHostMallocMapped | hipHostMallocCoherent);
     if (e != hipSuccess) return hip_fail(e, "nav_transport: hipHostMalloc");
+    *(volatile unsigned long long*)g->h_live = 0;
+    g->live_tag = 0;
     e = hipHostGetDevicePointer((void**)&g->d_live, g->h_live, 0);
     if (e != hipSuccess) return hip_fail(e, "nav_transport: hipHostGetDevicePointer");
-    for (int i = 0; i < 2; ++i) {
-      e = hipEventCreateWithFlags(&g->ev[i], hipEventDisableTiming);
-      if (e != hipSuccess) return hip_fail(e, "nav_transport: hipEventCreate");
-    }
   }
   g->ws = mem;
   g->ws_bytes = total;
   g->ws_tracks = cap;
   return GV_OK;
+}
+
+// Waits until the index kernel has stored the live count tagged `tag` into
+// the pinned word and returns the word.  The host spins on the word; every
+// 2 ms without it, it asks whether the stream has drained (an error there, or
+// a drained stream without the tag, is returned as a failure).
+int wait_live(gv_geom* g, hipStream_t s, uint32_t tag, unsigned long long* out) {
+  const volatile unsigned long long* w = g->h_live;
+  auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    for (int i = 0; i < 1024; ++i) {
+      const unsigned long long v = *w;
+      if ((uint32_t)(v >> 32) == tag) {
+        *out = v;
+        return GV_OK;
+      }
+      _mm_pause();
+    }
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2)) {
+      const hipError_t q = hipStreamQuery(s);
+      if (q == hipSuccess) {
+        const unsigned long long v = *w;
+        if ((uint32_t)(v >> 32) == tag) {
+          *out = v;
+          return GV_OK;
+        }
+        return fail(GV_EHIP, "nav_transport: live count of chunk %u not stored", tag);
+      }
+      if (q != hipErrorNotReady) return hip_fail(q, "nav_transport: hipStreamQuery");
+      t0 = std::chrono::steady_clock::now();
+    }
+  }
 }
 
 // Step-major output staging for `steps` steps of the workspace's tracks, kept
@@ -951,7 +983,7 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
   // live track ids in bucket order (into idx[1]), then slots in that order
   hipLaunchKernelGGL(k_bt_reindex, dim3(rg), dim3(1024), lds_ix, s, (const int*)nullptr, (const int*)nullptr, 0, n,
                      (const int*)g->nxt_lv, 0, g->idx[1], (const int*)C.cnt[0], C.cur[0], C.cnt[1], C.cur[1],
-                     (int*)nullptr, nl);
+                     (unsigned long long*)nullptr, 0u, nl);
   GV_TRY(launched(fn));
   hipLaunchKernelGGL(k_bt_place, dim3(sg), dim3(kBlock), 0, s, (const int*)g->idx[1], x, y, z, dx, dy, dz,
                      (const int32_t*)out_pv, max_steps, cb, nl, g->rec, g->slot_id, g->idx[0], C);
@@ -965,12 +997,15 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
   const int64_t max_tiles = n / kWave + g->n_lv + 1;
   const unsigned step_grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((max_tiles + 3) / 4, 1024));
   // The host enqueues steps in chunks of kChunk; at a chunk's end the index
-  // kernel stores the live count into pinned host memory.  Before enqueueing
-  // the end of chunk m the host waits for the count stored at the end of chunk
-  // m-1 and stops once it is zero, so at most about two chunks of empty steps
-  // are launched, and the device still has a chunk queued while the host looks.
+  // kernel stores the live count, tagged with the chunk, into pinned host
+  // memory.  Before enqueueing the end of chunk m the host polls for the count
+  // of chunk m-1 and stops once it is zero, so at most about two chunks of
+  // empty steps are launched, and the device still has a chunk queued while
+  // the host looks.  The host reads the word directly rather than through
+  // stream events, which would put a system-scope fence between two steps.
   constexpr int kChunk = 4;
   int chunk = 0, launched_steps = 0;
+  const uint32_t tag0 = g->live_tag + 1;
   for (int k = 0; k < max_steps; ++k) {
     const int c = k & 1, k0 = k % 3, k1 = (k + 1) % 3, k2 = (k + 2) % 3;
     hipEvent_t* pe = nullptr;
@@ -995,21 +1030,18 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
     if (pe) (void)hipEventRecord(pe[1], s);
     if (k + 1 == max_steps) break;
     const bool report = (k + 1) % kChunk == 0;
-    const int slot = chunk & 1;
     if (report && chunk >= 1) {
-      // the count stored at the end of the previous chunk (the other slot)
-      const int prev = slot ^ 1;
-      hipError_t e = hipEventSynchronize(g->ev[prev]);
-      if (e != hipSuccess) return hip_fail(e, "nav_transport: hipEventSynchronize");
-      if (((volatile int*)g->h_live)[prev] == 0) break;
+      unsigned long long w = 0;
+      GV_TRY(wait_live(g, s, tag0 + (uint32_t)chunk - 1, &w));
+      if ((uint32_t)w == 0) break;
     }
     hipLaunchKernelGGL(k_bt_reindex, dim3(rg), dim3(1024), lds_ix, s, (const int*)g->idx[c], (const int*)C.cnt[k0],
                        nl, (int64_t)0, (const int*)g->nxt_lv, 0, g->idx[c ^ 1], (const int*)C.cnt[k1], C.cur[k1],
-                       C.cnt[k2], C.cur[k2], report ? g->d_live + slot : (int*)nullptr, nl);
+                       C.cnt[k2], C.cur[k2], report ? g->d_live : (unsigned long long*)nullptr,
+                       tag0 + (uint32_t)chunk, nl);
     GV_TRY(launched(fn));
     if (report) {
-      hipError_t e = hipEventRecord(g->ev[slot], s);
-      if (e != hipSuccess) return hip_fail(e, "nav_transport: hipEventRecord");
+      g->live_tag = tag0 + (uint32_t)chunk;
       ++chunk;
     }
   }

@@ -300,14 +300,15 @@ __device__ __forceinline__ int wave_lds_reserve(int v, bool on, int* cnt) {
 // one contiguous range per bucket with a single global atomic, then writes them
 // in a second pass, so a workgroup's entries keep their order in each bucket.
 // Workgroup 0 clears cnt_clear/cur_clear (nullable) and stores the number of
-// entries of the new list into `live` (nullable; device memory or mapped pinned
-// host memory).  Needs 12 * nb + 4 bytes of dynamic LDS.
+// entries of the new list, tagged (tag << 32 | count), into `live` (nullable;
+// device memory or mapped pinned host memory).  Needs 12 * nb + 4 bytes of
+// dynamic LDS.
 __global__ void __launch_bounds__(1024) k_bt_reindex(const int* __restrict__ src_idx, const int* __restrict__ cnt_src,
                                                       int nsrc_bins, int64_t nsrc_fixed, const int* __restrict__ key,
                                                       int gather, int* __restrict__ dst_idx,
                                                       const int* __restrict__ cnt_dst, int* __restrict__ cur_dst,
                                                       int* __restrict__ cnt_clear, int* __restrict__ cur_clear,
-                                                      int* __restrict__ live, int nb) {
+                                                      unsigned long long* __restrict__ live, uint32_t tag, int nb) {
   extern __shared__ int lds[];
   int* cnt = lds;
   int* base = lds + nb;
@@ -326,7 +327,9 @@ __global__ void __launch_bounds__(1024) k_bt_reindex(const int* __restrict__ src
     nsrc = total;
   }
   if (blockIdx.x == 0) {
-    if (threadIdx.x == 0 && live) __hip_atomic_store(live, start[nb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (threadIdx.x == 0 && live)
+      __hip_atomic_store(live, ((unsigned long long)tag << 32) | (uint32_t)start[nb], __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_SYSTEM);
     for (int b = threadIdx.x; b < nb; b += blockDim.x) {
       if (cnt_clear) cnt_clear[b] = 0;
       if (cur_clear) cur_clear[b] = 0;
