@@ -8,7 +8,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["or_solids.c", "or_nav.c", "or_phys.c", "or_api.c"]
+SOURCES = ["or_solids.c", "or_bool.c", "or_nav.c", "or_phys.c", "or_api.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

@@ -16,7 +16,9 @@ static int nthr(int nthreads) { return nthreads > 0 ? nthreads : 1; }
 
 int orc_solid_check(int type, const double* params, int np) {
   or_solid s;
-  return or_solid_init(&s, type, params, np);
+  const int rc = or_solid_init(&s, type, params, np);
+  if (rc == 0) or_solid_release(&s);
+  return rc;
 }
 
 int orc_solid_signed(int type, const double* params, int np, int64_t n, const double* x,
@@ -28,6 +30,7 @@ int orc_solid_signed(int type, const double* params, int np, int64_t n, const do
     double p[3] = {x[i], y[i], z[i]};
     out[i] = or_signed(&s, p);
   }
+  or_solid_release(&s);
   return 0;
 }
 
@@ -40,6 +43,7 @@ int orc_solid_inside(int type, const double* params, int np, int64_t n, const do
     double p[3] = {x[i], y[i], z[i]};
     out[i] = (int8_t)or_inside(&s, p);
   }
+  or_solid_release(&s);
   return 0;
 }
 
@@ -47,13 +51,14 @@ int orc_solid_safety(int type, const double* params, int np, int mode, int64_t n
                      const double* x, const double* y, const double* z, double* out,
                      int nthreads) {
   or_solid s;
-  if (or_solid_init(&s, type, params, np)) return -1;
   if (mode < 0 || mode > 2) return -1;
+  if (or_solid_init(&s, type, params, np)) return -1;
 #pragma omp parallel for schedule(static, CHUNK) num_threads(nthr(nthreads))
   for (int64_t i = 0; i < n; ++i) {
     double p[3] = {x[i], y[i], z[i]};
     out[i] = or_safety(&s, mode, p);
   }
+  or_solid_release(&s);
   return 0;
 }
 
@@ -62,8 +67,8 @@ int orc_solid_distance(int type, const double* params, int np, int dir, int64_t 
                        const double* dy, const double* dz, double* out, uint32_t* diag,
                        int nthreads) {
   or_solid s;
-  if (or_solid_init(&s, type, params, np)) return -1;
   if (dir != 0 && dir != 1) return -1;
+  if (or_solid_init(&s, type, params, np)) return -1;
 #pragma omp parallel for schedule(static, CHUNK) num_threads(nthr(nthreads))
   for (int64_t i = 0; i < n; ++i) {
     double p[3] = {x[i], y[i], z[i]}, d[3] = {dx[i], dy[i], dz[i]};
@@ -71,6 +76,7 @@ int orc_solid_distance(int type, const double* params, int np, int dir, int64_t 
     out[i] = dir == 0 ? or_dist_in(&s, p, d, &dg) : or_dist_out(&s, p, d, &dg);
     if (diag) diag[i] = dg;
   }
+  or_solid_release(&s);
   return 0;
 }
 
@@ -81,6 +87,7 @@ int orc_solid_roots(int type, const double* params, int np, const double* p, con
   double R[OR_MAX_ROOTS];
   int n = or_roots(&s, p, d, R);
   for (int i = 0; i < n && i < cap; ++i) roots[i] = R[i];
+  or_solid_release(&s);
   return n;
 }
 

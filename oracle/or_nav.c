@@ -118,6 +118,7 @@ int or_geom_load(const void* blob, size_t nbytes, or_geom** out) {
     rc = -2;
     goto fail;
   }
+  g->n_lv = n_lv; /* lets or_geom_free release composites on failure */
   for (int i = 0; i < n_lv; ++i) {
     size_t o = lv_off + 32 * (size_t)i;
     int type = rd_i32(b, o), poff = rd_i32(b, o + 4), pcnt = rd_i32(b, o + 8);
@@ -177,6 +178,8 @@ fail:
 
 void or_geom_free(or_geom* g) {
   if (!g) return;
+  if (g->lv_solid)
+    for (int i = 0; i < g->n_lv; ++i) or_solid_release(&g->lv_solid[i]);
   free(g->lv_solid);
   free(g->pv_lv);
   free(g->pv_parent);

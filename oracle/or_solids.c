@@ -116,8 +116,19 @@ int or_solid_init(or_solid* s, int type, const double* q, int nq) {
       }
       return 0;
     }
+    case OR_BOOL:
+      return or_bool_init(s, q, nq);
   }
   return -1;
+}
+
+void or_solid_release(or_solid* s) {
+  if (s->type == OR_BOOL && s->comp) {
+    or_solid_release(&s->comp[0]);
+    or_solid_release(&s->comp[1]);
+    free(s->comp);
+    s->comp = NULL;
+  }
 }
 
 /* ------------------------------------------------------------ signed term */
@@ -176,6 +187,8 @@ double or_signed(const or_solid* s, const double p[3]) {
       t = dmax(t, s->z[0] - z);
       return dmax(t, z - s->z[s->nz - 1]);
     }
+    case OR_BOOL:
+      return or_bool_signed(s, p);
   }
   return NAN;
 }
@@ -259,6 +272,8 @@ double or_safety_out(const or_solid* s, const double p[3]) {
     }
     case OR_PCON:
       return pcon_boundary_dist(s, p);
+    case OR_BOOL:
+      return or_bool_safety_out(s, p);
   }
   return NAN;
 }
@@ -300,6 +315,8 @@ double or_safety_in(const or_solid* s, const double p[3]) {
     }
     case OR_PCON:
       return pcon_boundary_dist(s, p);
+    case OR_BOOL:
+      return or_bool_safety_in(s, p);
   }
   return NAN;
 }
@@ -426,6 +443,8 @@ int or_roots(const or_solid* s, const double p[3], const double d[3], double* R)
       n = plane_root(R, n, 0, 0, 1, s->z[0], p, d);
       n = plane_root(R, n, 0, 0, 1, s->z[s->nz - 1], p, d);
       return n;
+    case OR_BOOL:
+      return or_bool_roots(s, p, d, R);
   }
   return 0;
 }

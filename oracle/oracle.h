@@ -36,9 +36,11 @@
 #define OR_KTOL 1e-9   /* kTolerance, mm */
 #define OR_KHALF 5e-10 /* half-width of the surface band, mm */
 #define OR_MAX_NZ 64   /* polycone planes */
-#define OR_MAX_ROOTS (4 * OR_MAX_NZ + 16)
+#define OR_MAX_ROOTS (2 * (4 * OR_MAX_NZ + 16)) /* a composite holds two solids */
 
-enum { OR_BOX = 0, OR_TUBS = 1, OR_CONS = 2, OR_SPHERE = 3, OR_TRD = 4, OR_PCON = 5 };
+enum { OR_BOX = 0, OR_TUBS = 1, OR_CONS = 2, OR_SPHERE = 3, OR_TRD = 4, OR_PCON = 5, OR_BOOL = 6 };
+/* composite operations: A u C, A \ C, A n C */
+enum { OR_UNION = 0, OR_SUBTRACTION = 1, OR_INTERSECTION = 2 };
 enum { OR_OUTSIDE = 0, OR_SURFACE = 1, OR_INSIDE = 2 };
 enum { OR_SAFETY_AUTO = 0, OR_SAFETY_IN = 1, OR_SAFETY_OUT = 2 };
 
@@ -54,7 +56,7 @@ enum { OR_SAFETY_AUTO = 0, OR_SAFETY_IN = 1, OR_SAFETY_OUT = 2 };
 #define OR_D_BAND_EDGE 128u
 #define OR_D_NO_EXIT 256u
 
-typedef struct {
+typedef struct or_solid {
   int type;
   int nz; /* polycone planes */
   double p[8];
@@ -70,10 +72,25 @@ typedef struct {
   double z[OR_MAX_NZ], rmin[OR_MAX_NZ], rmax[OR_MAX_NZ];
   double pc_bo[OR_MAX_NZ], pc_co[OR_MAX_NZ], pc_bi[OR_MAX_NZ], pc_ci[OR_MAX_NZ];
   int pc_inner[OR_MAX_NZ];
+  /* composite: comp[0] = A at the composite's origin, comp[1] = C placed by
+   * x = R x_C + t (R row major); heap-owned, see or_solid_release */
+  int op;
+  double bR[9], bt[3];
+  struct or_solid* comp;
 } or_solid;
 
-/* returns 0 on success, negative on invalid parameters */
+/* returns 0 on success, negative on invalid parameters; a composite's
+ * components are allocated and must be released with or_solid_release */
 int or_solid_init(or_solid* s, int type, const double* params, int nparams);
+void or_solid_release(or_solid* s);
+
+/* composites (or_bool.c) */
+int or_bool_init(or_solid* s, const double* q, int nq);
+void or_bool_to_c(const or_solid* s, const double p[3], const double d[3], double pc[3], double dc[3]);
+double or_bool_signed(const or_solid* s, const double p[3]);
+double or_bool_safety_in(const or_solid* s, const double p[3]);
+double or_bool_safety_out(const or_solid* s, const double p[3]);
+int or_bool_roots(const or_solid* s, const double p[3], const double d[3], double* roots);
 
 double or_signed(const or_solid* s, const double p[3]);
 int or_code(double s);

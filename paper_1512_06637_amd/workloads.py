@@ -29,6 +29,9 @@ Solid types and parameters (lengths in mm, angles in rad):
   3 sphere   rmin rmax                                 (full shell)
   4 trd      dx1 dx2 dy1 dy2 dz                        (half-widths at -dz / +dz)
   5 pcon     nz z[nz] rmin[nz] rmax[nz]                (full phi)
+  6 bool     op tA nA A[nA] tC nC C[nC] R[9] t[3]      (composite of two solids of
+             types 0-5: op 0 union, 1 A minus C, 2 intersection; A at the
+             composite's origin, C placed by x = R x_C + t, R row major)
 
 Track sets follow the paper's workload of randomly placed particles with random
 directions (Sec. III.C speed test); the concrete recipes are the five benchmark
@@ -47,8 +50,9 @@ SEED_BASE = 1512066370
 MAGIC = b"GVGEOM\x00\x01"
 VERSION = 1
 
-BOX, TUBS, CONS, SPHERE, TRD, PCON = 0, 1, 2, 3, 4, 5
-SOLID_NAMES = {BOX: "box", TUBS: "tubs", CONS: "cons", SPHERE: "sphere", TRD: "trd", PCON: "pcon"}
+BOX, TUBS, CONS, SPHERE, TRD, PCON, BOOL = 0, 1, 2, 3, 4, 5, 6
+UNION, SUBTRACTION, INTERSECTION = 0, 1, 2
+SOLID_NAMES = {BOX: "box", TUBS: "tubs", CONS: "cons", SPHERE: "sphere", TRD: "trd", PCON: "pcon", BOOL: "bool"}
 TWO_PI = 2.0 * math.pi
 
 
@@ -87,6 +91,29 @@ def pcon(z, rmin, rmax):
     z, rmin, rmax = list(map(float, z)), list(map(float, rmin)), list(map(float, rmax))
     assert len(z) == len(rmin) == len(rmax) >= 2
     return Solid(PCON, [float(len(z))] + z + rmin + rmax)
+
+
+def boolean(op, a: Solid, c: Solid, R=None, t=(0.0, 0.0, 0.0)) -> Solid:
+    """Composite op(A, C) of two elementary solids; C placed by x = R x_C + t."""
+    assert a.type != BOOL and c.type != BOOL and op in (UNION, SUBTRACTION, INTERSECTION)
+    R = np.eye(3) if R is None else np.asarray(R, dtype=np.float64)
+    return Solid(BOOL, [float(op), float(a.type), float(len(a.params))] + [float(v) for v in a.params]
+                 + [float(c.type), float(len(c.params))] + [float(v) for v in c.params]
+                 + [float(v) for v in R.reshape(9)] + [float(v) for v in np.asarray(t, dtype=np.float64)])
+
+
+def bool_parts(s: Solid):
+    """(op, A, C, R, t) of a composite."""
+    q = s.params
+    op, at = int(q[0]), 1
+    parts = []
+    for _ in range(2):
+        typ, n = int(q[at]), int(q[at + 1])
+        parts.append(Solid(typ, list(q[at + 2:at + 2 + n])))
+        at += 2 + n
+    R = np.asarray(q[at:at + 9], dtype=np.float64).reshape(3, 3)
+    t = np.asarray(q[at + 9:at + 12], dtype=np.float64)
+    return op, parts[0], parts[1], R, t
 
 
 def pcon_arrays(s: Solid):
@@ -137,6 +164,20 @@ def solid_extent(s: Solid):
         z, _, rmax = pcon_arrays(s)
         r = float(rmax.max())
         return np.array([0.0, 0.0, 0.5 * (z[0] + z[-1])]), np.array([r, r, 0.5 * (z[-1] - z[0])])
+    if s.type == BOOL:
+        op, a, c, R, t = bool_parts(s)
+        ca, ha = solid_extent(a)
+        cc, hc = solid_extent(c)
+        cc = R @ cc + t
+        hc = np.abs(R) @ hc
+        lo_a, hi_a, lo_c, hi_c = ca - ha, ca + ha, cc - hc, cc + hc
+        if op == UNION:
+            lo, hi = np.minimum(lo_a, lo_c), np.maximum(hi_a, hi_c)
+        elif op == INTERSECTION and np.all(np.maximum(lo_a, lo_c) < np.minimum(hi_a, hi_c)):
+            lo, hi = np.maximum(lo_a, lo_c), np.minimum(hi_a, hi_c)
+        else:
+            lo, hi = lo_a, hi_a
+        return 0.5 * (lo + hi), 0.5 * (hi - lo)
     raise ValueError(s.type)
 
 
@@ -391,6 +432,13 @@ def _sample_z_quadratic_density(rng, n, z0, z1, dens):
 
 def sample_volume(s: Solid, rng, n: int) -> np.ndarray:
     p = s.params
+    if s.type == BOOL:  # rejection from the bounding box
+        c, h = solid_extent(s)
+        out = np.empty((3, 0))
+        while out.shape[1] < n:
+            P = uniform_box_points(rng, 4 * (n - out.shape[1]) + 1024, c, h)
+            out = np.concatenate([out, P[:, _member(s, P)]], axis=1)
+        return out[:, :n]
     if s.type == BOX:
         return rng.uniform(-1, 1, (3, n)) * np.array(p[:3])[:, None]
     if s.type in (TUBS, CONS):
@@ -475,6 +523,10 @@ def _member(s: Solid, P: np.ndarray) -> np.ndarray:
         ro = np.interp(z, zs, rmax)
         ri = np.interp(z, zs, rmin)
         return ok & (r <= ro) & (r >= ri)
+    if s.type == BOOL:
+        op, a, c, R, t = bool_parts(s)
+        ma, mc = _member(a, P), _member(c, R.T @ (P - t[:, None]))
+        return (ma | mc) if op == UNION else ((ma & ~mc) if op == SUBTRACTION else (ma & mc))
     raise ValueError(s.type)
 
 
@@ -632,7 +684,30 @@ def _faces(s: Solid):
     raise ValueError(s.type)
 
 
+def _bool_surface(s: Solid, rng, n: int):
+    """Points of the components' faces that lie on the composite's boundary
+    (membership differs 1e-7 mm to either side), with outward normals."""
+    op, a, c, R, t = bool_parts(s)
+    P, N = np.empty((3, 0)), np.empty((3, 0))
+    while P.shape[1] < n:
+        m = 2 * (n - P.shape[1]) + 1024
+        pa, na = sample_surface(a, rng, m)
+        pc, nc = sample_surface(c, rng, m)
+        Q = np.concatenate([pa, R @ pc + t[:, None]], axis=1)
+        M = np.concatenate([na, R @ nc], axis=1)
+        e = 1e-7
+        inn, out = _member(s, Q - e * M), _member(s, Q + e * M)
+        keep = inn != out
+        M = np.where(inn, M, -M)
+        P = np.concatenate([P, Q[:, keep]], axis=1)
+        N = np.concatenate([N, M[:, keep]], axis=1)
+    sel = rng.permutation(P.shape[1])[:n]
+    return P[:, sel], N[:, sel]
+
+
 def sample_surface(s: Solid, rng, n: int):
+    if s.type == BOOL:
+        return _bool_surface(s, rng, n)
     faces = _faces(s)
     areas = np.array([a for a, _ in faces])
     pick = rng.choice(len(faces), size=n, p=areas / areas.sum())
