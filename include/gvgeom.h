@@ -61,7 +61,14 @@ enum { GV_FP64 = 0, GV_FP32_REFINE = 1 };
 #define GV_FLAG_LOCATE_FAIL 4u /* point found outside its volume or inside a daughter */
 
 /* Solid types of the geometry blob: 0 box, 1 tube segment, 2 cone segment,
- * 3 sphere shell, 4 trapezoid (Trd), 5 polycone (Sec. III.B elementary solids). */
+ * 3 sphere shell, 4 trapezoid (Trd), 5 polycone (Sec. III.B elementary solids),
+ * 6 composite: union, A minus C or intersection of two solids of types 0-5, A
+ * at the composite's origin and C placed by a rotation and translation
+ * (Sec. III.B: complex elements built with Boolean operations).  A composite's
+ * Inside code composes its parts' signed terms (union the smaller, intersection
+ * the larger, A minus C the larger of s_A and -s_C); its distances follow the
+ * Boolean combination of the parts' pieces along the ray under the elementary
+ * solids' kTolerance rules; its safeties are bounds composed from the parts'. */
 
 /* ------------------------------------------------------------------ geometry */
 
@@ -210,8 +217,9 @@ int nav_transport_phys(gv_geom* g, int64_t n, const double* x, const double* y, 
  * basket transport (host array of 24 uint64: [0] steps taken, [1] daughter
  * bounding-box tests, [2+t] daughter lower-bound checks, [8+t] daughter
  * DistanceToIn evaluations in culled loops, [14+t] DistanceToIn evaluations in
- * plain loops, t = daughter solid type 0..5, [20] track-steps of culled loops
- * screened in FP32, [21] those screened in FP64, [22] physics-limited steps,
+ * plain loops, t = daughter solid type 0..5 (composites are not counted there),
+ * [20] track-steps of culled loops screened in FP32, [21] those screened in
+ * FP64, [22] physics-limited steps,
  * [23] of which taken by the safety short-cut).  Reading synchronises the
  * device. */
 int gv_profile(gv_geom* g, int enable);

@@ -43,6 +43,7 @@ struct gv_geom {
   int device = -1;
   DevGeom dg{};
   int n_lv = 0, n_pv = 0, n_place = 0, max_depth = 0, world_lv = 0;
+  bool has_bool = false;  // some LV is a composite: navigation runs the kernels built with composite code
   std::vector<int> lv_type, lv_par;
   void* dmem = nullptr;
   // nav_transport workspace (grown on demand)
@@ -193,6 +194,43 @@ bool derive(int type, const double* q, int nq, std::vector<double>& out, std::st
       for (auto* a : {&bo, &co, &bi, &ci, &in}) out.insert(out.end(), a->begin(), a->end());
       return true;
     }
+    case kBool: {
+      // op, type_A, n_A, A[n_A], type_C, n_C, C[n_C], R[9], t[3]
+      if (nq < 3) return bad("composite needs op and two parts");
+      const int op = (int)q[0];
+      if ((double)op != q[0] || op < kUnion || op > kIntersection) return bad("composite op must be 0, 1 or 2");
+      int at = 1, pt[2], pn[2], po[2];
+      for (int c = 0; c < 2; ++c) {
+        if (at + 2 > nq) return bad("composite parameters truncated");
+        pt[c] = (int)q[at];
+        pn[c] = (int)q[at + 1];
+        if ((double)pt[c] != q[at] || (double)pn[c] != q[at + 1] || pt[c] < kBox || pt[c] > kPcon || pn[c] < 1)
+          return bad("composite parts must be elementary solids (types 0-5)");
+        po[c] = at + 2;
+        at = po[c] + pn[c];
+        if (at > nq) return bad("composite parameters truncated");
+      }
+      if (at + 12 != nq) return bad("composite needs R[9] and t[3] after the parts");
+      const double* R = q + at;
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          double v = 0.0;
+          for (int k = 0; k < 3; ++k) v += R[3 * i + k] * R[3 * j + k];
+          if (std::fabs(v - (i == j ? 1.0 : 0.0)) > 1e-9) return bad("composite placement R is not a rotation");
+        }
+      const size_t h = out.size();
+      out.resize(h + L::BO_N, 0.0);
+      out[h + L::BO_OP] = op;
+      out[h + L::BO_TA] = pt[0];
+      out[h + L::BO_TC] = pt[1];
+      for (int i = 0; i < 12; ++i) out[h + L::BO_R + i] = q[at + i];
+      for (int c = 0; c < 2; ++c) {
+        out[h + (c == 0 ? L::BO_OA : L::BO_OC)] = (double)(out.size() - h);
+        std::string w;
+        if (!derive(pt[c], q + po[c], pn[c], out, w)) return bad(c == 0 ? "composite part A invalid" : "composite part C invalid");
+      }
+      return true;
+    }
   }
   why = "unknown solid type";
   return false;
@@ -207,6 +245,37 @@ struct HostTree {
 // Axis-aligned box holding a solid in its own frame, from the derived
 // parameters (layouts in gv_solids.h).
 void local_extent(int type, const double* q, double* lo, double* hi) {
+  if (type == kBool) {
+    // union: the box around both parts; intersection: the overlap of the
+    // parts' boxes; A minus C: A's box
+    double alo[3], ahi[3], clo[3], chi[3];
+    local_extent((int)q[L::BO_TA], q + (int)q[L::BO_OA], alo, ahi);
+    local_extent((int)q[L::BO_TC], q + (int)q[L::BO_OC], clo, chi);
+    const double* X = q + L::BO_R;  // R[9] then t[3]
+    double blo[3] = {HUGE_VAL, HUGE_VAL, HUGE_VAL}, bhi[3] = {-HUGE_VAL, -HUGE_VAL, -HUGE_VAL};
+    for (int c = 0; c < 8; ++c) {
+      const double v[3] = {(c & 1) ? chi[0] : clo[0], (c & 2) ? chi[1] : clo[1], (c & 4) ? chi[2] : clo[2]};
+      for (int i = 0; i < 3; ++i) {
+        const double w = X[3 * i] * v[0] + X[3 * i + 1] * v[1] + X[3 * i + 2] * v[2] + X[9 + i];
+        blo[i] = std::min(blo[i], w);
+        bhi[i] = std::max(bhi[i], w);
+      }
+    }
+    const int op = (int)q[L::BO_OP];
+    bool empty = false;
+    for (int i = 0; i < 3; ++i) {
+      lo[i] = alo[i], hi[i] = ahi[i];
+      if (op == kUnion) {
+        lo[i] = std::min(alo[i], blo[i]), hi[i] = std::max(ahi[i], bhi[i]);
+      } else if (op == kIntersection) {
+        lo[i] = std::max(alo[i], blo[i]), hi[i] = std::min(ahi[i], bhi[i]);
+        empty = empty || lo[i] > hi[i];
+      }
+    }
+    if (empty)
+      for (int i = 0; i < 3; ++i) lo[i] = alo[i], hi[i] = ahi[i];
+    return;
+  }
   double rx = 0, ry = 0, z0 = 0, z1 = 0;
   switch (type) {
     case kBox: rx = q[0], ry = q[1], z0 = -q[2], z1 = q[2]; break;
@@ -543,6 +612,7 @@ extern "C" int geom_load(const void* blob, size_t nbytes, gv_geom** out) {
     g->max_depth = T.max_depth;
     g->world_lv = world;
     g->lv_type = lv_type;
+    g->has_bool = std::find(lv_type.begin(), lv_type.end(), (int)kBool) != lv_type.end();
     g->lv_par = lv_par;
     *out = g;
     t_err.clear();
@@ -646,6 +716,7 @@ int launched(const char* fn) {
     case kCons: CALL(Cons); break;  \
     case kSphere: CALL(Sphere); break; \
     case kTrd: CALL(Trd); break;    \
+    case kBool: CALL(Bool); break;  \
     default: CALL(Pcon); break;     \
   }
 
@@ -769,7 +840,7 @@ extern "C" int basket_locate(gv_geom* g, int64_t n, const double* x, const doubl
   GV_TRY(check_f64(fn, "z", z));
   GV_TRY(check_i32(fn, "out_pv", out_pv));
   DeviceGuard dgd(g->device);
-  hipLaunchKernelGGL(k_locate, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, g->dg, n, x, y, z, out_pv);
+  hipLaunchKernelGGL(g->has_bool ? k_locate<true> : k_locate<false>, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, g->dg, n, x, y, z, out_pv);
   return launched(fn);
 }
 
@@ -790,7 +861,9 @@ extern "C" int basket_step(gv_geom* g, int64_t n, const double* x, const double*
   GV_TRY(check_i32(fn, "out_next_pv", out_next_pv));
   GV_TRY(check_i32(fn, "out_flags", out_flags, true));
   DeviceGuard dgd(g->device);
-  hipLaunchKernelGGL(precision == GV_FP64 ? k_step_nav<false> : k_step_nav<true>, dim3(grid_for(n)), dim3(kBlock), 0,
+  const auto kern = g->has_bool ? (precision == GV_FP64 ? k_step_nav<false, true> : k_step_nav<true, true>)
+                                : (precision == GV_FP64 ? k_step_nav<false, false> : k_step_nav<true, false>);
+  hipLaunchKernelGGL(kern, dim3(grid_for(n)), dim3(kBlock), 0,
                      (hipStream_t)stream, g->dg, n, x, y, z, dx, dy, dz, pv, pstep, out_step, out_next_pv, out_flags);
   return launched(fn);
 }
@@ -807,7 +880,9 @@ extern "C" int basket_nav_safety(gv_geom* g, int64_t n, const double* x, const d
   GV_TRY(check_i32(fn, "pv", pv));
   GV_TRY(check_f64(fn, "out", out));
   DeviceGuard dgd(g->device);
-  hipLaunchKernelGGL(precision == GV_FP64 ? k_nav_safety : k_nav_safety_scr, dim3(grid_for(n)), dim3(kBlock), 0,
+  const auto kern = g->has_bool ? (precision == GV_FP64 ? k_nav_safety<true> : k_nav_safety_scr<true>)
+                                : (precision == GV_FP64 ? k_nav_safety<false> : k_nav_safety_scr<false>);
+  hipLaunchKernelGGL(kern, dim3(grid_for(n)), dim3(kBlock), 0,
                      (hipStream_t)stream, g->dg, n, x, y, z, pv, out);
   return launched(fn);
 }
@@ -823,7 +898,7 @@ extern "C" int basket_nav_inside(gv_geom* g, int64_t n, const double* x, const d
   GV_TRY(check_i32(fn, "pv", pv));
   if (!out) return fail(GV_EINVAL, "%s: out is NULL", fn);
   DeviceGuard dgd(g->device);
-  hipLaunchKernelGGL(k_nav_inside, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, g->dg, n, x, y, z, pv,
+  hipLaunchKernelGGL(g->has_bool ? k_nav_inside<true> : k_nav_inside<false>, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, g->dg, n, x, y, z, pv,
                      out);
   return launched(fn);
 }
@@ -977,7 +1052,7 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
   TCtl& C = g->ctl;
   hipLaunchKernelGGL(k_bt_clear, dim3(1), dim3(kBlock), 0, s, C, nl);
   GV_TRY(launched(fn));
-  hipLaunchKernelGGL(k_bt_init, dim3(sg), dim3(kBlock), 4 * (size_t)nl, s, g->dg, n, x, y, z, dx, dy, dz, start_pv,
+  hipLaunchKernelGGL(g->has_bool ? k_bt_init<true> : k_bt_init<false>, dim3(sg), dim3(kBlock), 4 * (size_t)nl, s, g->dg, n, x, y, z, dx, dy, dz, start_pv,
                      max_steps, out_pv, out_nsteps, out_flags, g->nxt_lv, cb, C);
   GV_TRY(launched(fn));
   // live track ids in bucket order (into idx[1]), then slots in that order
@@ -992,8 +1067,11 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
   double* ob_step = staged ? g->ob_step : nullptr;
   int* ob_pv = staged ? g->ob_pv : nullptr;
   int8_t* ob_proc = staged && phys && out_proc ? g->ob_proc : nullptr;
-  const auto step_kernel = fp32 ? (phys ? k_bt_step<true, true> : k_bt_step<true, false>)
-                                : (phys ? k_bt_step<false, true> : k_bt_step<false, false>);
+  const auto step_kernel =
+      g->has_bool ? (fp32 ? (phys ? k_bt_step<true, true, true> : k_bt_step<true, false, true>)
+                          : (phys ? k_bt_step<false, true, true> : k_bt_step<false, false, true>))
+                  : (fp32 ? (phys ? k_bt_step<true, true, false> : k_bt_step<true, false, false>)
+                          : (phys ? k_bt_step<false, true, false> : k_bt_step<false, false, false>));
   const int64_t max_tiles = n / kWave + g->n_lv + 1;
   const unsigned step_grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((max_tiles + 3) / 4, 1024));
   // The host enqueues steps in chunks of kChunk; at a chunk's end the index
@@ -1082,8 +1160,11 @@ int transport_common(const char* fn, gv_geom* g, int64_t n, const double* x, con
   if (n >= kBasketMin && n <= (1L << 30) && g->n_lv <= 4096)
     return basket_transport(g, n, x, y, z, dx, dy, dz, start_pv, max_steps, out_pv, out_step, out_nsteps, out_flags,
                             fp32, phys, P, out_proc, (hipStream_t)stream);
-  const auto lane = fp32 ? (phys ? k_transport_lane<true, true> : k_transport_lane<true, false>)
-                         : (phys ? k_transport_lane<false, true> : k_transport_lane<false, false>);
+  const auto lane =
+      g->has_bool ? (fp32 ? (phys ? k_transport_lane<true, true, true> : k_transport_lane<true, false, true>)
+                          : (phys ? k_transport_lane<false, true, true> : k_transport_lane<false, false, true>))
+                  : (fp32 ? (phys ? k_transport_lane<true, true, false> : k_transport_lane<true, false, false>)
+                          : (phys ? k_transport_lane<false, true, false> : k_transport_lane<false, false, false>));
   hipLaunchKernelGGL(lane, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, g->dg, n, x, y, z, dx, dy, dz,
                      start_pv, (int)max_steps, out_pv, out_step, out_nsteps, out_flags, P, out_proc);
   return launched(fn);

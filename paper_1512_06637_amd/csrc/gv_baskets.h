@@ -144,6 +144,7 @@ __device__ __forceinline__ int dir_cell(double dx, double dy, double dz, int cb)
 // counts of the first list (per-workgroup LDS histogram, 4 nb bytes of dynamic
 // LDS).  Tracks that start outside the world finish here with zero steps and
 // get bucket -1.
+template <bool B>
 __global__ void k_bt_init(DevGeom G, int64_t n, const double* __restrict__ x, const double* __restrict__ y,
                           const double* __restrict__ z, const double* __restrict__ dx, const double* __restrict__ dy,
                           const double* __restrict__ dz, const int32_t* __restrict__ start_pv, int max_steps,
@@ -161,7 +162,7 @@ __global__ void k_bt_init(DevGeom G, int64_t n, const double* __restrict__ x, co
     if (act) {
       uint32_t fl = 0;
       V3 p = ld3(x, y, z, i);
-      int v = start_pv ? start_pv[i] : locate(G, p);
+      int v = start_pv ? start_pv[i] : locate<B>(G, p);
       if (v < -1 || v >= G.n_pv) {
         v = -1;
         fl = kFlagLocateFail;
@@ -368,7 +369,7 @@ __global__ void __launch_bounds__(1024) k_bt_reindex(const int* __restrict__ src
 #ifndef GV_STEP_WAVES_PER_EU
 #define GV_STEP_WAVES_PER_EU 1
 #endif
-template <bool F32, bool PHYS>
+template <bool F32, bool PHYS, bool B>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GV_STEP_WAVES_PER_EU))) k_bt_step(DevGeom G, int k, int max_steps, int cb, const int* __restrict__ idx,
                                                   TRec* __restrict__ rec, const int* __restrict__ cnt_cur,
                                                   int* __restrict__ nxt_lv, int* __restrict__ cnt_next, TCtl C,
@@ -428,9 +429,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GV_STE
       int nx, proc = -1;
       double st;
       if (PHYS) {
-        st = step_physics<F32>(G, b, r.pv, p, d, (uint32_t)id, k, P, r.safe, &nx, &proc, &fl, w);
+        st = step_physics<F32, B>(G, b, r.pv, p, d, (uint32_t)id, k, P, r.safe, &nx, &proc, &fl, w);
       } else {
-        st = step_culled<F32>(G, b, r.pv, p, d, &nx, &fl, w);
+        st = step_culled<F32, B>(G, b, r.pv, p, d, &nx, &fl, w);
         p = advance(p, st, d);
       }
       if (ob_step) {  // staged by slot, moved to the rows at the end

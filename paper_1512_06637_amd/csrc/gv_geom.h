@@ -59,9 +59,10 @@ __device__ __forceinline__ V3 to_child_d(CQ X, V3 d) {
 
 constexpr uint32_t kFlagOverflow = 1u, kFlagStuck = 2u, kFlagLocateFail = 4u;
 
+template <bool B>
 __device__ __forceinline__ int locate(const DevGeom& G, V3 p) {
   int lv0 = G.pv_lv[0];
-  if (code_of(solid_sgn(G.lv_type[lv0], G.par + G.lv_par[lv0], p)) == kOutside) return -1;
+  if (code_of(solid_sgn<B>(G.lv_type[lv0], G.par + G.lv_par[lv0], p)) == kOutside) return -1;
   int pv = 0;
   V3 pl = p;
   for (;;) {
@@ -72,7 +73,7 @@ __device__ __forceinline__ int locate(const DevGeom& G, V3 p) {
     for (int k = 0; k < cnt; ++k) {
       int clv = G.dau_lv[off + k];
       pc = to_child_p(G.dau_xf + 12 * (size_t)(off + k), pl);
-      if (code_of(solid_sgn(G.lv_type[clv], G.par + G.lv_par[clv], pc)) != kOutside) {
+      if (code_of(solid_sgn<B>(G.lv_type[clv], G.par + G.lv_par[clv], pc)) != kOutside) {
         found = k;
         break;
       }
@@ -83,21 +84,22 @@ __device__ __forceinline__ int locate(const DevGeom& G, V3 p) {
   }
 }
 
+template <bool B>
 __device__ __forceinline__ double nav_safety(const DevGeom& G, int pv, V3 p) {
   int lv = G.pv_lv[pv];
   V3 pl = to_child_p(G.pv_gxf + 12 * (size_t)pv, p);
   int t = G.lv_type[lv];
   CQ q = G.par + G.lv_par[lv];
-  if (code_of(solid_sgn(t, q, pl)) != kInside) return 0.0;
-  double s = solid_safety_out(t, q, pl);
+  if (code_of(solid_sgn<B>(t, q, pl)) != kInside) return 0.0;
+  double s = solid_safety_out<B>(t, q, pl);
   int off = G.lv_dau_off[lv], cnt = G.lv_dau_cnt[lv];
   for (int k = 0; k < cnt; ++k) {
     int clv = G.dau_lv[off + k];
     V3 pc = to_child_p(G.dau_xf + 12 * (size_t)(off + k), pl);
     CQ qc = G.par + G.lv_par[clv];
     int tc = G.lv_type[clv];
-    if (code_of(solid_sgn(tc, qc, pc)) != kOutside) return 0.0;
-    s = fmin(s, solid_safety_in(tc, qc, pc));
+    if (code_of(solid_sgn<B>(tc, qc, pc)) != kOutside) return 0.0;
+    s = fmin(s, solid_safety_in<B>(tc, qc, pc));
   }
   return fmax(s, 0.0);
 }

@@ -74,19 +74,22 @@ __global__ void k_solid_all(CQ q, int64_t n, const double* __restrict__ x,
 }
 
 // ------------------------------------------------------------- navigation
+template <bool B>
 __global__ void k_locate(DevGeom G, int64_t n, const double* __restrict__ x, const double* __restrict__ y,
                          const double* __restrict__ z, int32_t* __restrict__ out) {
-  for (int64_t i = gtid(); i < n; i += gstride()) out[i] = locate(G, ld3(x, y, z, i));
+  for (int64_t i = gtid(); i < n; i += gstride()) out[i] = locate<B>(G, ld3(x, y, z, i));
 }
 
+template <bool B>
 __global__ void k_nav_safety(DevGeom G, int64_t n, const double* __restrict__ x, const double* __restrict__ y,
                              const double* __restrict__ z, const int32_t* __restrict__ pv, double* __restrict__ out) {
   for (int64_t i = gtid(); i < n; i += gstride()) {
     int v = pv[i];
-    out[i] = (v >= 0 && v < G.n_pv) ? nav_safety(G, v, ld3(x, y, z, i)) : 0.0;
+    out[i] = (v >= 0 && v < G.n_pv) ? nav_safety<B>(G, v, ld3(x, y, z, i)) : 0.0;
   }
 }
 
+template <bool B>
 __global__ void k_nav_inside(DevGeom G, int64_t n, const double* __restrict__ x, const double* __restrict__ y,
                              const double* __restrict__ z, const int32_t* __restrict__ pv, int8_t* __restrict__ out) {
   for (int64_t i = gtid(); i < n; i += gstride()) {
@@ -97,7 +100,7 @@ __global__ void k_nav_inside(DevGeom G, int64_t n, const double* __restrict__ x,
     }
     int lv = G.pv_lv[v];
     V3 pl = to_child_p(G.pv_gxf + 12 * (size_t)v, ld3(x, y, z, i));
-    out[i] = (int8_t)code_of(solid_sgn(G.lv_type[lv], G.par + G.lv_par[lv], pl));
+    out[i] = (int8_t)code_of(solid_sgn<B>(G.lv_type[lv], G.par + G.lv_par[lv], pl));
   }
 }
 

@@ -41,6 +41,7 @@ __host__ __device__ inline int64_t serve_out_bytes(int kind, int64_t n) {
 // Fused mixed-query kernel: one wavefront answers one tile of 64 tracks of one
 // basket, so the query kind and precision are wavefront-uniform; a basket's
 // tracks may sit in different volumes (per-lane navigation state).
+template <bool B>
 __global__ void __launch_bounds__(256) k_serve(DevGeom G, const SDesc* __restrict__ desc, int nb, int64_t ntiles,
                                                const char* __restrict__ din, char* __restrict__ dout) {
   __shared__ int64_t t0[kServeMaxSlots + 1];
@@ -74,8 +75,8 @@ __global__ void __launch_bounds__(256) k_serve(DevGeom G, const SDesc* __restric
       int nx = -1;
       double st = 0.0;
       if (v >= 0 && v < G.n_pv) {
-        st = prec == 0 ? step_culled_limited<false>(G, v, p, d, ps, &nx, &fl, w)
-                       : step_culled_limited<true>(G, v, p, d, ps, &nx, &fl, w);
+        st = prec == 0 ? step_culled_limited<false, B>(G, v, p, d, ps, &nx, &fl, w)
+                       : step_culled_limited<true, B>(G, v, p, d, ps, &nx, &fl, w);
       } else {
         fl = kFlagLocateFail;
       }
@@ -89,13 +90,13 @@ __global__ void __launch_bounds__(256) k_serve(DevGeom G, const SDesc* __restric
       const int v = ((const int32_t*)(X + 3 * n))[i];
       const bool ok = v >= 0 && v < G.n_pv;
       if (kind == kQSafety) {
-        ((double*)O)[i] = !ok ? 0.0 : prec == 0 ? nav_safety(G, v, p) : nav_safety_screened(G, v, p);
+        ((double*)O)[i] = !ok ? 0.0 : prec == 0 ? nav_safety<B>(G, v, p) : nav_safety_screened<B>(G, v, p);
       } else {
         int8_t c = (int8_t)kOutside;
         if (ok) {
           const int lv = G.pv_lv[v];
           const V3 pl = to_child_p(G.pv_gxf + 12 * (size_t)v, p);
-          c = (int8_t)code_of(solid_sgn(G.lv_type[lv], G.par + G.lv_par[lv], pl));
+          c = (int8_t)code_of(solid_sgn<B>(G.lv_type[lv], G.par + G.lv_par[lv], pl));
         }
         ((int8_t*)O)[i] = c;
       }
@@ -191,7 +192,7 @@ int server_launch(gv_server* s, int k) {
   if (e == hipSuccess) e = hipMemcpyAsync(dd, hd, R.bs.size() * sizeof(gv::SDesc), hipMemcpyHostToDevice, q);
   if (e != hipSuccess) return hip_fail(e, "gv_server: input copy");
   const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, 2048));
-  hipLaunchKernelGGL(gv::k_serve, dim3(grid), dim3(kBlock), 0, q, s->g->dg, (const gv::SDesc*)dd, (int)R.bs.size(),
+  hipLaunchKernelGGL(s->g->has_bool ? gv::k_serve<true> : gv::k_serve<false>, dim3(grid), dim3(kBlock), 0, q, s->g->dg, (const gv::SDesc*)dd, (int)R.bs.size(),
                      tiles, (const char*)s->d_in, s->d_out);
   GV_TRY(launched(fn));
   for (auto& r : runs(R.bs, [](const gv_server::Bk& b) { return std::make_pair(b.out_off, b.out_len); }))

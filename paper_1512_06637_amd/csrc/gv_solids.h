@@ -24,7 +24,8 @@ constexpr double kTol = 1e-9;
 constexpr double kHalf = 5e-10;
 #define GV_INF __builtin_huge_val()
 
-enum SolidType { kBox = 0, kTubs = 1, kCons = 2, kSphere = 3, kTrd = 4, kPcon = 5 };
+enum SolidType { kBox = 0, kTubs = 1, kCons = 2, kSphere = 3, kTrd = 4, kPcon = 5, kBool = 6 };
+enum BoolOp { kUnion = 0, kSubtraction = 1, kIntersection = 2 };
 enum { kOutside = 0, kSurface = 1, kInside = 2 };
 
 // ---- derived parameter layouts (filled on the host by geom_load) ----------
@@ -34,6 +35,8 @@ enum { kOutside = 0, kSurface = 1, kInside = 2 };
 // sphere: rmin rmax rmin^2 rmax^2
 // trd   : dx1 dx2 dy1 dy2 dz x0 tx cx y0 ty cy
 // pcon  : nz z[nz] rmin[nz] rmax[nz] bo[nz-1] co[nz-1] bi[nz-1] ci[nz-1] inner[nz-1]
+// bool  : op typeA offA typeC offC R[9] t[3], then the parts' own tables at
+//         offA / offC from the start of this one (R row major, x = R x_C + t)
 // phimode: 0 full circle, 1 wedge <= pi (intersection of two half-spaces),
 //          2 wedge > pi (union of two half-spaces).
 namespace L {
@@ -42,6 +45,7 @@ enum { CN_RMIN1 = 0, CN_RMAX1, CN_RMIN2, CN_RMAX2, CN_DZ, CN_PHI, CN_NS, CN_NE =
        CN_AO = 14, CN_BO, CN_CO, CN_AI, CN_BI, CN_CI, CN_INNER, CN_N };
 enum { SP_RMIN = 0, SP_RMAX, SP_RMIN2, SP_RMAX2, SP_N };
 enum { TD_DX1 = 0, TD_DX2, TD_DY1, TD_DY2, TD_DZ, TD_X0, TD_TX, TD_CX, TD_Y0, TD_TY, TD_CY, TD_N };
+enum { BO_OP = 0, BO_TA, BO_OA, BO_TC, BO_OC, BO_R, BO_T = 14, BO_N = 17 };
 }  // namespace L
 
 struct V3 {
@@ -650,7 +654,8 @@ struct Pcon {
 };
 
 // ------------------------------------------------------- runtime dispatch
-__device__ __forceinline__ double solid_sgn(int type, CQ q, V3 p) {
+// elementary solids
+__device__ __forceinline__ double prim_sgn(int type, CQ q, V3 p) {
   switch (type) {
     case kBox: return Box::sgn(q, p);
     case kTubs: return Tubs::sgn(q, p);
@@ -660,7 +665,7 @@ __device__ __forceinline__ double solid_sgn(int type, CQ q, V3 p) {
     default: return Pcon::sgn(q, p);
   }
 }
-__device__ __forceinline__ double solid_dist_in(int type, CQ q, V3 p, V3 d) {
+__device__ __forceinline__ double prim_dist_in(int type, CQ q, V3 p, V3 d) {
   switch (type) {
     case kBox: return Box::dist_in(q, p, d);
     case kTubs: return Tubs::dist_in(q, p, d);
@@ -670,7 +675,7 @@ __device__ __forceinline__ double solid_dist_in(int type, CQ q, V3 p, V3 d) {
     default: return Pcon::dist_in(q, p, d);
   }
 }
-__device__ __forceinline__ double solid_dist_out(int type, CQ q, V3 p, V3 d) {
+__device__ __forceinline__ double prim_dist_out(int type, CQ q, V3 p, V3 d) {
   switch (type) {
     case kBox: return Box::dist_out(q, p, d);
     case kTubs: return Tubs::dist_out(q, p, d);
@@ -680,7 +685,7 @@ __device__ __forceinline__ double solid_dist_out(int type, CQ q, V3 p, V3 d) {
     default: return Pcon::dist_out(q, p, d);
   }
 }
-__device__ __forceinline__ double solid_safety_in(int type, CQ q, V3 p) {
+__device__ __forceinline__ double prim_safety_in(int type, CQ q, V3 p) {
   switch (type) {
     case kBox: return Box::safety_in(q, p);
     case kTubs: return Tubs::safety_in(q, p);
@@ -690,7 +695,7 @@ __device__ __forceinline__ double solid_safety_in(int type, CQ q, V3 p) {
     default: return Pcon::safety_in(q, p);
   }
 }
-__device__ __forceinline__ double solid_safety_out(int type, CQ q, V3 p) {
+__device__ __forceinline__ double prim_safety_out(int type, CQ q, V3 p) {
   switch (type) {
     case kBox: return Box::safety_out(q, p);
     case kTubs: return Tubs::safety_out(q, p);
@@ -699,6 +704,186 @@ __device__ __forceinline__ double solid_safety_out(int type, CQ q, V3 p) {
     case kTrd: return Trd::safety_out(q, p);
     default: return Pcon::safety_out(q, p);
   }
+}
+
+// ================================================================ COMPOSITE
+// op(A, C) of two elementary solids (Sec. III.B: complex elements composed
+// with Boolean operations); A at the composite's origin, C placed by
+// x = R x_C + t.  The Inside term composes the parts' terms (union: the
+// smaller; intersection: the larger; A minus C: the larger of s_A and -s_C).
+// Along a ray the composite is the Boolean combination of the parts' pieces,
+// walked with the parts' own DistanceToIn/Out from the point reached so far:
+// an entry needs a run of at least kTolerance inside the composite, and a gap
+// of less than kTolerance before a part resumes is no exit (the elementary
+// solids' rules).  Safeties are bounds composed from the parts' safeties.
+// The functions are kept out of line: only the navigation kernels built for
+// geometries with composites call them.
+struct Bool {
+  static constexpr int kType = kBool;
+  static constexpr int kMaxIter = 64;  // > the pieces two elementary solids can have on a ray
+  __device__ static __forceinline__ int op(CQ q) { return (int)q[L::BO_OP]; }
+  __device__ static __forceinline__ int ta(CQ q) { return (int)q[L::BO_TA]; }
+  __device__ static __forceinline__ int tc(CQ q) { return (int)q[L::BO_TC]; }
+  __device__ static __forceinline__ CQ qa(CQ q) { return q + (int)q[L::BO_OA]; }
+  __device__ static __forceinline__ CQ qc(CQ q) { return q + (int)q[L::BO_OC]; }
+  __device__ static __forceinline__ V3 rt(CQ q, V3 v) {  // R^T v
+    CQ R = q + L::BO_R;
+    return V3{R[0] * v.x + R[3] * v.y + R[6] * v.z, R[1] * v.x + R[4] * v.y + R[7] * v.z,
+              R[2] * v.x + R[5] * v.y + R[8] * v.z};
+  }
+  __device__ static __forceinline__ V3 to_c(CQ q, V3 p) {
+    CQ T = q + L::BO_T;
+    return rt(q, V3{p.x - T[0], p.y - T[1], p.z - T[2]});
+  }
+  __device__ static __forceinline__ V3 at(V3 p, V3 d, double t) {
+    return V3{p.x + t * d.x, p.y + t * d.y, p.z + t * d.z};
+  }
+  // entry of a part: 0 when the point is inside it or enters it at once
+  __device__ static __forceinline__ double entry(int type, CQ q, V3 p, V3 d) {
+    return fmax(prim_dist_in(type, q, p, d), 0.0);
+  }
+  // t + s for t >= 0, s > 0, but at least the next double above t: a part's
+  // distance below the resolution of t (a point within rounding of a
+  // surface) must still move the walk forward
+  __device__ static __forceinline__ double ahead(double t, double s) {
+    const double u = t + s;
+    return u > t ? u : __longlong_as_double(__double_as_longlong(t) + 1);
+  }
+
+  __device__ __noinline__ static double sgn(CQ q, V3 p) {
+    const double a = prim_sgn(ta(q), qa(q), p), c = prim_sgn(tc(q), qc(q), to_c(q, p));
+    const int o = op(q);
+    return o == kUnion ? fmin(a, c) : (o == kSubtraction ? fmax(a, -c) : fmax(a, c));
+  }
+
+  // point outside: union min(SafetyToIn A, C); intersection the larger
+  // SafetyToIn of the parts the point is outside of; A minus C the larger of
+  // SafetyToIn A (outside A) and SafetyToOut C (inside C)
+  __device__ __noinline__ static double safety_in(CQ q, V3 p) {
+    const int A = ta(q), C = tc(q), o = op(q);
+    CQ a = qa(q), c = qc(q);
+    const V3 pc = to_c(q, p);
+    if (o == kUnion) return fmin(prim_safety_in(A, a, p), prim_safety_in(C, c, pc));
+    double m = -GV_INF;
+    if (code_of(prim_sgn(A, a, p)) == kOutside) m = fmax(m, prim_safety_in(A, a, p));
+    const int cc = code_of(prim_sgn(C, c, pc));
+    if (o == kSubtraction) {
+      if (cc == kInside) m = fmax(m, prim_safety_out(C, c, pc));
+    } else if (cc == kOutside) {
+      m = fmax(m, prim_safety_in(C, c, pc));
+    }
+    return m == -GV_INF ? 0.0 : m;
+  }
+
+  // point inside: union the larger SafetyToOut of the parts holding it;
+  // intersection min(SafetyToOut A, C); A minus C min(SafetyToOut A, SafetyToIn C)
+  __device__ __noinline__ static double safety_out(CQ q, V3 p) {
+    const int A = ta(q), C = tc(q), o = op(q);
+    CQ a = qa(q), c = qc(q);
+    const V3 pc = to_c(q, p);
+    if (o == kSubtraction) return fmin(prim_safety_out(A, a, p), prim_safety_in(C, c, pc));
+    if (o == kIntersection) return fmin(prim_safety_out(A, a, p), prim_safety_out(C, c, pc));
+    double m = -GV_INF;
+    if (code_of(prim_sgn(A, a, p)) == kInside) m = fmax(m, prim_safety_out(A, a, p));
+    if (code_of(prim_sgn(C, c, pc)) == kInside) m = fmax(m, prim_safety_out(C, c, pc));
+    return m == -GV_INF ? 0.0 : m;
+  }
+
+  __device__ __noinline__ static double dist_in(CQ q, V3 p, V3 d) {
+    if (sgn(q, p) < -kHalf) return -1.0;
+    const int A = ta(q), C = tc(q), o = op(q);
+    CQ a = qa(q), c = qc(q);
+    const V3 pc = to_c(q, p), dc = rt(q, d);
+    if (o == kUnion) return fmin(entry(A, a, p, d), entry(C, c, pc, dc));
+    double t = 0.0;
+    for (int it = 0; it < kMaxIter; ++it) {
+      const V3 x = at(p, d, t), xc = at(pc, dc, t);
+      const double ea = entry(A, a, x, d);
+      if (!(ea < GV_INF)) return GV_INF;
+      double run;
+      if (o == kIntersection) {
+        const double ec = entry(C, c, xc, dc);
+        if (!(ec < GV_INF)) return GV_INF;
+        if (ea > 0.0 || ec > 0.0) {  // nothing before the later of the two entries
+          t = ahead(t, fmax(ea, ec));
+          continue;
+        }
+        run = fmin(prim_dist_out(A, a, x, d), prim_dist_out(C, c, xc, dc));
+      } else {
+        if (ea > 0.0) {
+          t = ahead(t, ea);
+          continue;
+        }
+        const double xcv = prim_dist_out(C, c, xc, dc);
+        if (xcv > 0.0) {  // inside C: skip to its exit
+          t = ahead(t, xcv);
+          continue;
+        }
+        run = fmin(prim_dist_out(A, a, x, d), entry(C, c, xc, dc));
+      }
+      if (run >= kTol) return t;
+      t = ahead(t, run);
+    }
+    return t;
+  }
+
+  __device__ __noinline__ static double dist_out(CQ q, V3 p, V3 d) {
+    if (sgn(q, p) > kHalf) return -1.0;
+    const int A = ta(q), C = tc(q), o = op(q);
+    CQ a = qa(q), c = qc(q);
+    const V3 pc = to_c(q, p), dc = rt(q, d);
+    if (o == kIntersection) return fmax(fmin(prim_dist_out(A, a, p, d), prim_dist_out(C, c, pc, dc)), 0.0);
+    if (o == kSubtraction) return fmax(fmin(prim_dist_out(A, a, p, d), entry(C, c, pc, dc)), 0.0);
+    double t = 0.0;
+    for (int it = 0; it < kMaxIter; ++it) {
+      const V3 x = at(p, d, t), xc = at(pc, dc, t);
+      const double m = fmax(prim_dist_out(A, a, x, d), prim_dist_out(C, c, xc, dc));
+      if (m > 0.0) {  // still inside a part: go to the farther exit
+        t = ahead(t, m);
+        continue;
+      }
+      const double e = fmin(entry(A, a, x, d), entry(C, c, xc, dc));
+      if (e > 0.0 && e < kTol) {  // a part resumes within kTolerance
+        t = ahead(t, e);
+        continue;
+      }
+      return t;
+    }
+    return t;
+  }
+};
+
+// Any solid.  B: the geometry may hold composites.  Kernels instantiated with
+// B false (geometries of elementary solids only) contain no composite code.
+template <bool B>
+__device__ __forceinline__ double solid_sgn(int type, CQ q, V3 p) {
+  if constexpr (B)
+    if (type == kBool) return Bool::sgn(q, p);
+  return prim_sgn(type, q, p);
+}
+template <bool B>
+__device__ __forceinline__ double solid_dist_in(int type, CQ q, V3 p, V3 d) {
+  if constexpr (B)
+    if (type == kBool) return Bool::dist_in(q, p, d);
+  return prim_dist_in(type, q, p, d);
+}
+template <bool B>
+__device__ __forceinline__ double solid_dist_out(int type, CQ q, V3 p, V3 d) {
+  if constexpr (B)
+    if (type == kBool) return Bool::dist_out(q, p, d);
+  return prim_dist_out(type, q, p, d);
+}
+template <bool B>
+__device__ __forceinline__ double solid_safety_in(int type, CQ q, V3 p) {
+  if constexpr (B)
+    if (type == kBool) return Bool::safety_in(q, p);
+  return prim_safety_in(type, q, p);
+}
+template <bool B>
+__device__ __forceinline__ double solid_safety_out(int type, CQ q, V3 p) {
+  if constexpr (B)
+    if (type == kBool) return Bool::safety_out(q, p);
+  return prim_safety_out(type, q, p);
 }
 
 }  // namespace gv

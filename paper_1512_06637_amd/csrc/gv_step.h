@@ -275,12 +275,12 @@ constexpr int kCullMin = 8;  // LVs with fewer daughters run the plain loop
 
 // One ComputeStep of a track in placed volume pv (logical volume lv) with no
 // physics limit.  Valid for any lv; fastest when lv is wavefront-uniform.
-template <bool F32, class W>
+template <bool F32, bool B, class W>
 __device__ __forceinline__ double step_culled(const DevGeom& G, int lv, int pv, V3 p, V3 d, int* next,
                                               uint32_t* flags, W& w) {
   CQ X = G.pv_gxf + 12 * (size_t)pv;
   V3 pl = to_child_p(X, p), dl = to_child_d(X, d);
-  double dout = solid_dist_out(G.lv_type[lv], G.par + G.lv_par[lv], pl, dl);
+  double dout = solid_dist_out<B>(G.lv_type[lv], G.par + G.lv_par[lv], pl, dl);
   uint32_t fl = *flags;
   if (dout < 0.0) {
     dout = 0.0;
@@ -306,8 +306,8 @@ __device__ __forceinline__ double step_culled(const DevGeom& G, int lv, int pv, 
       const int clv = G.dau_lv[off + k];
       V3 pc = to_child_p(Y, pl), dc = to_child_d(Y, dl);
       const int ct = G.lv_type[clv];
-      double t = solid_dist_in(ct, G.par + G.lv_par[clv], pc, dc);
-      w.add(kWorkPlain + ct);
+      double t = solid_dist_in<B>(ct, G.par + G.lv_par[clv], pc, dc);
+      if (ct <= kPcon) w.add(kWorkPlain + ct);  // composites have no counter
       neg = neg || t < 0.0;
       t = fmax(t, 0.0);
       if (t < best) {
@@ -328,11 +328,11 @@ __device__ __forceinline__ double step_culled(const DevGeom& G, int lv, int pv, 
 
 // ComputeStep with a physics limit: as step_culled, then the physics length
 // wins when it is below both the daughter minimum and the exit.
-template <bool F32, class W>
+template <bool F32, bool B, class W>
 __device__ __forceinline__ double step_culled_limited(const DevGeom& G, int pv, V3 p, V3 d, double pstep, int* next,
                                                       uint32_t* flags, W& w) {
   int nx;
-  const double s = step_culled<F32>(G, G.pv_lv[pv], pv, p, d, &nx, flags, w);
+  const double s = step_culled<F32, B>(G, G.pv_lv[pv], pv, p, d, &nx, flags, w);
   // s is the daughter minimum when a daughter was chosen, else the exit
   if (pstep < s) {
     *next = pv;
@@ -357,7 +357,7 @@ struct PhysArgs {
   int shortcut;
 };
 
-template <bool F32, class W>
+template <bool F32, bool B, class W>
 __device__ __forceinline__ double step_physics(const DevGeom& G, int lv, int pv, V3& p, V3 d, uint32_t track, int k,
                                                const PhysArgs& P, double& safe, int* next, int* proc,
                                                uint32_t* flags, W& w) {
@@ -373,7 +373,7 @@ __device__ __forceinline__ double step_physics(const DevGeom& G, int lv, int pv,
     return ps;
   }
   int nx;
-  const double sg = step_culled<F32>(G, lv, pv, p, d, &nx, flags, w);  // min(best daughter, exit)
+  const double sg = step_culled<F32, B>(G, lv, pv, p, d, &nx, flags, w);  // min(best daughter, exit)
   double st;
   if (ps < sg) {
     w.add(kWorkPhys);
@@ -396,13 +396,14 @@ __device__ __forceinline__ double step_physics(const DevGeom& G, int lv, int pv,
 // when its FP32 lower bound (minus its error) exceeds both the running minimum
 // and the surface half-band by kTolerance, i.e. when the point is provably
 // outside it and it cannot lower the minimum.  Equal to nav_safety bit for bit.
+template <bool B>
 __device__ __forceinline__ double nav_safety_screened(const DevGeom& G, int pv, V3 p) {
   const int lv = G.pv_lv[pv];
   const V3 pl = to_child_p(G.pv_gxf + 12 * (size_t)pv, p);
   const int t = G.lv_type[lv];
   CQ q = G.par + G.lv_par[lv];
-  if (code_of(solid_sgn(t, q, pl)) != kInside) return 0.0;
-  double s = solid_safety_out(t, q, pl);
+  if (code_of(solid_sgn<B>(t, q, pl)) != kInside) return 0.0;
+  double s = solid_safety_out<B>(t, q, pl);
   const int off = G.lv_dau_off[lv], cnt = G.lv_dau_cnt[lv], dtype = G.lv_dau_type[lv];
   const F3 p32{(float)pl.x, (float)pl.y, (float)pl.z};
   const float pmax = max3f(fabsf(p32.x), fabsf(p32.y), fabsf(p32.z));
@@ -419,15 +420,15 @@ __device__ __forceinline__ double nav_safety_screened(const DevGeom& G, int pv, 
     const V3 pc = to_child_p(G.dau_xf + 12 * (size_t)(off + k), pl);
     CQ qc = G.par + G.lv_par[clv];
     const int tc = G.lv_type[clv];
-    if (code_of(solid_sgn(tc, qc, pc)) != kOutside) return 0.0;
-    s = fmin(s, solid_safety_in(tc, qc, pc));
+    if (code_of(solid_sgn<B>(tc, qc, pc)) != kOutside) return 0.0;
+    s = fmin(s, solid_safety_in<B>(tc, qc, pc));
   }
   return fmax(s, 0.0);
 }
 
 // --------------------------------------------------------- per-lane kernels
 // ComputeStep for every track of a basket, each lane in its own volume.
-template <bool F32>
+template <bool F32, bool B>
 __global__ void k_step_nav(DevGeom G, int64_t n, const double* __restrict__ x, const double* __restrict__ y,
                            const double* __restrict__ z, const double* __restrict__ dx, const double* __restrict__ dy,
                            const double* __restrict__ dz, const int32_t* __restrict__ pv,
@@ -440,7 +441,7 @@ __global__ void k_step_nav(DevGeom G, int64_t n, const double* __restrict__ x, c
     int nx = -1;
     double st = 0.0;
     if (v >= 0 && v < G.n_pv) {
-      st = step_culled_limited<F32>(G, v, ld3(x, y, z, i), ld3(dx, dy, dz, i), pstep ? pstep[i] : GV_INF, &nx, &fl,
+      st = step_culled_limited<F32, B>(G, v, ld3(x, y, z, i), ld3(dx, dy, dz, i), pstep ? pstep[i] : GV_INF, &nx, &fl,
                                     w);
     } else {
       fl = kFlagLocateFail;
@@ -451,19 +452,20 @@ __global__ void k_step_nav(DevGeom G, int64_t n, const double* __restrict__ x, c
   }
 }
 
+template <bool B>
 __global__ void k_nav_safety_scr(DevGeom G, int64_t n, const double* __restrict__ x, const double* __restrict__ y,
                                  const double* __restrict__ z, const int32_t* __restrict__ pv,
                                  double* __restrict__ out) {
   for (int64_t i = gtid(); i < n; i += gstride()) {
     int v = pv[i];
-    out[i] = (v >= 0 && v < G.n_pv) ? nav_safety_screened(G, v, ld3(x, y, z, i)) : 0.0;
+    out[i] = (v >= 0 && v < G.n_pv) ? nav_safety_screened<B>(G, v, ld3(x, y, z, i)) : 0.0;
   }
 }
 
 // Whole-track transport, one lane per track, until the track leaves the world
 // (used for batches too small to fill the device with per-volume tiles);
 // with PHYS, physics-limited steps (track index = counter of the draws).
-template <bool F32, bool PHYS>
+template <bool F32, bool PHYS, bool B>
 __global__ void k_transport_lane(DevGeom G, int64_t n, const double* __restrict__ x, const double* __restrict__ y,
                                  const double* __restrict__ z, const double* __restrict__ dx,
                                  const double* __restrict__ dy, const double* __restrict__ dz,
@@ -474,7 +476,7 @@ __global__ void k_transport_lane(DevGeom G, int64_t n, const double* __restrict_
   for (int64_t i = gtid(); i < n; i += gstride()) {
     V3 p = ld3(x, y, z, i), d = ld3(dx, dy, dz, i);
     uint32_t fl = 0;
-    int pv = start_pv ? start_pv[i] : locate(G, p);
+    int pv = start_pv ? start_pv[i] : locate<B>(G, p);
     if (pv < -1 || pv >= G.n_pv) {
       pv = -1;
       fl |= kFlagLocateFail;
@@ -490,10 +492,10 @@ __global__ void k_transport_lane(DevGeom G, int64_t n, const double* __restrict_
         double st;
         if (PHYS) {
           int proc;
-          st = step_physics<F32>(G, G.pv_lv[pv], pv, p, d, (uint32_t)i, k, P, safe, &nx, &proc, &fl, w);
+          st = step_physics<F32, B>(G, G.pv_lv[pv], pv, p, d, (uint32_t)i, k, P, safe, &nx, &proc, &fl, w);
           if (out_proc) out_proc[(size_t)i * max_steps + k] = (int8_t)proc;
         } else {
-          st = step_culled<F32>(G, G.pv_lv[pv], pv, p, d, &nx, &fl, w);
+          st = step_culled<F32, B>(G, G.pv_lv[pv], pv, p, d, &nx, &fl, w);
           p = advance(p, st, d);
         }
         rs[k] = st;

@@ -278,6 +278,57 @@ def detector_blob() -> bytes:
     return make_blob(detector_description()[0])
 
 
+# Composite-solid setup: a 600 mm world cube holding five volumes, four of them
+# composites (one with daughters of its own), the fifth an elementary tube.
+def _rot(axis, ang):
+    a = np.asarray(axis, dtype=np.float64)
+    a = a / np.linalg.norm(a)
+    K = np.array([[0.0, -a[2], a[1]], [a[2], 0.0, -a[0]], [-a[1], a[0], 0.0]])
+    return np.eye(3) + math.sin(ang) * K + (1.0 - math.cos(ang)) * K @ K
+
+
+def composite_description():
+    """LV 0 world; LV 1 a 120 mm cube with a radius-20 bore along z holding four
+    small boxes in its wall; LV 2 a sphere shell united with a tilted Trd; LV 3
+    a sphere clipped by a cube; LV 4 a tube segment (elementary); LV 5 a
+    polycone with a tilted cone cut out; LV 6 the small box."""
+    lvs = [LV(box(300.0, 300.0, 300.0), [], "world")]
+    lvs.append(LV(boolean(SUBTRACTION, box(60.0, 60.0, 60.0), tubs(0.0, 20.0, 80.0)), [], "bored_cube"))
+    lvs.append(LV(boolean(UNION, sphere(10.0, 40.0), trd(8.0, 16.0, 9.0, 20.0, 30.0), R=_rot((1, 0, 1), 1.1),
+                          t=(35.0, 5.0, 0.0)), [], "shell_and_trd"))
+    lvs.append(LV(boolean(INTERSECTION, sphere(0.0, 55.0), box(45.0, 45.0, 45.0)), [], "clipped_sphere"))
+    lvs.append(LV(tubs(10.0, 50.0, 60.0, 0.3, 1.4 * math.pi), [], "tube_segment"))
+    z = -90.0 + 20.0 * np.arange(10)
+    lvs.append(LV(boolean(SUBTRACTION, pcon(z, np.zeros(10), polycone_radii() + 15.0), cons(0.0, 6.0, 0.0, 14.0, 30.0),
+                          R=_rot((0, 1, 0), 0.4), t=(3.0, 0.0, -20.0)), [], "cut_polycone"))
+    lvs.append(LV(box(5.0, 5.0, 5.0), [], "insert"))
+    for sx, sy in ((1, 1), (-1, 1), (1, -1), (-1, -1)):
+        lvs[1].placements.append((6, rot_z(0.3 * sx), np.array([40.0 * sx, 40.0 * sy, 10.0 * sy])))
+    lvs[0].placements += [(1, _rot((0, 0, 1), 0.2), np.array([-170.0, 0.0, 0.0])),
+                          (2, _rot((1, 1, 0), 0.6), np.array([160.0, 20.0, 0.0])),
+                          (3, np.eye(3), np.array([0.0, 170.0, 60.0])),
+                          (4, _rot((1, 0, 0), 0.5), np.array([0.0, -160.0, 0.0])),
+                          (5, np.eye(3), np.array([0.0, 0.0, -150.0]))]
+    return lvs
+
+
+def composite_blob() -> bytes:
+    return make_blob(composite_description())
+
+
+COMPOSITE_CENTRES = np.array([[-170.0, 0.0, 0.0], [160.0, 20.0, 0.0], [0.0, 170.0, 60.0], [0.0, -160.0, 0.0],
+                              [0.0, 0.0, -150.0]])
+
+
+def composite_tracks(n: int) -> Tracks:
+    """Each start is uniform in the 160 mm cube around one of the five placed
+    volumes (chosen uniformly), directions isotropic."""
+    rng = np.random.Generator(np.random.PCG64(SEED_BASE + 7))
+    c = COMPOSITE_CENTRES[rng.integers(0, len(COMPOSITE_CENTRES), n)].T
+    p = c + rng.uniform(-80.0, 80.0, (3, n))
+    return Tracks(p[0].copy(), p[1].copy(), p[2].copy(), *isotropic(rng, n))
+
+
 def expand_pvs(lvs: list, world_lv: int = 0):
     """DFS pre-order expansion: list of (lv, parent_pv, R_global, t_global, depth).
     Global transforms are composed here only for test brute force and generators."""
