@@ -157,6 +157,63 @@ def solids_leg(copies=8, replays=10):
     return res
 
 
+def composites_leg(args, copies=4, replays=10, n=1 << 20):
+    """Composite solids.  (1) The fused solid-level query of each of the eight
+    composites over 2^20 tracks uniform in 1.6 times its bounding box, cycling
+    over `copies` input sets.  (2) Transport in the composite geometry (four
+    composites, one with daughters, and a tube segment in a 600 mm cube): 2^20
+    tracks starting around its volumes, to world exit, FP64; the oracle's rate
+    on the first 2^16 of them beside it."""
+    import torch
+
+    import oracle as O
+    import paper_1512_06637_amd as G
+    from paper_1512_06637_amd import workloads as W
+
+    comps = W.composite_solids()
+    names = list(comps)
+    g = G.Geometry(W.multi_solid_blob([comps[k] for k in names]))
+    res = {"solids": {}}
+    for lv, name in enumerate(names):
+        t = W.composite_box_tracks(comps[name], n, 500 + lv)
+        base = [torch.from_numpy(v).to("cuda") for v in t.arrays()]
+        sets = [[v.clone() for v in base] for _ in range(copies)]
+        outs = [[torch.empty(n, dtype=torch.int8, device="cuda")]
+                + [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(3)] for _ in range(copies)]
+        ms = graph_ms(lambda c: g.solid_all(lv, *sets[c], *outs[c]), copies, replays)
+        res["solids"][name] = {"fused_us_per_call": ms * 1e3, "tracks_per_s": n / (ms * 1e-3)}
+        del sets, outs, base
+    g.close()
+    blob = W.composite_blob()
+    g = G.Geometry(blob)
+    t = W.composite_tracks(n)
+    a = [torch.from_numpy(v).to("cuda") for v in t.arrays()]
+    for _ in range(args.warmup):
+        out = g.transport(*a)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        out = g.transport(*a)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    total = int(out["nsteps"].sum())
+    g.close()
+    og = O.Geometry(blob)
+    k = 1 << 16
+    t0 = time.perf_counter()
+    r = og.transport(t.take(slice(0, k)))
+    cpu_s = time.perf_counter() - t0
+    og.close()
+    res["transport"] = {"tracks": n, "track_steps": total, "ms_per_call": ms, "track_steps_per_s": total / (ms * 1e-3),
+                        "flags_nonzero": int((out["flags"] != 0).sum()),
+                        "oracle_track_steps_per_s": int(r["nsteps"].sum()) / cpu_s,
+                        "oracle_cores": O.default_threads(), "oracle_sample": f"first {k} tracks"}
+    return res
+
+
 def protocol_leg(replays=50, calls=100):
     """The paper's measurement protocol: DistanceToOut of points inside the box
     and the tube segment, N = 2^4 .. 2^20, per-call time over 5,000 graph-replayed
@@ -311,6 +368,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-screen + FP64-refine leg")
     ap.add_argument("--no-solids", action="store_true", help="skip the solid-level legs")
     ap.add_argument("--no-phys", action="store_true", help="skip the physics-limited transport leg")
+    ap.add_argument("--no-composites", action="store_true", help="skip the composite-solid legs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 256 MiB device to device (a kernel of known traffic for counter scaling)")
     args = ap.parse_args()
@@ -412,6 +470,8 @@ def main():
     if not args.no_solids:
         res["solids"] = solids_leg()
         res["protocol"] = protocol_leg()
+    if not args.no_composites:
+        res["composites"] = composites_leg(args)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(blob, tracks)
         if not args.no_solids:

@@ -716,8 +716,7 @@ __device__ __forceinline__ double prim_safety_out(int type, CQ q, V3 p) {
 // an entry needs a run of at least kTolerance inside the composite, and a gap
 // of less than kTolerance before a part resumes is no exit (the elementary
 // solids' rules).  Safeties are bounds composed from the parts' safeties.
-// The functions are kept out of line: only the navigation kernels built for
-// geometries with composites call them.
+// The navigation kernels reach these functions through BoolCall, out of line.
 struct Bool {
   static constexpr int kType = kBool;
   static constexpr int kMaxIter = 64;  // > the pieces two elementary solids can have on a ray
@@ -750,7 +749,7 @@ struct Bool {
     return u > t ? u : __longlong_as_double(__double_as_longlong(t) + 1);
   }
 
-  __device__ __noinline__ static double sgn(CQ q, V3 p) {
+  __device__ __forceinline__ static double sgn(CQ q, V3 p) {
     const double a = prim_sgn(ta(q), qa(q), p), c = prim_sgn(tc(q), qc(q), to_c(q, p));
     const int o = op(q);
     return o == kUnion ? fmin(a, c) : (o == kSubtraction ? fmax(a, -c) : fmax(a, c));
@@ -759,7 +758,7 @@ struct Bool {
   // point outside: union min(SafetyToIn A, C); intersection the larger
   // SafetyToIn of the parts the point is outside of; A minus C the larger of
   // SafetyToIn A (outside A) and SafetyToOut C (inside C)
-  __device__ __noinline__ static double safety_in(CQ q, V3 p) {
+  __device__ __forceinline__ static double safety_in(CQ q, V3 p) {
     const int A = ta(q), C = tc(q), o = op(q);
     CQ a = qa(q), c = qc(q);
     const V3 pc = to_c(q, p);
@@ -777,7 +776,7 @@ struct Bool {
 
   // point inside: union the larger SafetyToOut of the parts holding it;
   // intersection min(SafetyToOut A, C); A minus C min(SafetyToOut A, SafetyToIn C)
-  __device__ __noinline__ static double safety_out(CQ q, V3 p) {
+  __device__ __forceinline__ static double safety_out(CQ q, V3 p) {
     const int A = ta(q), C = tc(q), o = op(q);
     CQ a = qa(q), c = qc(q);
     const V3 pc = to_c(q, p);
@@ -789,7 +788,7 @@ struct Bool {
     return m == -GV_INF ? 0.0 : m;
   }
 
-  __device__ __noinline__ static double dist_in(CQ q, V3 p, V3 d) {
+  __device__ __forceinline__ static double dist_in(CQ q, V3 p, V3 d) {
     if (sgn(q, p) < -kHalf) return -1.0;
     const int A = ta(q), C = tc(q), o = op(q);
     CQ a = qa(q), c = qc(q);
@@ -827,7 +826,7 @@ struct Bool {
     return t;
   }
 
-  __device__ __noinline__ static double dist_out(CQ q, V3 p, V3 d) {
+  __device__ __forceinline__ static double dist_out(CQ q, V3 p, V3 d) {
     if (sgn(q, p) > kHalf) return -1.0;
     const int A = ta(q), C = tc(q), o = op(q);
     CQ a = qa(q), c = qc(q);
@@ -853,36 +852,47 @@ struct Bool {
   }
 };
 
+// Out-of-line entry points of the composite code for the navigation kernels
+// (inlined there it would set their register budget for every geometry); the
+// solid-level kernels, instantiated per solid type, inline Bool directly.
+struct BoolCall {
+  __device__ __noinline__ static double sgn(CQ q, V3 p) { return Bool::sgn(q, p); }
+  __device__ __noinline__ static double safety_in(CQ q, V3 p) { return Bool::safety_in(q, p); }
+  __device__ __noinline__ static double safety_out(CQ q, V3 p) { return Bool::safety_out(q, p); }
+  __device__ __noinline__ static double dist_in(CQ q, V3 p, V3 d) { return Bool::dist_in(q, p, d); }
+  __device__ __noinline__ static double dist_out(CQ q, V3 p, V3 d) { return Bool::dist_out(q, p, d); }
+};
+
 // Any solid.  B: the geometry may hold composites.  Kernels instantiated with
 // B false (geometries of elementary solids only) contain no composite code.
 template <bool B>
 __device__ __forceinline__ double solid_sgn(int type, CQ q, V3 p) {
   if constexpr (B)
-    if (type == kBool) return Bool::sgn(q, p);
+    if (type == kBool) return BoolCall::sgn(q, p);
   return prim_sgn(type, q, p);
 }
 template <bool B>
 __device__ __forceinline__ double solid_dist_in(int type, CQ q, V3 p, V3 d) {
   if constexpr (B)
-    if (type == kBool) return Bool::dist_in(q, p, d);
+    if (type == kBool) return BoolCall::dist_in(q, p, d);
   return prim_dist_in(type, q, p, d);
 }
 template <bool B>
 __device__ __forceinline__ double solid_dist_out(int type, CQ q, V3 p, V3 d) {
   if constexpr (B)
-    if (type == kBool) return Bool::dist_out(q, p, d);
+    if (type == kBool) return BoolCall::dist_out(q, p, d);
   return prim_dist_out(type, q, p, d);
 }
 template <bool B>
 __device__ __forceinline__ double solid_safety_in(int type, CQ q, V3 p) {
   if constexpr (B)
-    if (type == kBool) return Bool::safety_in(q, p);
+    if (type == kBool) return BoolCall::safety_in(q, p);
   return prim_safety_in(type, q, p);
 }
 template <bool B>
 __device__ __forceinline__ double solid_safety_out(int type, CQ q, V3 p) {
   if constexpr (B)
-    if (type == kBool) return Bool::safety_out(q, p);
+    if (type == kBool) return BoolCall::safety_out(q, p);
   return prim_safety_out(type, q, p);
 }
 

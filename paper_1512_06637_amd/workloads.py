@@ -278,8 +278,6 @@ def detector_blob() -> bytes:
     return make_blob(detector_description()[0])
 
 
-# Composite-solid setup: a 600 mm world cube holding five volumes, four of them
-# composites (one with daughters of its own), the fifth an elementary tube.
 def _rot(axis, ang):
     a = np.asarray(axis, dtype=np.float64)
     a = a / np.linalg.norm(a)
@@ -287,6 +285,34 @@ def _rot(axis, ang):
     return np.eye(3) + math.sin(ang) * K + (1.0 - math.cos(ang)) * K @ K
 
 
+def composite_solids() -> dict:
+    """Eight composites: the three operations, every elementary part type,
+    rotated and translated placements, touching parts (two cubes sharing a
+    face) and a part that cuts through (a bore)."""
+    return {
+        "box_u_box": boolean(UNION, box(10, 10, 10), box(10, 10, 10), t=(20, 0, 0)),
+        "box_minus_hole": boolean(SUBTRACTION, box(20, 20, 20), tubs(0, 5, 30)),
+        "sphere_n_cube": boolean(INTERSECTION, sphere(0, 12), box(10, 10, 10)),
+        "cube_n_rot_cube": boolean(INTERSECTION, box(10, 10, 10), box(10, 10, 10), R=rot_z(math.pi / 4)),
+        "tubs_u_rot_box": boolean(UNION, tubs(5, 15, 20, 0.3, 1.2 * math.pi), box(4, 9, 25),
+                                  R=_rot((1, 2, 3), 0.7), t=(8, -3, 2)),
+        "pcon_minus_cons": boolean(SUBTRACTION, config_solids()["pcon"], cons(0, 6, 0, 14, 30),
+                                   R=_rot((0, 1, 0), 0.4), t=(3, 0, -20)),
+        "trd_n_sphere": boolean(INTERSECTION, trd(10, 20, 15, 25, 30), sphere(8, 28), t=(2, -3, 5)),
+        "sphere_u_trd": boolean(UNION, sphere(10, 30), trd(5, 12, 6, 14, 20), R=_rot((1, 0, 1), 1.1), t=(25, 5, 0)),
+    }
+
+
+def composite_box_tracks(s: Solid, n: int, seed: int) -> Tracks:
+    """Points uniform in the box 1.6 times a solid's bounding box, isotropic."""
+    rng = np.random.default_rng(seed)
+    c, h = solid_extent(s)
+    P = uniform_box_points(rng, n, c, 1.6 * h)
+    return Tracks(*P, *isotropic(rng, n))
+
+
+# Composite-solid setup: a 600 mm world cube holding five volumes, four of them
+# composites (one with daughters of its own), the fifth an elementary tube.
 def composite_description():
     """LV 0 world; LV 1 a 120 mm cube with a radius-20 bore along z holding four
     small boxes in its wall; LV 2 a sphere shell united with a tilted Trd; LV 3

@@ -25,19 +25,7 @@ def rot_axis(axis, ang):
     return np.eye(3) + math.sin(ang) * K + (1 - math.cos(ang)) * K @ K
 
 
-COMPOSITES = {
-    "box_u_box": W.boolean(U, W.box(10, 10, 10), W.box(10, 10, 10), t=(20, 0, 0)),
-    "box_minus_hole": W.boolean(S, W.box(20, 20, 20), W.tubs(0, 5, 30)),
-    "sphere_n_cube": W.boolean(I, W.sphere(0, 12), W.box(10, 10, 10)),
-    "cube_n_rot_cube": W.boolean(I, W.box(10, 10, 10), W.box(10, 10, 10), R=W.rot_z(math.pi / 4)),
-    "tubs_u_rot_box": W.boolean(U, W.tubs(5, 15, 20, 0.3, 1.2 * math.pi), W.box(4, 9, 25),
-                                R=rot_axis((1, 2, 3), 0.7), t=(8, -3, 2)),
-    "pcon_minus_cons": W.boolean(S, W.config_solids()["pcon"], W.cons(0, 6, 0, 14, 30),
-                                 R=rot_axis((0, 1, 0), 0.4), t=(3, 0, -20)),
-    "trd_n_sphere": W.boolean(I, W.trd(10, 20, 15, 25, 30), W.sphere(8, 28), t=(2, -3, 5)),
-    "sphere_u_trd": W.boolean(U, W.sphere(10, 30), W.trd(5, 12, 6, 14, 20), R=rot_axis((1, 0, 1), 1.1),
-                              t=(25, 5, 0)),
-}
+COMPOSITES = W.composite_solids()
 NAMES = list(COMPOSITES)
 
 
