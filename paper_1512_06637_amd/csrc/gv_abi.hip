@@ -54,6 +54,7 @@ struct gv_geom {
   int* idx[2] = {nullptr, nullptr};  // bucketed slot lists
   TCtl ctl{};
   int* nxt_lv = nullptr;    // [cap] next bucket per list entry (start bucket per track at the start)
+  uint32_t* nxt_pos = nullptr;  // [cap] place of each list entry in the next list (workgroup, rank)
   int* slot_id = nullptr;   // [cap] track id of each slot
   void* ob = nullptr;       // staged outputs: ob_step [ob_steps][cap] double, then ob_pv [ob_steps][cap] int
   double* ob_step = nullptr;
@@ -62,7 +63,7 @@ struct gv_geom {
   void* mat_mem = nullptr;  // device material tables (geom_set_materials)
   int64_t ob_cap = 0, ob_steps = 0;
   // live count of the transport loop: one pinned, mapped word (tag << 32 |
-  // count) that the index kernel stores at a chunk's end and the host polls
+  // count) that the scatter kernel stores at a chunk's end and the host polls
   unsigned long long* h_live = nullptr;
   unsigned long long* d_live = nullptr;  // device address of h_live
   uint32_t live_tag = 0;                 // tag of the last stored count
@@ -919,8 +920,8 @@ int ensure_workspace(gv_geom* g, int64_t n) {
   if (g->ws && g->ws_tracks >= n) return GV_OK;
   int64_t cap = n < 4096 ? 4096 : n;
   int nl = g->n_lv << coarse_bits(g->n_lv);
-  size_t total = al256(sizeof(TRec) * (size_t)cap) + 4 * al256(4 * (size_t)cap) + 6 * al256(4 * (size_t)nl) +
-                 al256(8 * kWorkN) + al256(4);
+  size_t total = al256(sizeof(TRec) * (size_t)cap) + 5 * al256(4 * (size_t)cap) + 6 * al256(4 * (size_t)nl) +
+                 al256(8 * kWorkN) + al256(4) + al256(4 * (size_t)kMaxStepGrid * nl) + al256(8);
   if (g->ws) {
     (void)hipDeviceSynchronize();
     (void)hipFree(g->ws);
@@ -945,6 +946,7 @@ int ensure_workspace(gv_geom* g, int64_t n) {
   g->idx[0] = (int*)take(4 * cap);
   g->idx[1] = (int*)take(4 * cap);
   g->nxt_lv = (int*)take(4 * cap);
+  g->nxt_pos = (uint32_t*)take(4 * cap);
   g->slot_id = (int*)take(4 * cap);
   for (int s = 0; s < 3; ++s) {
     g->ctl.cnt[s] = (int*)take(4 * nl);
@@ -952,6 +954,8 @@ int ensure_workspace(gv_geom* g, int64_t n) {
   }
   g->ctl.work = (unsigned long long*)take(8 * kWorkN);
   g->ctl.nlive = (int*)take(4);
+  g->ctl.seg = (int*)take(4 * (size_t)kMaxStepGrid * nl);
+  g->ctl.len = (int*)take(8);
   if (!g->h_live) {
     e = hipHostMalloc((void**)&g->h_live, sizeof(unsigned long long), hipHostMallocMapped | hipHostMallocCoherent);
     if (e != hipSuccess) return hip_fail(e, "nav_transport: hipHostMalloc");
@@ -966,7 +970,7 @@ int ensure_workspace(gv_geom* g, int64_t n) {
   return GV_OK;
 }
 
-// Waits until the index kernel has stored the live count tagged `tag` into
+// Waits until the scatter kernel has stored the live count tagged `tag` into
 // the pinned word and returns the word.  The host spins on the word; every
 // 2 ms without it, it asks whether the stream has drained (an error there, or
 // a drained stream without the tag, is returned as a failure).
@@ -1073,8 +1077,10 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
                   : (fp32 ? (phys ? k_bt_step<true, true, false> : k_bt_step<true, false, false>)
                           : (phys ? k_bt_step<false, true, false> : k_bt_step<false, false, false>));
   const int64_t max_tiles = n / kWave + g->n_lv + 1;
-  const unsigned step_grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((max_tiles + 3) / 4, 1024));
-  // The host enqueues steps in chunks of kChunk; at a chunk's end the index
+  const unsigned step_grid =
+      (unsigned)std::max<int64_t>(1, std::min<int64_t>((max_tiles + 3) / 4, kMaxStepGrid));
+  const size_t lds_sc = 8 * (size_t)nl + 4;
+  // The host enqueues steps in chunks of kChunk; at a chunk's end the scatter
   // kernel stores the live count, tagged with the chunk, into pinned host
   // memory.  Before enqueueing the end of chunk m the host polls for the count
   // of chunk m-1 and stops once it is zero, so at most about two chunks of
@@ -1100,7 +1106,8 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
       (void)hipEventRecord(pe[0], s);
     }
     hipLaunchKernelGGL(step_kernel, dim3(step_grid), dim3(kBlock), lds_step, s, g->dg, k, max_steps, cb,
-                       (const int*)g->idx[c], g->rec, (const int*)C.cnt[k0], g->nxt_lv, C.cnt[k1], C, out_pv,
+                       (const int*)g->idx[c], g->rec, (const int*)C.cnt[k0], g->nxt_lv, g->nxt_pos, C.cnt[k1], C,
+                       out_pv,
                        out_step, out_nsteps, out_flags, (const int*)g->slot_id, ob_step, ob_pv, g->ob_cap, P,
                        ob_proc, out_proc);
     GV_TRY(launched(fn));
@@ -1113,9 +1120,10 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
       GV_TRY(wait_live(g, s, tag0 + (uint32_t)chunk - 1, &w));
       if ((uint32_t)w == 0) break;
     }
-    hipLaunchKernelGGL(k_bt_reindex, dim3(rg), dim3(1024), lds_ix, s, (const int*)g->idx[c], (const int*)C.cnt[k0],
-                       nl, (int64_t)0, (const int*)g->nxt_lv, 0, g->idx[c ^ 1], (const int*)C.cnt[k1], C.cur[k1],
-                       C.cnt[k2], C.cur[k2], report ? g->d_live : (unsigned long long*)nullptr,
+    hipLaunchKernelGGL(k_bt_scatter, dim3(rg), dim3(1024), lds_sc, s, (const int*)g->idx[c],
+                       (const int*)(k == 0 ? C.nlive : C.len + (k & 1)), (const int*)g->nxt_lv,
+                       (const uint32_t*)g->nxt_pos, (const int*)C.seg, (const int*)C.cnt[k1], g->idx[c ^ 1],
+                       C.len + ((k + 1) & 1), C.cnt[k2], report ? g->d_live : (unsigned long long*)nullptr,
                        tag0 + (uint32_t)chunk, nl);
     GV_TRY(launched(fn));
     if (report) {

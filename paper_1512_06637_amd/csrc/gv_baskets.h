@@ -12,12 +12,11 @@
 // solid type.  The direction cell keeps a tile's rays within one cone of
 // directions, so they tend to meet the same daughters (the group screen of the
 // culled loop then skips most daughters for the whole wavefront).  After the
-// step each workgroup adds its tracks to the bucket counts of the next step;
-// the next step's workgroups each turn those counts into the bucket layout,
-// and an index kernel writes each live slot index into its new bucket
-// (workgroup-aggregated atomics keep one workgroup's writes to a bucket
-// contiguous).  Per track and step that moves 12 bytes of indices instead of
-// the 64-byte state.
+// step each workgroup reserves, per next bucket, one share with a single
+// atomic on the bucket's count and gives each of its tracks a rank in its
+// share (LDS atomics); a scatter kernel then writes each live slot index at
+// bucket start + share offset + rank.  Per track and step that moves 16 bytes
+// of indices instead of the 64-byte state.
 #pragma once
 #include "gv_phys.h"
 #include "gv_step.h"
@@ -42,16 +41,23 @@ __device__ __forceinline__ int zfc_cc(int v) { return (v >> 16) & 0xffff; }
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return __lanemask_lt(); }
 
-// Per-step control arrays.  Counts and cursors are triple-buffered: step k
-// reads counts k and accumulates counts k+1; the index kernel after it reads
-// counts k+1 through cursors k+1 and clears counts and cursors k+2, which no
-// kernel of steps k..k+1 reads.
+// Per-step control arrays.  Counts are triple-buffered: step k reads counts k
+// and accumulates counts k+1; the scatter kernel after it reads counts k+1 and
+// clears counts k+2, which no kernel of steps k..k+1 reads.
 struct TCtl {
-  int* cnt[3];    // [nlv] tracks per LV in list k % 3
-  int* cur[3];    // [nlv] index-scatter cursors of list k % 3
+  int* cnt[3];    // [nlv] tracks per bucket in list k % 3
+  int* cur[3];    // [nlv] cursors of the first list's index kernel
   unsigned long long* work;  // [kWorkN] operation counts of the current call
   int* nlive;                // live tracks at the start (slots in use)
+  int* seg;                  // [kMaxStepGrid][nb] offset of a step workgroup's share of each next bucket
+  int* len;                  // [2] list lengths: list k in len[k & 1] (list 0 in nlive)
 };
+
+// Step-kernel workgroups at most, and the packing of an entry's place in the
+// next list: workgroup (high 10 bits) | rank within that workgroup's share of
+// its bucket (low 22 bits).
+constexpr int kMaxStepGrid = 1024;
+constexpr int kRankBits = 22;
 
 // wavefront-aggregated histogram update: one atomic per distinct LV in the wave
 __device__ __forceinline__ void wave_count(int v, bool on, int* cnt) {
@@ -365,14 +371,74 @@ __global__ void __launch_bounds__(1024) k_bt_reindex(const int* __restrict__ src
   }
 }
 
+// Writes list k+1 from the places the step kernel reserved: entry j of list k
+// (slot src_idx[j], next bucket nxt_lv[j] >= 0) goes to start[b] (the bucket's
+// start, from the new counts cnt_dst) + seg[w][b] (its workgroup's share) +
+// its rank in that share.  One pass, no atomics.  A thread's first kScatterUnroll
+// entries are loaded before the bucket layout is computed, so their latency
+// overlaps it.  len_src holds list k's length; workgroup 0 stores list k+1's
+// into len_dst and, tagged (tag << 32 | count), into `live` (nullable), and
+// clears the counts two lists ahead.  Needs 8 * nb + 4 bytes of dynamic LDS.
+constexpr int kScatterUnroll = 4;
+__global__ void __launch_bounds__(1024) k_bt_scatter(const int* __restrict__ src_idx, const int* __restrict__ len_src,
+                                                      const int* __restrict__ nxt_lv,
+                                                      const uint32_t* __restrict__ nxt_pos,
+                                                      const int* __restrict__ seg, const int* __restrict__ cnt_dst,
+                                                      int* __restrict__ dst_idx, int* __restrict__ len_dst,
+                                                      int* __restrict__ cnt_clear, unsigned long long* __restrict__ live,
+                                                      uint32_t tag, int nb) {
+  extern __shared__ int lds[];
+  int* base = lds;
+  int* start = lds + nb;  // nb + 1 entries
+  const int64_t nsrc = *len_src;
+  const int64_t chunk = (int64_t)blockDim.x * kScatterUnroll;
+  int64_t j0 = (int64_t)blockIdx.x * chunk + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * chunk;
+  int b[kScatterUnroll], sl[kScatterUnroll];
+  uint32_t u[kScatterUnroll];
+  auto load = [&](int64_t j0_, int64_t bound) {
+#pragma unroll
+    for (int q = 0; q < kScatterUnroll; ++q) {
+      const int64_t j = j0_ + (int64_t)q * blockDim.x;
+      const bool in = j < bound;
+      b[q] = in ? nxt_lv[j] : -1;
+      u[q] = in ? nxt_pos[j] : 0u;
+      sl[q] = in ? src_idx[j] : 0;
+    }
+  };
+  load(j0, nsrc);
+  stage_counts(cnt_dst, nb, base);
+  block_layout(base, nb, start, nullptr);
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) {
+      *len_dst = start[nb];
+      if (live)
+        __hip_atomic_store(live, ((unsigned long long)tag << 32) | (uint32_t)start[nb], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    for (int v = threadIdx.x; v < nb; v += blockDim.x) cnt_clear[v] = 0;
+  }
+  for (; j0 < nsrc; j0 += stride) {
+    int o[kScatterUnroll];
+#pragma unroll
+    for (int q = 0; q < kScatterUnroll; ++q)
+      o[q] = b[q] >= 0 ? seg[(size_t)(u[q] >> kRankBits) * nb + b[q]] : 0;
+#pragma unroll
+    for (int q = 0; q < kScatterUnroll; ++q)
+      if (b[q] >= 0) dst_idx[start[b[q]] + o[q] + (int)(u[q] & ((1u << kRankBits) - 1))] = sl[q];
+    if (j0 + stride < nsrc) load(j0 + stride, nsrc);
+  }
+}
+
 // ---------------------------------------------------------------- step
 #ifndef GV_STEP_WAVES_PER_EU
-#define GV_STEP_WAVES_PER_EU 1
+#define GV_STEP_WAVES_PER_EU 4
 #endif
 template <bool F32, bool PHYS, bool B>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GV_STEP_WAVES_PER_EU))) k_bt_step(DevGeom G, int k, int max_steps, int cb, const int* __restrict__ idx,
                                                   TRec* __restrict__ rec, const int* __restrict__ cnt_cur,
-                                                  int* __restrict__ nxt_lv, int* __restrict__ cnt_next, TCtl C,
+                                                  int* __restrict__ nxt_lv, uint32_t* __restrict__ nxt_pos,
+                                                  int* __restrict__ cnt_next, TCtl C,
                                                   int32_t* __restrict__ out_pv, double* __restrict__ out_step,
                                                   int32_t* __restrict__ out_nsteps, uint32_t* __restrict__ out_flags,
                                                   const int* __restrict__ slot_id, double* __restrict__ ob_step,
@@ -470,11 +536,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GV_STE
       nxt_lv[e] = nlv_out;
     }
     if (act) count_active(&wsum[kWorkSteps]);
-    wave_count(nlv_out >= 0 ? nlv_out : 0, nlv_out >= 0, hist);
+    // place in this workgroup's share of the next bucket
+    const int rank = wave_lds_reserve(nlv_out >= 0 ? nlv_out : 0, nlv_out >= 0, hist);
+    if (nlv_out >= 0) nxt_pos[e] = ((uint32_t)blockIdx.x << kRankBits) | (uint32_t)rank;
   }
   __syncthreads();
+  // the workgroup's share of each next bucket starts where the count stood
   for (int v = threadIdx.x; v < nb; v += blockDim.x)
-    if (hist[v]) atomicAdd(&cnt_next[v], hist[v]);
+    if (hist[v]) C.seg[(size_t)blockIdx.x * nb + v] = atomicAdd(&cnt_next[v], hist[v]);
   for (int i = threadIdx.x; i < kWorkN; i += blockDim.x)
     if (wsum[i]) atomicAdd(&C.work[i], wsum[i]);
 }
