@@ -469,6 +469,36 @@ extern "C" int geom_load(const void* blob, size_t nbytes, gv_geom** out) {
         grp_box32.insert(grp_box32.end(), {lo32[0], lo32[1], lo32[2], hi32[0], hi32[1], hi32[2], 0.0f, 0.0f});
       }
     }
+    // radial order: LVs with >= kCullMin daughters that are all identity-placed
+    // full tubes whose radial ranges [rmin, rmax] are pairwise disjoint
+    std::vector<int> lv_rad(n_lv, -1), rad_k;
+    std::vector<double> rad_r2;
+    for (int i = 0; i < n_lv; ++i) {
+      const int c = lv_dcnt[i], o = lv_doff[i];
+      if (c < kCullMin) continue;
+      bool ok = true;
+      std::vector<std::pair<double, int>> by_r;
+      for (int k = 0; k < c && ok; ++k) {
+        const int clv = dau_lv[o + k];
+        const double* q = par.data() + lv_par[clv];
+        ok = lv_type[clv] == kTubs && dau_ident[o + k] && q[L::TB_PHI] == 0.0;
+        if (ok) by_r.push_back({q[L::TB_RMIN], k});
+      }
+      if (!ok) continue;
+      std::sort(by_r.begin(), by_r.end());
+      for (size_t m = 1; m < by_r.size() && ok; ++m) {
+        const double* qa = par.data() + lv_par[dau_lv[o + by_r[m - 1].second]];
+        ok = qa[L::TB_RMAX] < by_r[m].first;
+      }
+      if (!ok) continue;
+      lv_rad[i] = (int)rad_k.size();
+      for (auto& e : by_r) {
+        const double* q = par.data() + lv_par[dau_lv[o + e.second]];
+        rad_r2.push_back(q[L::TB_RMIN] * q[L::TB_RMIN]);
+        rad_r2.push_back(q[L::TB_RMAX] * q[L::TB_RMAX]);
+        rad_k.push_back(e.second);
+      }
+    }
     // count the tree first (depth and size limits also reject cycles)
     std::vector<long> subtree(n_lv, -1);
     std::vector<int> state(n_lv, 0), height(n_lv, 0);
@@ -553,7 +583,9 @@ extern "C" int geom_load(const void* blob, size_t nbytes, gv_geom** out) {
         {dau_box.data(), dau_box.size() * 8, 0},   {lv_scr.data(), lv_scr.size() * 4, 0},
         {dau_box32.data(), dau_box32.size() * 4, 0}, {dau_scr32.data(), dau_scr32.size() * 4, 0},
         {dau_ident.data(), dau_ident.size() * 4, 0}, {lv_grp.data(), lv_grp.size() * 4, 0},
-        {grp_box.data(), grp_box.size() * 8, 0},     {grp_box32.data(), grp_box32.size() * 4, 0}};
+        {grp_box.data(), grp_box.size() * 8, 0},     {grp_box32.data(), grp_box32.size() * 4, 0},
+        {lv_rad.data(), lv_rad.size() * 4, 0},       {rad_r2.data(), rad_r2.size() * 8, 0},
+        {rad_k.data(), rad_k.size() * 4, 0}};
     size_t total = 0;
     for (auto& p : parts) {
       p.off = total;
@@ -607,6 +639,9 @@ extern "C" int geom_load(const void* blob, size_t nbytes, gv_geom** out) {
     D.lv_grp = (CQI)(base + parts[19].off);
     D.grp_box = (CQ)(base + parts[20].off);
     D.grp_box32 = (CQF)(base + parts[21].off);
+    D.lv_rad = (CQI)(base + parts[22].off);
+    D.rad_r2 = (CQ)(base + parts[23].off);
+    D.rad_k = (CQI)(base + parts[24].off);
     g->n_lv = n_lv;
     g->n_pv = (int)npv;
     g->n_place = n_place;
@@ -1249,7 +1284,7 @@ extern "C" int gv_profile(gv_geom* g, int enable) {
 }
 
 extern "C" int gv_profile_read(gv_geom* g, double* step_ms, int64_t* step_launches, uint64_t* work) {
-  static_assert(kWorkN == 24, "gvgeom.h documents 24 work counters");
+  static_assert(kWorkN == 26, "gvgeom.h documents 26 work counters");
   if (!g) return fail(GV_EINVAL, "gv_profile_read: geometry handle is NULL");
   DeviceGuard dgd(g->device);
   double ms = 0.0;

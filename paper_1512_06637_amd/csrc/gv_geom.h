@@ -36,6 +36,11 @@ struct DevGeom {
   CQI lv_grp;        // [n_lv] index of the LV's first group box, -1 without groups
   CQ grp_box;        // [n_grp][6] union of the group's padded daughter boxes (lo xyz, hi xyz)
   CQF grp_box32;     // [n_grp][8] union of the group's FP32 boxes; 2 unused
+  // radial order: an LV whose daughters are identity-placed full tubes with
+  // disjoint radial ranges lists them by radius
+  CQI lv_rad;        // [n_lv] first entry of the LV's radial list, -1 without one
+  CQ rad_r2;         // [n_rad][2] rmin^2, rmax^2 in radial order
+  CQI rad_k;         // [n_rad] daughter index (placement order) of each entry
   // materials for physics-limited steps (geom_set_materials); n_mat 0 if unset
   int n_mat, n_proc;
   CQ mat_rate;       // [n_mat][n_proc] n sigma = 1 / mean free path, 1/mm

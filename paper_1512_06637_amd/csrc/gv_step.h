@@ -33,7 +33,9 @@ enum {
   kWorkScr64 = 21,
   kWorkPhys = 22,   // physics-limited steps
   kWorkShort = 23,  // of which taken without geometry (safety short-cut)
-  kWorkN = 24
+  kWorkRadial = 24,    // radial-order lookups (steps in an LV with a radial list)
+  kWorkRadBound = 25,  // crossing-parameter bounds computed by the radial walk
+  kWorkN = 26
 };
 
 // Exact counting inside divergent code: the first active lane adds the number
@@ -273,6 +275,63 @@ __device__ __forceinline__ void daughters_culled(const DevGeom& G, int lv, int o
 
 constexpr int kCullMin = 8;  // LVs with fewer daughters run the plain loop
 
+// Ordered radial walk over an LV's concentric tube daughters (identity
+// placements, full tubes, disjoint radial ranges, listed by radius).  Along a
+// ray r^2(t) = A t^2 + 2 B t + rho^2 is convex: a tube lying outside the
+// start radius can only be entered at or after the parameter where the ray
+// reaches its rmin moving outward, one lying inside only at or after the ray
+// reaches its rmax moving inward, and both parameters grow with the tube's
+// distance from the start radius.  So the tubes are visited outward and then
+// inward from the start; each walk stops at the first tube whose parameter
+// exceeds the best distance so far (or the mother's exit) by more than
+// kTolerance + 1e-6 mm (a margin well above the parameters' rounding), and a
+// tube radially holding the point is evaluated directly.  Equal distances keep
+// the lowest placement index, as the plain loop does.
+template <class W>
+__device__ __forceinline__ void daughters_radial(const DevGeom& G, int r0, int off, int cnt, V3 pl, V3 dl,
+                                                 double dout, double& best, int& bestk, bool& neg, W& w) {
+  CQ R2 = G.rad_r2 + 2 * (size_t)r0;
+  CQI K = G.rad_k + r0;
+  const double rho2 = pl.x * pl.x + pl.y * pl.y;
+  const double A = dl.x * dl.x + dl.y * dl.y, B = pl.x * dl.x + pl.y * dl.y;
+  w.add(kWorkRadial);
+  int j = 0;  // entries with rmin^2 <= rho^2
+  for (int m = 0; m < cnt; ++m) j += R2[2 * m] <= rho2 ? 1 : 0;
+  auto eval = [&](int m) {
+    const int k = K[m];
+    w.add(kWorkFull + kTubs);
+    double t = Tubs::dist_in(G.par + G.dau_par[off + k], pl, dl);
+    neg = neg || t < 0.0;
+    t = fmax(t, 0.0);
+    if (t < best || (t == best && k < bestk)) {
+      best = t;
+      bestk = k;
+    }
+  };
+  auto beyond = [&](double t) { return t - 1e-6 - 1e-12 * t > fmin(best, dout) + kTol; };
+  const bool holds = j > 0 && rho2 <= R2[2 * (j - 1) + 1];
+  if (holds) eval(j - 1);
+  if (!(A > 0.0)) return;  // parallel to the axis: the radius never changes
+  for (int m = j; m < cnt; ++m) {  // outward: larger root of A t^2 + 2 B t + (rho^2 - rmin^2), C < 0
+    const double C = rho2 - R2[2 * m];
+    const double sq = sqrt(B * B - A * C);
+    const double t = B <= 0.0 ? (sq - B) / A : -C / (B + sq);
+    w.add(kWorkRadBound);
+    if (beyond(t)) break;
+    eval(m);
+  }
+  if (!(B < 0.0)) return;  // moving outward: the radius only grows
+  for (int m = holds ? j - 2 : j - 1; m >= 0; --m) {  // inward: smaller root with rmax^2, C > 0
+    const double C = rho2 - R2[2 * m + 1];
+    const double disc = B * B - A * C;
+    if (disc < -1e-12 * (B * B + A * C)) break;  // misses rmax_m, hence every inner tube
+    const double t = C / (sqrt(fmax(disc, 0.0)) - B);
+    w.add(kWorkRadBound);
+    if (beyond(t)) break;
+    eval(m);
+  }
+}
+
 // One ComputeStep of a track in placed volume pv (logical volume lv) with no
 // physics limit.  Valid for any lv; fastest when lv is wavefront-uniform.
 template <bool F32, bool B, class W>
@@ -290,7 +349,10 @@ __device__ __forceinline__ double step_culled(const DevGeom& G, int lv, int pv, 
   int bestk = -1;
   const int off = G.lv_dau_off[lv], cnt = G.lv_dau_cnt[lv], dtype = G.lv_dau_type[lv];
   bool neg = false;
-  if (dtype == kBox && cnt >= kCullMin) {
+  const int rad = G.lv_rad[lv];
+  if (rad >= 0) {
+    daughters_radial(G, rad, off, cnt, pl, dl, dout, best, bestk, neg, w);
+  } else if (dtype == kBox && cnt >= kCullMin) {
     daughters_culled<Box, F32>(G, lv, off, cnt, pl, dl, dout, best, bestk, neg, w);
   } else if (dtype == kTubs && cnt >= kCullMin) {
     daughters_culled<Tubs, F32>(G, lv, off, cnt, pl, dl, dout, best, bestk, neg, w);

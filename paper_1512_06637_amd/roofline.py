@@ -65,10 +65,20 @@ DIST_IN = {0: BOX_DIST_IN, 1: TUBE_DIST_IN}
 DIST_OUT = {"world": BOX_DIST_OUT, "layer": TUBE_DIST_OUT, "module": BOX_DIST_OUT}
 
 
+# Radial walk (an LV whose daughters are concentric tubes, the detector's
+# world): per step rho^2, A, B (9), the count of tubes with rmin^2 <= rho^2
+# over the world's 20 tubes (2 each) and the holding test (1); per crossing
+# bound C, the discriminant, a square root, the stable root and the margin
+# test (12).
+RADIAL_LOOKUP = 9 + 2 * 20 + 1
+RADIAL_BOUND = 12
+
+
 def detector_ops_culled(world, layer, module, work) -> float:
     """Operation count of the culled navigator from the library's work counters
     ([0] steps, [1] box tests, [2+t] bound checks, [8+t] culled DistanceToIn,
-    [14+t] plain DistanceToIn, t = daughter solid type)."""
+    [14+t] plain DistanceToIn, t = daughter solid type, [24] radial lookups,
+    [25] radial crossing bounds)."""
     fixed = TRANSFORM + STEP_FIXED
     ops = world * (fixed + DIST_OUT["world"] + RAY_SETUP) + layer * (fixed + DIST_OUT["layer"] + RAY_SETUP)
     ops += module * (fixed + DIST_OUT["module"])
@@ -77,4 +87,6 @@ def detector_ops_culled(world, layer, module, work) -> float:
         ops += work[2 + t] * (12 + SAFETY_IN[t])
         ops += work[8 + t] * (9 + DIST_IN[t] + SELECT)
         ops += work[14 + t] * (TRANSFORM + DIST_IN[t] + SELECT)
+    if len(work) > 25:
+        ops += work[24] * RADIAL_LOOKUP + work[25] * RADIAL_BOUND
     return float(ops)
