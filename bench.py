@@ -458,7 +458,8 @@ def main():
                      "kernel_ms_per_transport": step_ms, "ops_per_transport": ops},
         "work": {"plain_navigator_ops": ops_plain, "culled_ops": ops, "daughter_box_tests": work[1],
                  "bound_checks_box_tube": work[2:4], "dist_in_box_tube": work[8:10], "steps": work[0],
-                 "radial_lookups": work[24], "radial_bounds": work[25]},
+                 "radial_lookups": work[24], "radial_bounds": work[25], "phi_lookups": work[26],
+                 "phi_sectors_read": work[27]},
         "wall_s": wall,
         "flags_nonzero": int((flags != 0).sum()),
     }

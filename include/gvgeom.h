@@ -214,7 +214,7 @@ int nav_transport_phys(gv_geom* g, int64_t n, const double* x, const double* y, 
  * kernel.  gv_profile_read waits for those events and returns the summed
  * kernel milliseconds and the number of launches since the last read (then
  * forgets them), and, if `work` is not NULL, the operation counts of the last
- * basket transport (host array of 26 uint64: [0] steps taken, [1] daughter
+ * basket transport (host array of 28 uint64: [0] steps taken, [1] daughter
  * bounding-box tests, [2+t] daughter lower-bound checks, [8+t] daughter
  * DistanceToIn evaluations in culled loops (and radial walks), [14+t]
  * DistanceToIn evaluations in plain loops, t = daughter solid type 0..5
@@ -222,7 +222,8 @@ int nav_transport_phys(gv_geom* g, int64_t n, const double* x, const double* y, 
  * screened in FP32, [21] those screened in FP64, [22] physics-limited steps,
  * [23] of which taken by the safety short-cut, [24] steps in an LV whose
  * daughters are walked in radial order, [25] crossing-parameter bounds of
- * those walks).  Reading synchronises the device. */
+ * those walks, [26] steps whose daughters came from phi sectors, [27] sector
+ * masks read).  Reading synchronises the device. */
 int gv_profile(gv_geom* g, int enable);
 int gv_profile_read(gv_geom* g, double* step_ms, int64_t* step_launches, uint64_t* work);
 

@@ -21,7 +21,7 @@ OUTSIDE, SURFACE, INSIDE = 0, 1, 2
 TO_IN, TO_OUT = 0, 1
 SAFETY_AUTO, SAFETY_IN, SAFETY_OUT = 0, 1, 2
 FP64, FP32_REFINE = 0, 1
-WORK_N = 26  # work counters returned by gv_profile_read
+WORK_N = 28  # work counters returned by gv_profile_read
 PHYS_SAFETY_SHORTCUT = 1
 FLAG_OVERFLOW, FLAG_STUCK, FLAG_LOCATE_FAIL = 1, 2, 4
 
@@ -255,7 +255,7 @@ class Geometry:
         t = daughter solid type, [20] culled track-steps screened in FP32, [21] culled
         track-steps screened in FP64, [22] physics-limited steps, [23] of which taken
         by the safety short-cut, [24] radial-order lookups, [25] radial crossing
-        bounds)."""
+        bounds, [26] phi-sector lookups, [27] sectors read)."""
         ms = C.c_double(0.0)
         launches = C.c_int64(0)
         work = (C.c_uint64 * WORK_N)()

@@ -499,6 +499,61 @@ extern "C" int geom_load(const void* blob, size_t nbytes, gv_geom** out) {
         rad_k.push_back(e.second);
       }
     }
+    // phi sectors: LVs without a radial list, with kCullMin..64 daughters of one
+    // type (box or tube) that each lie within less than a half turn around the
+    // z axis (angular extent of the corners of the child's padded local box
+    // through its placement, in the mother frame)
+    std::vector<int> lv_phi(n_lv, -1);
+    std::vector<unsigned long long> phi_mask;
+    for (int i = 0; i < n_lv; ++i) {
+      const int c = lv_dcnt[i], o = lv_doff[i];
+      if (lv_rad[i] >= 0 || c < kCullMin || c > 64 || (lv_dtype[i] != kBox && lv_dtype[i] != kTubs)) continue;
+      std::vector<unsigned long long> m(kPhiSectors, 0ull);
+      bool ok = true;
+      for (int k = 0; k < c && ok; ++k) {
+        const int clv = dau_lv[o + k];
+        double lo[3], hi[3];
+        local_extent(lv_type[clv], par.data() + lv_par[clv], lo, hi);
+        const double* X = &dau_xf[12 * (size_t)(o + k)];
+        double ang[8], sx = 0.0, sy = 0.0;
+        for (int q = 0; q < 8; ++q) {
+          const double v[3] = {(q & 1) ? hi[0] + 1e-6 : lo[0] - 1e-6, (q & 2) ? hi[1] + 1e-6 : lo[1] - 1e-6,
+                               (q & 4) ? hi[2] + 1e-6 : lo[2] - 1e-6};
+          const double X0 = X[0] * v[0] + X[1] * v[1] + X[2] * v[2] + X[9];
+          const double Y0 = X[3] * v[0] + X[4] * v[1] + X[5] * v[2] + X[10];
+          ang[q] = std::atan2(Y0, X0);
+          sx += X0;
+          sy += Y0;
+          ok = ok && X0 * X0 + Y0 * Y0 > 1e-6;
+        }
+        const double am = std::atan2(sy, sx);
+        double alo = HUGE_VAL, ahi = -HUGE_VAL;
+        for (double a : ang) {
+          double d = a - am;  // unwrapped around the mean direction
+          while (d > M_PI) d -= 2.0 * M_PI;
+          while (d <= -M_PI) d += 2.0 * M_PI;
+          alo = std::min(alo, d);
+          ahi = std::max(ahi, d);
+        }
+        ok = ok && ahi - alo < 0.9 * M_PI;
+        if (!ok) break;
+        // pseudo-angle interval, widened by 1e-4 (rounding of the lane's angles
+        // is ~1e-15), swept counterclockwise from plo to phi
+        const double plo = pseudo_angle(std::cos(am + alo), std::sin(am + alo)) - 1e-4;
+        const double phi = pseudo_angle(std::cos(am + ahi), std::sin(am + ahi)) + 1e-4;
+        auto sec = [](double a) {
+          a = std::fmod(a + 4.0, 4.0);
+          return std::min(kPhiSectors - 1, std::max(0, (int)(a * (kPhiSectors / 4.0))));
+        };
+        for (int s0 = sec(plo), s = s0;; s = (s + 1) % kPhiSectors) {
+          m[s] |= 1ull << k;
+          if (s == sec(phi)) break;
+        }
+      }
+      if (!ok) continue;
+      lv_phi[i] = (int)phi_mask.size();
+      phi_mask.insert(phi_mask.end(), m.begin(), m.end());
+    }
     // count the tree first (depth and size limits also reject cycles)
     std::vector<long> subtree(n_lv, -1);
     std::vector<int> state(n_lv, 0), height(n_lv, 0);
@@ -585,7 +640,8 @@ extern "C" int geom_load(const void* blob, size_t nbytes, gv_geom** out) {
         {dau_ident.data(), dau_ident.size() * 4, 0}, {lv_grp.data(), lv_grp.size() * 4, 0},
         {grp_box.data(), grp_box.size() * 8, 0},     {grp_box32.data(), grp_box32.size() * 4, 0},
         {lv_rad.data(), lv_rad.size() * 4, 0},       {rad_r2.data(), rad_r2.size() * 8, 0},
-        {rad_k.data(), rad_k.size() * 4, 0}};
+        {rad_k.data(), rad_k.size() * 4, 0},         {lv_phi.data(), lv_phi.size() * 4, 0},
+        {phi_mask.data(), phi_mask.size() * 8, 0}};
     size_t total = 0;
     for (auto& p : parts) {
       p.off = total;
@@ -642,6 +698,8 @@ extern "C" int geom_load(const void* blob, size_t nbytes, gv_geom** out) {
     D.lv_rad = (CQI)(base + parts[22].off);
     D.rad_r2 = (CQ)(base + parts[23].off);
     D.rad_k = (CQI)(base + parts[24].off);
+    D.lv_phi = (CQI)(base + parts[25].off);
+    D.phi_mask = (CQL)(base + parts[26].off);
     g->n_lv = n_lv;
     g->n_pv = (int)npv;
     g->n_place = n_place;
@@ -1284,7 +1342,7 @@ extern "C" int gv_profile(gv_geom* g, int enable) {
 }
 
 extern "C" int gv_profile_read(gv_geom* g, double* step_ms, int64_t* step_launches, uint64_t* work) {
-  static_assert(kWorkN == 26, "gvgeom.h documents 26 work counters");
+  static_assert(kWorkN == 28, "gvgeom.h documents 28 work counters");
   if (!g) return fail(GV_EINVAL, "gv_profile_read: geometry handle is NULL");
   DeviceGuard dgd(g->device);
   double ms = 0.0;

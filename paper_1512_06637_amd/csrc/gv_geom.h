@@ -10,6 +10,8 @@ namespace gv {
 
 // All arrays live in HBM; geom_load fills them once.  Transforms are 12
 // doubles: R row-major then t, with x_mother = R x_child + t.
+constexpr int kPhiSectors = 256;
+
 struct DevGeom {
   int n_lv, n_pv, n_place;
   CQI lv_type;       // [n_lv]
@@ -41,6 +43,11 @@ struct DevGeom {
   CQI lv_rad;        // [n_lv] first entry of the LV's radial list, -1 without one
   CQ rad_r2;         // [n_rad][2] rmin^2, rmax^2 in radial order
   CQI rad_k;         // [n_rad] daughter index (placement order) of each entry
+  // phi sectors: an LV whose (<= 64) daughters lie around the z axis, each
+  // within less than a half turn, has kPhiSectors masks of the daughters
+  // whose angular extent (widened) meets each sector of pseudo-angle
+  CQI lv_phi;        // [n_lv] first mask of the LV, -1 without sectors
+  CQL phi_mask;      // [n_phi_lv][kPhiSectors]
   // materials for physics-limited steps (geom_set_materials); n_mat 0 if unset
   int n_mat, n_proc;
   CQ mat_rate;       // [n_mat][n_proc] n sigma = 1 / mean free path, 1/mm

@@ -59,6 +59,16 @@ struct V3 {
 typedef const __attribute__((address_space(4))) double* CQ;
 typedef const __attribute__((address_space(4))) int* CQI;
 typedef const __attribute__((address_space(4))) float* CQF;
+typedef const __attribute__((address_space(4))) unsigned long long* CQL;
+
+// Pseudo-angle of (x, y) around the z axis: a monotone map of the polar angle
+// [0, 2 pi) onto [0, 4), one unit per quadrant, with a half turn adding
+// exactly 2 (modulo 4).  One division instead of an arctangent.
+__host__ __device__ inline double pseudo_angle(double x, double y) {
+  const double s = fabs(x) + fabs(y);
+  if (y >= 0.0) return x >= 0.0 ? y / s : 1.0 - x / s;
+  return x < 0.0 ? 2.0 - y / s : 3.0 + x / s;
+}
 
 // 1/d from the hardware reciprocal plus one Newton step: within a few ulp
 // (11 ulp worst over 2^22 random operands), i.e. 3e-15 relative, three orders

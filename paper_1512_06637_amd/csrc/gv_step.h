@@ -35,7 +35,9 @@ enum {
   kWorkShort = 23,  // of which taken without geometry (safety short-cut)
   kWorkRadial = 24,    // radial-order lookups (steps in an LV with a radial list)
   kWorkRadBound = 25,  // crossing-parameter bounds computed by the radial walk
-  kWorkN = 26
+  kWorkPhi = 26,       // phi-sector lookups
+  kWorkPhiSec = 27,    // sectors whose masks were read
+  kWorkN = 28
 };
 
 // Exact counting inside divergent code: the first active lane adds the number
@@ -332,6 +334,81 @@ __device__ __forceinline__ void daughters_radial(const DevGeom& G, int r0, int o
   }
 }
 
+// Daughters by phi sector: the ray's segment [0, exit + kTolerance] seen from
+// the z axis sweeps an angle of less than a half turn (it does not pass within
+// 1e-3 (|p|inf + 1) mm of the axis, else the culled loop runs instead); the
+// union of the masks of the sectors it sweeps holds every daughter whose
+// extent it can meet, and those candidates go through the SafetyToIn bound
+// and DistanceToIn in index order, as in the culled loop's second pass.
+template <class S, bool F32, class W>
+__device__ __forceinline__ void daughters_phi(const DevGeom& G, int lv, int m0, int off, int cnt, V3 pl, V3 dl,
+                                              double dout, double& best, int& bestk, bool& neg, W& w) {
+  const double T = dout + kTol;
+  const double A = dl.x * dl.x + dl.y * dl.y;
+  const double tc = A > 0.0 ? fmin(fmax(-(pl.x * dl.x + pl.y * dl.y) / A, 0.0), T) : 0.0;
+  const double cx = pl.x + tc * dl.x, cy = pl.y + tc * dl.y;
+  const double guard = 1e-3 * (fmax(fmax(fabs(pl.x), fabs(pl.y)), fabs(pl.z)) + 1.0);
+  if (!(cx * cx + cy * cy > guard * guard) || !(T < GV_INF)) {
+    daughters_culled<S, F32>(G, lv, off, cnt, pl, dl, dout, best, bestk, neg, w);
+    return;
+  }
+  w.add(kWorkPhi);
+  const double a0 = pseudo_angle(pl.x, pl.y), a1 = pseudo_angle(pl.x + T * dl.x, pl.y + T * dl.y);
+  const bool ccw = pl.x * dl.y - pl.y * dl.x >= 0.0;
+  auto sec = [](double a) { return min(kPhiSectors - 1, max(0, (int)(a * (kPhiSectors / 4.0)))); };
+  const int s1 = sec(ccw ? a1 : a0);
+  CQL M = G.phi_mask + (size_t)m0;
+  uint64_t cand = 0;
+  int ns = 0;
+  for (int s = sec(ccw ? a0 : a1);; s = (s + 1) & (kPhiSectors - 1)) {
+    cand |= M[s];
+    ++ns;
+    if (s == s1) break;
+  }
+  w.add(kWorkPhiSec, (unsigned)ns);
+  // FP32 screen of the bound (as in the culled loop): only when every active
+  // lane's point and exit lie in the range the FP32 margins cover
+  bool use32 = false;
+  F3 p32{};
+  float pmax = 0.0f;
+  if (F32) {
+    p32 = F3{(float)pl.x, (float)pl.y, (float)pl.z};
+    pmax = max3f(fabsf(p32.x), fabsf(p32.y), fabsf(p32.z));
+    const float sl = G.lv_scr[lv];
+    use32 = __ballot(!(pmax <= sl && dout + kTol <= 4.0 * (double)sl)) == 0;
+    w.add(use32 ? kWorkScr32 : kWorkScr64, 1);
+  }
+  while (cand) {
+    const int k = __builtin_ctzll(cand);
+    cand &= cand - 1;
+    const int pk = off + k;
+    CQ Y = G.dau_xf + 12 * (size_t)pk;
+    CQ q = G.par + G.dau_par[pk];
+    const bool ident = G.dau_ident[pk] != 0;
+    const double thr = fmin(best, dout) + kTol;
+    w.add(kWorkBound + S::kType);
+    V3 pc = pl;
+    if (use32) {
+      const float lb = lower_bound32<S>(G.dau_scr32 + 16 * (size_t)pk, p32, pmax);
+      const float t32 = (float)thr;
+      if (lb > fmaf(4.0f * kU32, t32, t32)) continue;
+      if (!ident) pc = to_child_p(Y, pl);
+    } else {
+      if (!ident) pc = to_child_p(Y, pl);
+      if (S::safety_in(q, pc) > thr) continue;
+    }
+    w.add(kWorkFull + S::kType);
+    const V3 dc = ident ? dl : to_child_d(Y, dl);
+    double t = S::dist_in(q, pc, dc);
+    neg = neg || t < 0.0;
+    t = fmax(t, 0.0);
+    if (t < best) {
+      best = t;
+      bestk = k;
+    }
+  }
+}
+
 // One ComputeStep of a track in placed volume pv (logical volume lv) with no
 // physics limit.  Valid for any lv; fastest when lv is wavefront-uniform.
 template <bool F32, bool B, class W>
@@ -349,9 +426,13 @@ __device__ __forceinline__ double step_culled(const DevGeom& G, int lv, int pv, 
   int bestk = -1;
   const int off = G.lv_dau_off[lv], cnt = G.lv_dau_cnt[lv], dtype = G.lv_dau_type[lv];
   bool neg = false;
-  const int rad = G.lv_rad[lv];
+  const int rad = G.lv_rad[lv], phs = G.lv_phi[lv];
   if (rad >= 0) {
     daughters_radial(G, rad, off, cnt, pl, dl, dout, best, bestk, neg, w);
+  } else if (phs >= 0 && dtype == kBox) {
+    daughters_phi<Box, F32>(G, lv, phs, off, cnt, pl, dl, dout, best, bestk, neg, w);
+  } else if (phs >= 0 && dtype == kTubs) {
+    daughters_phi<Tubs, F32>(G, lv, phs, off, cnt, pl, dl, dout, best, bestk, neg, w);
   } else if (dtype == kBox && cnt >= kCullMin) {
     daughters_culled<Box, F32>(G, lv, off, cnt, pl, dl, dout, best, bestk, neg, w);
   } else if (dtype == kTubs && cnt >= kCullMin) {

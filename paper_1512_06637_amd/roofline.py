@@ -72,13 +72,19 @@ DIST_OUT = {"world": BOX_DIST_OUT, "layer": TUBE_DIST_OUT, "module": BOX_DIST_OU
 # test (12).
 RADIAL_LOOKUP = 9 + 2 * 20 + 1
 RADIAL_BOUND = 12
+# Phi sectors (the detector's layers): per step the segment end (4), the
+# closest approach to the axis (13), its guard (7), two pseudo-angles (8 each,
+# with a division), the turning sense (3) and two sector indices (4); per
+# sector read one OR and one compare.
+PHI_LOOKUP = 4 + 13 + 7 + 16 + 3 + 4
+PHI_SECTOR = 2
 
 
 def detector_ops_culled(world, layer, module, work) -> float:
     """Operation count of the culled navigator from the library's work counters
     ([0] steps, [1] box tests, [2+t] bound checks, [8+t] culled DistanceToIn,
     [14+t] plain DistanceToIn, t = daughter solid type, [24] radial lookups,
-    [25] radial crossing bounds)."""
+    [25] radial crossing bounds, [26] phi-sector lookups, [27] sectors read)."""
     fixed = TRANSFORM + STEP_FIXED
     ops = world * (fixed + DIST_OUT["world"] + RAY_SETUP) + layer * (fixed + DIST_OUT["layer"] + RAY_SETUP)
     ops += module * (fixed + DIST_OUT["module"])
@@ -89,4 +95,6 @@ def detector_ops_culled(world, layer, module, work) -> float:
         ops += work[14 + t] * (TRANSFORM + DIST_IN[t] + SELECT)
     if len(work) > 25:
         ops += work[24] * RADIAL_LOOKUP + work[25] * RADIAL_BOUND
+    if len(work) > 27:
+        ops += work[26] * PHI_LOOKUP + work[27] * PHI_SECTOR
     return float(ops)
