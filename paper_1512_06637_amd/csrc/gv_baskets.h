@@ -488,7 +488,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GV_STE
     int nlv_out = -1;
     if (act) {
       const int sl = idx[e];
-      const int id = slot_id[sl];
+      // the track id is a dependent gather: read it only where it is needed
+      const int id = (PHYS || !ob_step) ? slot_id[sl] : -1;
       TRec r = rec[sl];
       V3 p{r.x, r.y, r.z}, d{r.dx, r.dy, r.dz};
       uint32_t fl = zfc_fl(r.zfc);
@@ -520,8 +521,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GV_STE
         done = true;
       }
       if (done) {
-        out_nsteps[id] = k + 1;
-        out_flags[id] = fl;
+        const int tid = id >= 0 ? id : slot_id[sl];
+        out_nsteps[tid] = k + 1;
+        out_flags[tid] = fl;
       } else {
         // the whole 64-byte record in one go: full-line writes need no
         // read-modify-write of the line
