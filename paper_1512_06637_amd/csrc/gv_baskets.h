@@ -241,7 +241,7 @@ __global__ void __launch_bounds__(256) k_bt_emit(const double* __restrict__ ob_s
   __shared__ double ts[64][65];
   __shared__ int tp[64][65];
   __shared__ int8_t tq[PROC ? 64 : 1][65];
-  __shared__ int sid[64], sns[64];
+  __shared__ int sid[64], sns[64], kwg;
   const int64_t s0 = (int64_t)blockIdx.x * 64;
   const int64_t nl = *C.nlive;
   if (s0 >= nl) return;  // the whole workgroup leaves together
@@ -251,17 +251,23 @@ __global__ void __launch_bounds__(256) k_bt_emit(const double* __restrict__ ob_s
     int id = 0, ns = 0;
     if (sl < nl) {
       id = slot_id[sl];
-      ns = out_nsteps[id];
+      ns = min(out_nsteps[id], kmax);
     }
     sid[threadIdx.x] = id;
     sns[threadIdx.x] = ns;
+    int m = ns;  // the workgroup's longest track bounds its step loop
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o));
+    if (threadIdx.x == 0) kwg = m;
   }
-  for (int k0 = 0; k0 < kmax; k0 += 64) {
+  __syncthreads();
+  const int kend = kwg;
+  for (int k0 = 0; k0 < kend; k0 += 64) {
     __syncthreads();
     for (int r = wv; r < 64; r += 4) {  // row r = step k0 + r, lanes = slots
       const int k = k0 + r;
       const int64_t sl = s0 + lane;
-      if (k < kmax && sl < nl) {
+      if (k < sns[lane]) {  // steps a slot did not take hold stale values
         ts[lane][r] = ob_step[(size_t)k * cap + sl];
         tp[lane][r] = ob_pv[(size_t)k * cap + sl];
         if (PROC) tq[lane][r] = ob_proc[(size_t)k * cap + sl];
