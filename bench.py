@@ -435,6 +435,11 @@ def main():
     ops_plain = R.detector_ops(world, layer, module)
     ops = R.detector_ops_culled(world, layer, module, work)
     achieved = ops / (step_ms * 1e-3)
+    # the step kernel's bound: its arithmetic intensity against the machine balance
+    bytes_launch = total_steps / max(1.0, launches / args.steps) * R.STEP_BYTES
+    intensity = ops / (total_steps * R.STEP_BYTES)
+    bound_hbm = intensity < R.PEAK_FP64_OPS / R.PEAK_HBM
+    achieved_gbs = bytes_launch / (launch_ms * 1e-3) / 1e9
     res = {
         "metric": "track-steps/s",
         "value": total_steps / (ms * 1e-3),
@@ -451,11 +456,17 @@ def main():
         "config": {"workload": "layered-detector navigation FP64: 2^20 origin tracks to world exit, 1301 PVs",
                    "tracks": n, "track_steps": total_steps, "max_steps": max_steps,
                    "steps_world_layer_module": [world, layer, module]},
-        "roofline": {"bound": "alu", "kernel": "k_bt_step", "achieved": achieved / 1e12,
-                     "peak": R.PEAK_FP64_OPS / 1e12, "unit": "TOP/s (FP64 lane-ops)",
-                     "frac": achieved / R.PEAK_FP64_OPS, "traffic": measured_traffic(),
+        "roofline": ({"bound": "hbm", "kernel": "k_bt_step", "achieved": achieved_gbs, "peak": R.PEAK_HBM / 1e9,
+                      "unit": "GB/s", "frac": achieved_gbs * 1e9 / R.PEAK_HBM} if bound_hbm else
+                     {"bound": "alu", "kernel": "k_bt_step", "achieved": achieved / 1e12,
+                      "peak": R.PEAK_FP64_OPS / 1e12, "unit": "TOP/s (FP64 lane-ops)",
+                      "frac": achieved / R.PEAK_FP64_OPS}) | {
+                     "traffic": measured_traffic(), "bytes_per_launch": bytes_launch,
                      "launches_per_transport": launches / args.steps, "avg_launch_ms": launch_ms,
-                     "kernel_ms_per_transport": step_ms, "ops_per_transport": ops},
+                     "kernel_ms_per_transport": step_ms,
+                     "alu": {"ops_per_transport": ops, "achieved_TOPs": achieved / 1e12,
+                             "frac": achieved / R.PEAK_FP64_OPS, "ops_per_byte": intensity,
+                             "machine_balance_ops_per_byte": R.PEAK_FP64_OPS / R.PEAK_HBM}},
         "work": {"plain_navigator_ops": ops_plain, "culled_ops": ops, "daughter_box_tests": work[1],
                  "bound_checks_box_tube": work[2:4], "dist_in_box_tube": work[8:10], "steps": work[0],
                  "radial_lookups": work[24], "radial_bounds": work[25], "phi_lookups": work[26],

@@ -25,6 +25,13 @@ OPS_WORLD_STEP = TRANSFORM + BOX_DIST_OUT + 20 * (TRANSFORM + TUBE_DIST_IN + SEL
 OPS_LAYER_STEP = TRANSFORM + TUBE_DIST_OUT + 64 * (TRANSFORM + BOX_DIST_IN + SELECT) + STEP_FIXED
 OPS_MODULE_STEP = TRANSFORM + BOX_DIST_OUT + STEP_FIXED
 
+# Algorithmic HBM bytes of one basket step of one track (k_bt_step): its list
+# entry (4), its 64-byte record read and rewritten (128), the staged step length
+# and next volume (12), its next bucket and its place in the next list (8).
+# Geometry tables (a few hundred KB) stay in the caches and are not counted.
+STEP_BYTES = 4 + 128 + 12 + 8
+
+
 # bytes that must move per track of a transport: the SoA start state in
 # (6 doubles) and the outputs (start PV, per step one int32 PV and one double
 # step, nsteps, flags)
