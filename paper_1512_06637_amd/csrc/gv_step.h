@@ -41,7 +41,8 @@ enum {
 };
 
 // Exact counting inside divergent code: the first active lane adds the number
-// of active lanes (times `mult`) to an LDS counter of the workgroup.
+// of active lanes (times `mult`, which must be wavefront-uniform) to an LDS
+// counter of the workgroup.
 __device__ __forceinline__ void count_active(unsigned long long* ctr, unsigned mult = 1) {
   uint64_t m = __ballot(1);
   if ((int)__lane_id() == __ffsll((unsigned long long)m) - 1) atomicAdd(ctr, (unsigned long long)__popcll(m) * mult);
@@ -359,13 +360,11 @@ __device__ __forceinline__ void daughters_phi(const DevGeom& G, int lv, int m0, 
   const int s1 = sec(ccw ? a1 : a0);
   CQL M = G.phi_mask + (size_t)m0;
   uint64_t cand = 0;
-  int ns = 0;
   for (int s = sec(ccw ? a0 : a1);; s = (s + 1) & (kPhiSectors - 1)) {
     cand |= M[s];
-    ++ns;
+    w.add(kWorkPhiSec);
     if (s == s1) break;
   }
-  w.add(kWorkPhiSec, (unsigned)ns);
   // FP32 screen of the bound (as in the culled loop): only when every active
   // lane's point and exit lie in the range the FP32 margins cover
   bool use32 = false;

@@ -355,6 +355,44 @@ def composite_tracks(n: int) -> Tracks:
     return Tracks(p[0].copy(), p[1].copy(), p[2].copy(), *isotropic(rng, n))
 
 
+# Index-structure setups.  Nested tubes: a world cube holding 10 identity-
+# placed full tubes with disjoint radial ranges (the innermost a solid
+# cylinder) and unequal lengths, placed out of radial order.  Ring: a world
+# cube holding a box that holds 16 small boxes on a ring of radius 60 mm around
+# the z axis, turned to face the axis.
+def nested_tubes_description():
+    lvs = [LV(box(400.0, 400.0, 400.0), [], "world")]
+    order = [3, 0, 7, 1, 9, 4, 2, 8, 5, 6]
+    for i in order:
+        rmin = 0.0 if i == 0 else 20.0 + 30.0 * i
+        rmax = rmin + 18.0 if i else 12.0
+        dz = 150.0 + 20.0 * ((i * 7) % 5)
+        lvs[0].placements.append((len(lvs), np.eye(3), np.zeros(3)))
+        lvs.append(LV(tubs(rmin, rmax, dz), [], f"tube{i}"))
+    return lvs
+
+
+def ring_description():
+    lvs = [LV(box(200.0, 200.0, 200.0), [], "world"), LV(box(100.0, 100.0, 50.0), [], "holder"),
+           LV(box(6.0, 9.0, 40.0), [], "block")]
+    lvs[0].placements.append((1, np.eye(3), np.array([0.0, 0.0, 10.0])))
+    for k in range(16):
+        phi = TWO_PI * k / 16 + 0.1
+        lvs[1].placements.append((2, rot_z(phi), np.array([60.0 * math.cos(phi), 60.0 * math.sin(phi), 0.0])))
+    return lvs
+
+
+def uniform_world_tracks(half, n: int, seed: int, centre=(0.0, 0.0, 0.0)) -> Tracks:
+    """Starts uniform in the box centre +- half (mm), isotropic directions; one
+    track in eight is parallel to the z axis."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    p = uniform_box_points(rng, n, np.asarray(centre, dtype=np.float64), np.broadcast_to(np.asarray(half, dtype=np.float64), (3,)))
+    dx, dy, dz = isotropic(rng, n)
+    par = np.arange(n) % 8 == 3
+    dx[par], dy[par], dz[par] = 0.0, 0.0, np.where(rng.random(int(par.sum())) < 0.5, 1.0, -1.0)
+    return Tracks(p[0].copy(), p[1].copy(), p[2].copy(), dx, dy, dz)
+
+
 def expand_pvs(lvs: list, world_lv: int = 0):
     """DFS pre-order expansion: list of (lv, parent_pv, R_global, t_global, depth).
     Global transforms are composed here only for test brute force and generators."""
