@@ -1225,7 +1225,7 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
     }
   }
   if (staged && launched_steps > 0) {
-    hipLaunchKernelGGL(ob_proc ? k_bt_emit<true> : k_bt_emit<false>, dim3((unsigned)((n + 63) / 64)), dim3(256), 0,
+    hipLaunchKernelGGL(ob_proc ? k_bt_emit<true> : k_bt_emit<false>, dim3((unsigned)((n + 63) / 64)), dim3(512), 0,
                        s, (const double*)ob_step,
                        (const int*)ob_pv, (const int8_t*)ob_proc, g->ob_cap, (const int*)g->slot_id, C, max_steps,
                        launched_steps, (const int32_t*)out_nsteps, out_step, out_pv, out_proc);

@@ -233,7 +233,7 @@ __global__ void k_bt_place(const int* __restrict__ perm, const double* __restric
 // were run are read; entries past a track's step count are not written.  The
 // process indices of physics-limited transport move along when staged.
 template <bool PROC>
-__global__ void __launch_bounds__(256) k_bt_emit(const double* __restrict__ ob_step, const int* __restrict__ ob_pv,
+__global__ void __launch_bounds__(512) k_bt_emit(const double* __restrict__ ob_step, const int* __restrict__ ob_pv,
                                                  const int8_t* __restrict__ ob_proc, int64_t cap,
                                                  const int* __restrict__ slot_id, TCtl C, int max_steps, int kmax,
                                                  const int32_t* __restrict__ out_nsteps, double* __restrict__ out_step,
@@ -264,7 +264,7 @@ __global__ void __launch_bounds__(256) k_bt_emit(const double* __restrict__ ob_s
   const int kend = kwg;
   for (int k0 = 0; k0 < kend; k0 += 64) {
     __syncthreads();
-    for (int r = wv; r < 64; r += 4) {  // row r = step k0 + r, lanes = slots
+    for (int r = wv; r < 64; r += 8) {  // row r = step k0 + r, lanes = slots
       const int k = k0 + r;
       const int64_t sl = s0 + lane;
       if (k < sns[lane]) {  // steps a slot did not take hold stale values
@@ -274,7 +274,7 @@ __global__ void __launch_bounds__(256) k_bt_emit(const double* __restrict__ ob_s
       }
     }
     __syncthreads();
-    for (int r = wv; r < 64; r += 4) {  // row r = slot s0 + r, lanes = steps
+    for (int r = wv; r < 64; r += 8) {  // row r = slot s0 + r, lanes = steps
       const int k = k0 + lane;
       if (k < sns[r]) {
         const int id = sid[r];
