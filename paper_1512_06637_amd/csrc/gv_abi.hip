@@ -1002,9 +1002,11 @@ namespace {
 
 size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// Bits of the coarse direction cell in a bucket key (LV << bits | cell): 16
-// cells while LVs x cells <= 4096, else 4 cells, else none.
-int coarse_bits(int n_lv) { return n_lv <= 256 ? 4 : n_lv <= 1024 ? 2 : 0; }
+// Bits of the coarse direction cell in a bucket key (LV << bits | cell): 4
+// cells (2 x 2) while LVs x cells <= 4096, else none.  Finer cells (16) gave
+// the same step time with the daughter indexes and cost more in the bucket
+// layouts of every step.
+int coarse_bits(int n_lv) { return n_lv <= 1024 ? 2 : 0; }
 
 // Track records, two bucketed index lists, the next-LV array, and per-LV
 // counters and layouts.  Allocated with hipMalloc on first use and kept in the
