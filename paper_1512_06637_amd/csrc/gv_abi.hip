@@ -1182,7 +1182,7 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
   // empty steps are launched, and the device still has a chunk queued while
   // the host looks.  The host reads the word directly rather than through
   // stream events, which would put a system-scope fence between two steps.
-  constexpr int kChunk = 4;
+  constexpr int kChunk = 2;
   int chunk = 0, launched_steps = 0;
   const uint32_t tag0 = g->live_tag + 1;
   for (int k = 0; k < max_steps; ++k) {
