@@ -148,3 +148,60 @@ def test_composite_transport(geos, n):
     a = [cuda(v) for v in t.arrays()]
     for prec in (G.FP64, G.FP32_REFINE):
         assert compare_transport(g.transport(*a, precision=prec), ref) > 0.99 * n
+
+
+# ------------------------------------------------- physics-limited and serving
+COMPOSITE_MAT = {"density": np.array([1.0, 5.0]),
+                 "sigma": np.array([[1e-4, 5e-5], [0.02, 0.01]]),  # mean free paths 1e4, 2e4 / 10, 20 mm
+                 "lv_mat": np.array([0, 1, 1, 1, 1, 1, 1], np.int32)}
+
+
+@pytest.mark.parametrize("n", [4099, 20011])
+def test_composite_phys_transport(geos, n):
+    """Physics-limited transport in the composite geometry (dense composites:
+    many interactions inside them), per-lane and basket paths, against the
+    oracle; the short-cut and the FP32 screens change nothing."""
+    import paper_1512_06637_amd as G
+    from tests.test_gpu_phys import _same, compare_phys
+    g, og = geos
+    g.set_materials(COMPOSITE_MAT["density"], COMPOSITE_MAT["sigma"], COMPOSITE_MAT["lv_mat"])
+    t = W.composite_tracks(n)
+    say(f"[composite phys transport] n={n}")
+    a = [cuda(v) for v in t.arrays()]
+    seed = W.PHYS_SEED + 1
+    got = g.transport_phys(*a, seed, max_steps=256, shortcut=False)
+    ref = og.transport_phys(t, COMPOSITE_MAT, seed, max_steps=256)
+    assert compare_phys(got, ref) > 0.5 * n
+    _same(got, g.transport_phys(*a, seed, max_steps=256, shortcut=True))
+    _same(got, g.transport_phys(*a, seed, max_steps=256, shortcut=True, precision=G.FP32_REFINE))
+
+
+def test_composite_serving(geos):
+    """Mixed baskets served in shared rounds on the composite geometry equal
+    the per-kind entry points and the oracle."""
+    import paper_1512_06637_amd as G
+    from tests.test_gpu_nav import STEP_REL
+    from tests.test_gpu_serve import alone, check_equal, make_baskets, run_server
+    g, og = geos
+    t = W.composite_tracks(6000)
+    pool = (t, og.locate(t.x, t.y, t.z).astype(np.int32))
+    baskets = make_baskets(pool, 40, 23)
+    say(f"[composite serve] {len(baskets)} baskets")
+    with G.Server(g, slots=16, hbm_budget=64 << 20, nstreams=2) as srv:
+        outs, _ = run_server(srv, baskets, pool)
+    _, pv = pool
+    for b, ob in zip(baskets, outs):
+        got = G.unpack_result(b["kind"], ob, b["n"])
+        check_equal(b["kind"], got, alone(g, b, pool))
+        i = b["idx"]
+        sub = t.take(i)
+        if b["kind"] == G.Q_STEP:
+            rs, rn, rf, rd = og.step(sub, pv[i], pstep=b["pstep"])
+            ok = (rd & O.D_ILL) == 0
+            assert np.array_equal(got[1][ok], rn[ok]) and np.array_equal(got[2][ok], rf[ok])
+            assert np.all(np.abs(got[0] - rs)[ok] <= STEP_REL * np.maximum(1, rs[ok]) + 1e-12)
+        elif b["kind"] == G.Q_SAFETY:
+            _, _, bad = compare_values(got, og.nav_safety(sub.x, sub.y, sub.z, pv[i]), what="served safety")
+            assert bad.size == 0
+        else:
+            assert np.array_equal(got, og.nav_inside(sub.x, sub.y, sub.z, pv[i]))
