@@ -104,6 +104,20 @@ struct F3 {
 };
 __device__ __forceinline__ float max3f(float a, float b, float c) { return fmaxf(fmaxf(a, b), c); }
 
+// Reciprocal direction components for the slab screens below, which form
+// (B - p) / d as B * inv + (-p * inv).  A zero (or denormal) component would
+// give an infinite reciprocal and then inf - inf = NaN or an infinity of the
+// wrong sign; a huge finite value of the component's sign keeps the product
+// difference finite with the sign of B - p (|B|, |p| < 2^20 mm).
+__device__ __forceinline__ double inv_dir64(double d) {
+  const double r = rcp_fast(d);
+  return fabs(r) < 0x1p900 ? r : copysign(0x1p900, d);
+}
+__device__ __forceinline__ float inv_dir32(float d) {
+  const float r = __builtin_amdgcn_rcpf(d);
+  return fabsf(r) < 0x1p100f ? r : copysignf(0x1p100f, d);
+}
+
 // Whether a lane's ray may enter a padded box at a parameter in [0, bound]:
 // false only when the ray provably misses the box or meets it beyond the
 // bound.  Undecidable (NaN) comparisons keep the box.
@@ -140,18 +154,15 @@ __device__ __forceinline__ bool box_hit32(CQF B, F3 inv, F3 pin, float bound) {
 constexpr int kGroup = 8, kGroupMin = 16;
 
 // Pass 1 over daughters c0 .. c0+m-1 (m <= 64) of an LV: per lane, the bit mask
-// of daughters whose box the ray may enter within the bound, and in `any` the
-// union over the wavefront's active lanes (wavefront-uniform).  With groups, a
-// group whose box no lane enters skips its members' tests.
+// of daughters whose box the ray may enter within the bound.  With groups, a
+// group whose box no lane of the wavefront enters skips its members' tests.
 template <class Hit, class HitG, class W>
-__device__ __forceinline__ uint64_t box_screen(int c0, int m, int grp, Hit hit, HitG hitg, uint64_t& any, W& w) {
+__device__ __forceinline__ uint64_t box_screen(int c0, int m, int grp, Hit hit, HitG hitg, W& w) {
   uint64_t cand = 0;
-  any = 0;
   if (grp < 0) {
     for (int k = 0; k < m; ++k) {
       const bool h = hit(c0 + k);
       cand |= h ? (1ull << k) : 0ull;
-      any |= __ballot(h) ? (1ull << k) : 0ull;
     }
     w.add(kWorkBox, (unsigned)m);
     return cand;
@@ -164,7 +175,6 @@ __device__ __forceinline__ uint64_t box_screen(int c0, int m, int grp, Hit hit, 
     for (int k = 0; k < mm; ++k) {
       const bool h = gh && hit(c0 + g0 + k);
       cand |= h ? (1ull << (g0 + k)) : 0ull;
-      any |= __ballot(h) ? (1ull << (g0 + k)) : 0ull;
     }
     w.add(kWorkBox, (unsigned)mm);
   }
@@ -217,8 +227,7 @@ __device__ __forceinline__ void daughters_culled(const DevGeom& G, int lv, int o
     use32 = __ballot(!safe) == 0;  // over the active lanes: all must be in range
     w.add(use32 ? kWorkScr32 : kWorkScr64, 1);
     if (use32) {
-      inv32 = F3{__builtin_amdgcn_rcpf((float)dl.x), __builtin_amdgcn_rcpf((float)dl.y),
-                 __builtin_amdgcn_rcpf((float)dl.z)};
+      inv32 = F3{inv_dir32((float)dl.x), inv_dir32((float)dl.y), inv_dir32((float)dl.z)};
       pin32 = F3{-p32.x * inv32.x, -p32.y * inv32.y, -p32.z * inv32.z};
       bound32 = (float)bound;
       bound32 = fmaf(4.0f * kU32, bound32, bound32);
@@ -226,23 +235,22 @@ __device__ __forceinline__ void daughters_culled(const DevGeom& G, int lv, int o
   }
   V3 inv{}, pin{};
   if (!use32) {
-    inv = V3{rcp_fast(dl.x), rcp_fast(dl.y), rcp_fast(dl.z)};
+    inv = V3{inv_dir64(dl.x), inv_dir64(dl.y), inv_dir64(dl.z)};
     pin = V3{-pl.x * inv.x, -pl.y * inv.y, -pl.z * inv.z};
   }
   const int grp = G.lv_grp[lv];
   for (int c0 = 0; c0 < cnt; c0 += 64) {
     const int m = min(64, cnt - c0);
-    uint64_t cand, any;
+    uint64_t cand;
     if (use32) {
       cand = box_screen(
           c0, m, grp, [&](int k) { return box_hit32(G.dau_box32 + 8 * (size_t)(off + k), inv32, pin32, bound32); },
-          [&](int gi) { return box_hit32(G.grp_box32 + 8 * (size_t)gi, inv32, pin32, bound32); }, any, w);
+          [&](int gi) { return box_hit32(G.grp_box32 + 8 * (size_t)gi, inv32, pin32, bound32); }, w);
     } else {
       cand = box_screen(
           c0, m, grp, [&](int k) { return box_hit64(G.dau_box + 6 * (size_t)(off + k), inv, pin, bound); },
-          [&](int gi) { return box_hit64(G.grp_box + 6 * (size_t)gi, inv, pin, bound); }, any, w);
+          [&](int gi) { return box_hit64(G.grp_box + 6 * (size_t)gi, inv, pin, bound); }, w);
     }
-    (void)any;
     while (cand) {
       const int k = __builtin_ctzll(cand);
       cand &= cand - 1;

@@ -382,6 +382,36 @@ def ring_description():
     return lvs
 
 
+def grid_description():
+    """A world cube holding a box that holds a 5 x 5 grid of boxes in the xy
+    plane, centred on the z axis (no phi index: the middle one surrounds the
+    axis), so the culled loop with group boxes runs."""
+    lvs = [LV(box(200.0, 200.0, 200.0), [], "world"), LV(box(120.0, 120.0, 60.0), [], "holder"),
+           LV(box(12.0, 9.0, 40.0), [], "cell")]
+    lvs[0].placements.append((1, np.eye(3), np.zeros(3)))
+    for i in range(5):
+        for j in range(5):
+            lvs[1].placements.append((2, rot_z(0.2 * (i - j)), np.array([40.0 * (i - 2), 40.0 * (j - 2), 4.0 * (i - j)])))
+    return lvs
+
+
+def bundle_description():
+    """A world cube holding a box that holds 12 tilted tubes in two planes of
+    3 x 2, two of them on the z axis (no phi index: the culled loop runs over
+    tube daughters)."""
+    lvs = [LV(box(200.0, 200.0, 200.0), [], "world"), LV(box(120.0, 120.0, 90.0), [], "holder"),
+           LV(tubs(4.0, 14.0, 30.0), [], "pipe")]
+    lvs[0].placements.append((1, np.eye(3), np.zeros(3)))
+    k = 0
+    for z in (-45.0, 45.0):
+        for x in (-70.0, 0.0, 70.0):
+            for y in (-75.0, 0.0):
+                axis = (math.cos(1.3 * k), math.sin(1.3 * k), 0.4)
+                lvs[1].placements.append((2, _rot(axis, 0.3 + 0.02 * k), np.array([x, y, z])))
+                k += 1
+    return lvs
+
+
 def uniform_world_tracks(half, n: int, seed: int, centre=(0.0, 0.0, 0.0)) -> Tracks:
     """Starts uniform in the box centre +- half (mm), isotropic directions; one
     track in eight is parallel to the z axis."""
