@@ -437,11 +437,19 @@ __global__ void __launch_bounds__(1024) k_bt_scatter(const int* __restrict__ src
 }
 
 // ---------------------------------------------------------------- step
+// Register budget per variant: the navigation step fits 128 VGPRs (4 waves per
+// SIMD) without spilling and runs fastest there; the physics-limited step
+// (process lengths, generator state, distance still to go) spills 80 bytes per
+// lane at 128 and runs faster with 168 VGPRs at 3 waves.
 #ifndef GV_STEP_WAVES_PER_EU
 #define GV_STEP_WAVES_PER_EU 4
 #endif
+#ifndef GV_PHYS_STEP_WAVES_PER_EU
+#define GV_PHYS_STEP_WAVES_PER_EU 3
+#endif
 template <bool F32, bool PHYS, bool B>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GV_STEP_WAVES_PER_EU))) k_bt_step(DevGeom G, int k, int max_steps, int cb, const int* __restrict__ idx,
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(PHYS ? GV_PHYS_STEP_WAVES_PER_EU : GV_STEP_WAVES_PER_EU))) k_bt_step(DevGeom G, int k, int max_steps, int cb, const int* __restrict__ idx,
                                                   TRec* __restrict__ rec, const int* __restrict__ cnt_cur,
                                                   int* __restrict__ nxt_lv, uint32_t* __restrict__ nxt_pos,
                                                   int* __restrict__ cnt_next, TCtl C,
