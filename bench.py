@@ -22,8 +22,9 @@ if ROOT not in sys.path:
 
 
 def cpu_baseline(blob, tracks, target_s=12.0, max_s=30.0):
-    """The CPU oracle on a bounded sample of the same workload, on this host's
-    cores; returns track-steps/s over the sample."""
+    """The CPU oracle on a bounded sample of the same workload (the first tracks,
+    in chunks, until about target_s seconds of work), on this host's cores.
+    Returns (the baseline record, the oracle's outputs for the sample)."""
     import numpy as np
 
     import oracle as O
@@ -34,11 +35,13 @@ def cpu_baseline(blob, tracks, target_s=12.0, max_s=30.0):
     spent = 0.0
     chunk = 8192
     start = 0
+    parts = []
     while spent < target_s and start < tracks.n:
         idx = np.arange(start, min(start + chunk, tracks.n))
         t0 = time.perf_counter()
         r = og.transport(tracks.take(idx), threads=threads)
         spent += time.perf_counter() - t0
+        parts.append(r)
         done_tracks += idx.size
         done_steps += int(r["nsteps"].sum())
         start += idx.size
@@ -47,14 +50,98 @@ def cpu_baseline(blob, tracks, target_s=12.0, max_s=30.0):
         if spent > max_s:
             break
     og.close()
-    return {"value": done_steps / spent, "unit": "track-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {done_tracks} of the 2^20 tracks ({done_steps} track-steps, {spent:.1f} s)"}
+    ref = {k: np.concatenate([r[k] for r in parts]) for k in parts[0]}
+    return ({"value": done_steps / spent, "unit": "track-steps/s", "cores": threads, "kind": "oracle",
+             "sample": f"first {done_tracks} of the {tracks.n} tracks ({done_steps} track-steps, {spent:.1f} s)"},
+            ref)
 
 
-# Algorithmic HBM bytes per track of the solid-level queries: inputs read
-# (3 or 6 doubles) and outputs written (int8 code, doubles).
-SOLID_BYTES = {"inside": 24 + 1, "safety": 24 + 8, "dist_in": 48 + 8, "dist_out": 48 + 8, "fused": 48 + 25}
-HBM_PEAK_GBS = 8000.0
+# Navigation steps: both codes advance the global point p += s d in FP64; after
+# k steps the points differ by up to about k ulp(|p|) (ulp(2048 mm) = 4.5e-13
+# mm, k <= 84 here), and a step measured from a shifted point shifts by as much
+# over the cosine of the hit angle.  Same bar as the navigation parity tests.
+STEP_REL, STEP_ABS = 1e-12, 1e-10
+
+
+def oracle_parity(ref, out):
+    """The GPU transport's outputs against the oracle's on the oracle's sample
+    (its first m tracks): volume sequences, step counts and flags bit-exact for
+    tracks the oracle does not flag as ill-conditioned (those are counted and
+    the first listed), step lengths within STEP_REL relative + STEP_ABS."""
+    import numpy as np
+
+    import oracle as O
+
+    m = ref["nsteps"].shape[0]
+    ns = out["nsteps"][:m].cpu().numpy()
+    fl = out["flags"][:m].cpu().numpy().astype(np.uint32)
+    pv = out["pv"][:m].cpu().numpy()
+    st = out["step"][:m].cpu().numpy()
+    ok = (ref["diag"] & O.D_ILL) == 0
+    rn = ref["nsteps"]
+    bad_len = (ns != rn) | (fl != ref["flags"])
+    k = np.arange(pv.shape[1])[None, :]
+    seq_bad = ((pv != ref["pv"]) & (k <= rn[:, None])).any(axis=1)
+    mk = k[:, :-1] < rn[:, None]
+    with np.errstate(invalid="ignore"):
+        err = np.where(mk, np.abs(st - ref["step"]), 0.0)
+        tol = STEP_REL * np.maximum(1.0, np.abs(np.where(mk, ref["step"], 0.0))) + STEP_ABS
+    step_bad = (mk & ~(err <= tol)).any(axis=1)
+    bad = bad_len | seq_bad | step_bad
+    flagged = np.nonzero(~ok)[0]
+    return {"tracks": int(m), "track_steps": int(rn.sum()), "mismatched_tracks": int((bad & ok).sum()),
+            "sequence_mismatches": int(((bad_len | seq_bad) & ok).sum()),
+            "flagged_tracks": int(flagged.size), "flagged_first": [int(i) for i in flagged[:20]],
+            "flagged_that_differ": int((bad & ~ok).sum()),
+            "max_step_err_mm": float(err[ok].max()) if ok.any() else None,
+            "bar": f"sequences, counts, flags exact; steps |d| <= {STEP_REL} max(1 mm, |ref|) + {STEP_ABS} mm"}
+
+
+def roof_probes():
+    """What this GPU reaches on the two roofs, measured in this process: a
+    stream triad c = a + s b and a copy over 3 x 512 MiB arrays (beyond the
+    256 MB last-level cache), and eight independent FP64 FMA chains per lane on
+    2^19 lanes.  Medians of 5 timed calls after a warm-up."""
+    import torch
+
+    import paper_1512_06637_amd as G
+
+    n = 1 << 26  # 512 MiB per array
+    a = torch.rand(n, dtype=torch.float64, device="cuda")
+    b = torch.rand(n, dtype=torch.float64, device="cuda")
+    c = torch.empty_like(a)
+
+    def med(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+        ts.sort()
+        return ts[len(ts) // 2]
+
+    t_triad = med(lambda: G.probe_stream(a, b, c, 0.5))
+    t_copy = med(lambda: G.probe_stream(a, None, c))
+    del a, b, c
+    lanes, iters = 1 << 19, 8192
+    out = torch.empty(lanes, dtype=torch.float64, device="cuda")
+    t_fma = med(lambda: G.probe_fma64(out, iters))
+    fmas = 8.0 * iters * lanes
+    return {"hbm_triad_GBs": 24.0 * n / t_triad / 1e9, "hbm_copy_GBs": 16.0 * n / t_copy / 1e9,
+            "fp64_fma_Tlane_ops": fmas / t_fma / 1e12, "fp64_TFLOPs": 2 * fmas / t_fma / 1e12,
+            "nominal": {"hbm_GBs": R_PEAK_HBM_GBS, "fp64_Tlane_ops": R_PEAK_FP64_TOPS},
+            "method": "triad/copy over 3 x 512 MiB float64 arrays; 8 FMA chains x 8192 on 2^19 lanes; "
+                      "median of 5 after warm-up"}
+
+
+R_PEAK_HBM_GBS = 8000.0
+R_PEAK_FP64_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 
 def kernel_sources_sha256():
@@ -121,6 +208,7 @@ def solids_leg(copies=8, replays=10):
     import torch
 
     import paper_1512_06637_amd as G
+    from paper_1512_06637_amd import roofline as R
     from paper_1512_06637_amd import workloads as W
 
     names = W.CONFIG2_SOLIDS
@@ -146,9 +234,9 @@ def solids_leg(copies=8, replays=10):
         r = {}
         for q, f in calls.items():
             ms = graph_ms(f, copies, replays)
-            gbs = n * SOLID_BYTES[q] / (ms * 1e-3) / 1e9
-            r[q] = {"us_per_call": ms * 1e3, "tracks_per_s": n / (ms * 1e-3), "GB_s": gbs,
-                    "frac_hbm": gbs / HBM_PEAK_GBS}
+            gbs = n * R.SOLID_BYTES[q] / (ms * 1e-3) / 1e9
+            r[q] = {"us_per_call": ms * 1e3, "tracks_per_s": n / (ms * 1e-3), "GB_s": gbs}
+            r[q].update(R.solid_roofline(name, q, n, ms * 1e3))
         r["separate_vs_fused_time"] = sum(r[q]["us_per_call"] for q in ("inside", "safety", "dist_in", "dist_out")) \
             / r["fused"]["us_per_call"]
         res[name] = r
@@ -278,6 +366,21 @@ def cpu_baseline_solids(protocol, max_s=1.0):
             "solids": full, "protocol": proto}
 
 
+def _time_calls(fn, calls):
+    """Device time per call of `fn` over `calls` calls, HIP events on the current
+    stream (the one the library launches on)."""
+    import torch
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(calls):
+        fn()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / calls
+
+
 def phys_leg(g, a, args, max_steps=256):
     """Physics-limited transport of the same tracks (synthetic materials: mean
     free paths 60-400 mm in the modules, 5e3-1e5 mm in the layers, 2e5-1e6 mm
@@ -296,21 +399,15 @@ def phys_leg(g, a, args, max_steps=256):
            "flags": torch.empty(n, dtype=torch.int32, device="cuda")}
     res = {}
     for short in (True, False):
+        run = lambda: g.transport_phys(*a, W.PHYS_SEED, max_steps=max_steps, out=out, shortcut=short)  # noqa: E731
         for _ in range(args.warmup):
-            g.transport_phys(*a, W.PHYS_SEED, max_steps=max_steps, out=out, shortcut=short)
+            run()
         torch.cuda.synchronize()
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        ev0.record()
-        for _ in range(args.steps):
-            g.transport_phys(*a, W.PHYS_SEED, max_steps=max_steps, out=out, shortcut=short)
-        ev1.record()
-        torch.cuda.synchronize()
-        ms = ev0.elapsed_time(ev1) / args.steps
-        g.profile(True)
-        g.transport_phys(*a, W.PHYS_SEED, max_steps=max_steps, out=out, shortcut=short)
+        ms = _time_calls(run, args.steps)
+        g.profile(work=True)
+        run()
         _, _, work = g.profile_read()
-        g.profile(False)
+        g.profile()
         total = int(out["nsteps"].sum())
         res["shortcut" if short else "no_shortcut"] = {
             "ms_per_step": ms, "track_steps_per_s": total / (ms * 1e-3), "track_steps": total,
@@ -318,32 +415,31 @@ def phys_leg(g, a, args, max_steps=256):
     return res
 
 
-def fp32_leg(g, a, ref, max_steps, args, ms64):
+def fp32_leg(g, a, ref, max_steps, args, ms64, oracle_ref=None):
     """The same workload with precision FP32_REFINE (FP32 daughter screens, FP64
-    distances): time per call, whether every output equals the FP64 run's, and
-    the share of culled track-steps whose screens ran in FP32."""
+    distances): time per call, whether every output equals the FP64 run's, the
+    oracle parity of its outputs, and the share of culled track-steps whose
+    screens ran in FP32."""
     import torch
 
     import paper_1512_06637_amd as G
 
     n = ref["nsteps"].shape[0]
     out = {k: torch.empty_like(v) for k, v in ref.items()}
+    run = lambda: g.transport(*a, max_steps=max_steps, out=out, precision=G.FP32_REFINE)  # noqa: E731
     for _ in range(args.warmup):
-        g.transport(*a, max_steps=max_steps, out=out, precision=G.FP32_REFINE)
+        run()
     torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(args.steps):
-        g.transport(*a, max_steps=max_steps, out=out, precision=G.FP32_REFINE)
-    ev1.record(stream)
+    ms = _time_calls(run, args.steps)
+    g.profile(events=True)
+    run()
+    step_ms, _, _ = g.profile_read()
+    g.profile(work=True)
+    run()
+    _, _, work = g.profile_read()
+    g.profile()
+    run()
     torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / args.steps
-    g.profile(True)
-    g.transport(*a, max_steps=max_steps, out=out, precision=G.FP32_REFINE)
-    step_ms, _, work = g.profile_read()
-    g.profile(False)
     ns = ref["nsteps"]
     k = torch.arange(max_steps, device=ns.device)[None, :]
     m = k < ns[:, None].long()
@@ -352,10 +448,30 @@ def fp32_leg(g, a, ref, max_steps, args, ms64):
             and torch.equal(ref["pv"][mp], out["pv"][mp])
             and torch.equal(ref["step"][m].view(torch.int64), out["step"][m].view(torch.int64)))
     total = int(ns.sum())
-    return {"ms_per_step": ms, "value": total / (ms * 1e-3), "speedup_vs_fp64": ms64 / ms,
-            "kernel_ms_per_transport": step_ms, "identical_to_fp64": bool(same),
-            "fp32_screened_frac": work[20] / max(1, work[20] + work[21]),
-            "daughter_box_tests": work[1], "dist_in_box_tube": work[8:10]}
+    r = {"ms_per_step": ms, "value": total / (ms * 1e-3), "speedup_vs_fp64": ms64 / ms,
+         "kernel_ms_per_transport": step_ms, "identical_to_fp64": bool(same),
+         "fp32_screened_frac": work[20] / max(1, work[20] + work[21]),
+         "daughter_box_tests": work[1], "dist_in_box_tube": work[8:10]}
+    if oracle_ref is not None:
+        r["oracle_parity"] = oracle_parity(oracle_ref, out)
+    return r
+
+
+def serving_leg(baskets=3000):
+    """The serving engine (continuous batching: slots 64, HBM budget 256 MiB,
+    2 streams) and the same engine serving one basket at a time (1 slot, 1
+    stream: the serial per-basket form), FP64 and FP32_REFINE, Poisson arrivals
+    at 0.5 / 0.8 / 0.95 of the batching engine's saturation rate; `baskets`
+    baskets per point."""
+    import paper_1512_06637_amd as G
+    from paper_1512_06637_amd import serve as S
+    from paper_1512_06637_amd import workloads as W
+
+    g = G.Geometry(W.detector_blob())
+    try:
+        return S.run(g, n_baskets=baskets)
+    finally:
+        g.close()
 
 
 def main():
@@ -369,6 +485,8 @@ def main():
     ap.add_argument("--no-solids", action="store_true", help="skip the solid-level legs")
     ap.add_argument("--no-phys", action="store_true", help="skip the physics-limited transport leg")
     ap.add_argument("--no-composites", action="store_true", help="skip the composite-solid legs")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-probes", action="store_true", help="skip the HBM and FP64 roof probes")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 256 MiB device to device (a kernel of known traffic for counter scaling)")
     args = ap.parse_args()
@@ -402,29 +520,29 @@ def main():
         "nsteps": torch.empty(n, dtype=torch.int32, device="cuda"),
         "flags": torch.empty(n, dtype=torch.int32, device="cuda"),
     }
+    run = lambda: g.transport(*a, max_steps=max_steps, out=out)  # noqa: E731
     for _ in range(args.warmup):
-        g.transport(*a, max_steps=max_steps, out=out)
+        run()
     torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        g.transport(*a, max_steps=max_steps, out=out)
-    ev1.record(stream)
-    torch.cuda.synchronize()
+    ms = _time_calls(run, args.steps)
     wall = time.perf_counter() - t0
-    ms = ev0.elapsed_time(ev1) / args.steps
 
-    # the per-step kernel alone: HIP events around each of its launches (on the
-    # stream the library launches on), then the library's work counters
-    g.profile(True)
+    # the per-step kernel alone: HIP events around each of its launches, on the
+    # stream the library launches on, over the same number of calls
+    g.profile(events=True)
     for _ in range(args.steps):
-        g.transport(*a, max_steps=max_steps, out=out)
-    step_ms_total, launches, work = g.profile_read()
-    g.profile(False)
+        run()
+    step_ms_total, launches, _ = g.profile_read()
+    # operation counts: one call of the counting instance of the step kernel
+    g.profile(work=True)
+    run()
+    _, _, work = g.profile_read()
+    g.profile()
+    run()  # outputs of the production kernels for the parity check below
+    torch.cuda.synchronize()
     step_ms = step_ms_total / args.steps  # step-kernel time per transport
+    launches_per = launches / args.steps
     launch_ms = step_ms_total / max(1, launches)
 
     ns = out["nsteps"].cpu().numpy()
@@ -432,14 +550,42 @@ def main():
     flags = out["flags"].cpu().numpy()
     total_steps = int(ns.sum())
     world, layer, module = R.detector_step_classes(pv, ns)
+    del pv
     ops_plain = R.detector_ops(world, layer, module)
     ops = R.detector_ops_culled(world, layer, module, work)
-    achieved = ops / (step_ms * 1e-3)
-    # the step kernel's bound: its arithmetic intensity against the machine balance
-    bytes_launch = total_steps / max(1.0, launches / args.steps) * R.STEP_BYTES
-    intensity = ops / (total_steps * R.STEP_BYTES)
-    bound_hbm = intensity < R.PEAK_FP64_OPS / R.PEAK_HBM
-    achieved_gbs = bytes_launch / (launch_ms * 1e-3) / 1e9
+    alg_bytes = R.transport_bytes(n, total_steps)
+    design_bytes = total_steps * R.STEP_DESIGN_BYTES
+    intensity = ops / alg_bytes
+    balance = R.PEAK_FP64_OPS / R.PEAK_HBM
+    achieved = ops / (step_ms * 1e-3)  # = ops per launch / average launch duration
+    traffic = measured_traffic()
+    roofs = None if args.no_probes else roof_probes()
+    roofline = {
+        "bound": "alu" if intensity > balance else "hbm",
+        "kernel": "k_bt_step",
+        "achieved": achieved / 1e12,
+        "peak": R.PEAK_FP64_OPS / 1e12,
+        "unit": "T FP64 lane-ops/s (an FMA counts 1; peak = 256 CU x 64 lanes x 2.4 GHz = 78.6 TFLOP/s)",
+        "frac": achieved / R.PEAK_FP64_OPS,
+        "traffic": traffic,
+        "ops_per_transport": ops,
+        "ops_per_launch": ops / launches_per,
+        "launches_per_transport": launches_per,
+        "avg_launch_ms": launch_ms,
+        "kernel_ms_per_transport": step_ms,
+        "algorithmic_bytes_per_transport": alg_bytes,
+        "ops_per_algorithmic_byte": intensity,
+        "machine_balance_ops_per_byte": balance,
+        "frac_measured_fp64_roof": achieved / (roofs["fp64_fma_Tlane_ops"] * 1e12) if roofs else None,
+        "hbm": {"algorithmic_GBs": alg_bytes / (ms * 1e-3) / 1e9,
+                "frac_algorithmic": alg_bytes / (ms * 1e-3) / R.PEAK_HBM,
+                "design_bytes_per_launch": design_bytes / launches_per,
+                "measured_traffic_per_launch": traffic,
+                "measured_traffic_over_algorithmic": (traffic * launches_per / alg_bytes) if traffic else None,
+                "frac_measured_traffic": (traffic / (launch_ms * 1e-3) / R.PEAK_HBM) if traffic else None},
+        "accounting": "ops = the culled navigator's own work from its operation counters x the per-operation "
+                      "table of roofline.py; bytes = inputs once + outputs once (transport_bytes)",
+    }
     res = {
         "metric": "track-steps/s",
         "value": total_steps / (ms * 1e-3),
@@ -456,17 +602,9 @@ def main():
         "config": {"workload": "layered-detector navigation FP64: 2^20 origin tracks to world exit, 1301 PVs",
                    "tracks": n, "track_steps": total_steps, "max_steps": max_steps,
                    "steps_world_layer_module": [world, layer, module]},
-        "roofline": ({"bound": "hbm", "kernel": "k_bt_step", "achieved": achieved_gbs, "peak": R.PEAK_HBM / 1e9,
-                      "unit": "GB/s", "frac": achieved_gbs * 1e9 / R.PEAK_HBM} if bound_hbm else
-                     {"bound": "alu", "kernel": "k_bt_step", "achieved": achieved / 1e12,
-                      "peak": R.PEAK_FP64_OPS / 1e12, "unit": "TOP/s (FP64 lane-ops)",
-                      "frac": achieved / R.PEAK_FP64_OPS}) | {
-                     "traffic": measured_traffic(), "bytes_per_launch": bytes_launch,
-                     "launches_per_transport": launches / args.steps, "avg_launch_ms": launch_ms,
-                     "kernel_ms_per_transport": step_ms,
-                     "alu": {"ops_per_transport": ops, "achieved_TOPs": achieved / 1e12,
-                             "frac": achieved / R.PEAK_FP64_OPS, "ops_per_byte": intensity,
-                             "machine_balance_ops_per_byte": R.PEAK_FP64_OPS / R.PEAK_HBM}},
+        "roofline": roofline,
+        "roofs": roofs,
+        "tuning": g.get_tuning(),
         "work": {"plain_navigator_ops": ops_plain, "culled_ops": ops, "daughter_box_tests": work[1],
                  "bound_checks_box_tube": work[2:4], "dist_in_box_tube": work[8:10], "steps": work[0],
                  "radial_lookups": work[24], "radial_bounds": work[25], "phi_lookups": work[26],
@@ -474,21 +612,26 @@ def main():
         "wall_s": wall,
         "flags_nonzero": int((flags != 0).sum()),
     }
+    oracle_ref = None
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"], oracle_ref = cpu_baseline(blob, tracks)
+        res["oracle_parity"] = oracle_parity(oracle_ref, out)
     if not args.no_fp32:
-        res["fp32_refine"] = fp32_leg(g, a, out, max_steps, args, ms)
+        res["fp32_refine"] = fp32_leg(g, a, out, max_steps, args, ms, oracle_ref)
+    del oracle_ref
     if not args.no_phys:
         res["physics_limited"] = phys_leg(g, a, args)
     g.close()
     del out, a
+    if not args.no_serving:
+        res["serving"] = serving_leg()
     if not args.no_solids:
         res["solids"] = solids_leg()
         res["protocol"] = protocol_leg()
+        if not args.no_cpu_baseline:
+            res["cpu_baseline_solids"] = cpu_baseline_solids(res["protocol"])
     if not args.no_composites:
         res["composites"] = composites_leg(args)
-    if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(blob, tracks)
-        if not args.no_solids:
-            res["cpu_baseline_solids"] = cpu_baseline_solids(res["protocol"])
     print(json.dumps(res), flush=True)
 
 

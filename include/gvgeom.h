@@ -50,10 +50,10 @@ enum { GV_SAFETY_AUTO = 0, GV_SAFETY_IN = 1, GV_SAFETY_OUT = 2 };
  * daughters of box- and tube-daughter volumes in FP32 (bounding-box slab test
  * and a SafetyToIn lower bound, on FP32 copies of the tables, with rounding
  * margins that keep both conservative) and computes every surviving distance
- * in FP64 (Sec. III.C: the single-precision variant of the vectorised
- * navigator, here as a screen only).  Its outputs equal those of GV_FP64 bit
- * for bit; a wavefront whose points lie outside the range the FP32 margins
- * cover falls back to the FP64 screens. */
+ * in FP64, so its outputs equal those of GV_FP64 bit for bit; a wavefront whose
+ * points lie outside the range the FP32 margins cover falls back to the FP64
+ * screens.  (The paper, Sec. III.C, describes vectorised solid and navigation
+ * code; it names no precision.  The mixed form is this library's own.) */
 enum { GV_FP64 = 0, GV_FP32_REFINE = 1 };
 /* per-track transport flags */
 #define GV_FLAG_OVERFLOW 1u    /* max_steps reached before leaving the world */
@@ -169,7 +169,13 @@ int basket_nav_inside(gv_geom* g, int64_t n, const double* x, const double* y, c
  * precision GV_FP64 or GV_FP32_REFINE (same outputs).
  * 1 <= max_steps <= 4096.  The library keeps a device workspace inside `g`,
  * grown on demand (hipMalloc) and freed by geom_free; concurrent calls on the
- * same `g` from several streams are not allowed (GV_ESTATE is not detected). */
+ * same `g` from several streams are not allowed (GV_ESTATE is not detected).
+ * The call only enqueues: for 8,192 or more tracks it enqueues every step up
+ * to max_steps (steps past the longest track find an empty list and cost one
+ * dispatch each), so it never waits for the device and may be captured into
+ * a HIP graph.  Under stream capture nothing is allocated: GV_ESTATE unless
+ * an earlier call outside the capture has sized the workspace for at least n
+ * tracks (and GV_ESTATE while profiling events are on). */
 int nav_transport(gv_geom* g, int64_t n, const double* x, const double* y, const double* z,
                   const double* dx, const double* dy, const double* dz, const int32_t* start_pv,
                   int32_t max_steps, int32_t* out_pv, double* out_step, int32_t* out_nsteps,
@@ -180,7 +186,7 @@ int nav_transport(gv_geom* g, int64_t n, const double* x, const double* y, const
  * density[m] and, for each of n_proc (1..16) processes, a cross section
  * sigma[m][p] (host arrays, row-major), and the material of every logical
  * volume, lv_material[n_lv].  The mean free path of process p in material m is
- * 1 / (density[m] sigma[m][p]) (Sec. II, Eq. (1)); units such that it comes out
+ * 1 / (density[m] sigma[m][p]) (Sec. III, Eq. (1)); units such that it comes out
  * in mm.  Copied to the device; replaces earlier tables.  Errors: GV_EINVAL for
  * negative or non-finite values or a material index out of range. */
 int geom_set_materials(gv_geom* g, int32_t n_mat, int32_t n_proc, const double* density, const double* sigma,
@@ -188,7 +194,7 @@ int geom_set_materials(gv_geom* g, int32_t n_mat, int32_t n_proc, const double* 
 
 #define GV_PHYS_SAFETY_SHORTCUT 1 /* nav_transport_phys option */
 
-/* Transport with physics-limited steps (Sec. II: the process with the shortest
+/* Transport with physics-limited steps (Sec. III.A with Eqs. (1)-(3): the process with the shortest
  * sampled interaction length acts unless the border is nearer; the lengths are
  * drawn again in every volume).  At step k of track i every process p draws
  * s_p = -ln(u) / (density sigma_p) of the current volume's material, u in
@@ -209,12 +215,16 @@ int nav_transport_phys(gv_geom* g, int64_t n, const double* x, const double* y, 
 
 /* ------------------------------------------------------------ measurement */
 
-/* Kernel timing for measurement.  While enabled, nav_transport records a pair
- * of HIP events on the caller's stream around every launch of its per-step
- * kernel.  gv_profile_read waits for those events and returns the summed
+/* Measurement.  flags GV_PROF_EVENTS: nav_transport records a pair of HIP
+ * events on the caller's stream around every launch of its per-step kernel
+ * (the production kernel, so the times are those of unprofiled calls).
+ * GV_PROF_WORK: basket transports run the per-step kernel instance that keeps
+ * operation counters (a ballot and an LDS atomic per counted event, so slower;
+ * geometries without composites only).  0 turns both off.
+ * gv_profile_read waits for the events and returns the summed
  * kernel milliseconds and the number of launches since the last read (then
  * forgets them), and, if `work` is not NULL, the operation counts of the last
- * basket transport (host array of 28 uint64: [0] steps taken, [1] daughter
+ * basket transport run with GV_PROF_WORK (host array of 28 uint64: [0] steps taken, [1] daughter
  * bounding-box tests, [2+t] daughter lower-bound checks, [8+t] daughter
  * DistanceToIn evaluations in culled loops (and radial walks), [14+t]
  * DistanceToIn evaluations in plain loops, t = daughter solid type 0..5
@@ -224,8 +234,51 @@ int nav_transport_phys(gv_geom* g, int64_t n, const double* x, const double* y, 
  * daughters are walked in radial order, [25] crossing-parameter bounds of
  * those walks, [26] steps whose daughters came from phi sectors, [27] sector
  * masks read).  Reading synchronises the device. */
-int gv_profile(gv_geom* g, int enable);
+#define GV_PROF_EVENTS 1
+#define GV_PROF_WORK 2
+int gv_profile(gv_geom* g, int flags);
 int gv_profile_read(gv_geom* g, double* step_ms, int64_t* step_launches, uint64_t* work);
+
+/* Roof probes (measurement only; device pointers, enqueued on `stream`).
+ * gv_probe_stream: c[i] = a[i] + s b[i] for i < n (n even, arrays 16-byte
+ * aligned), 24 n bytes of HBM traffic; with b NULL the copy c[i] = a[i],
+ * 16 n bytes.  gv_probe_fma64: n_lanes lanes (a positive multiple of 256)
+ * each run eight independent chains of `iters` FP64 fused multiply-adds
+ * (8 iters n_lanes FMAs = 16 iters n_lanes flops) and store one double to
+ * out[lane]. */
+int gv_probe_stream(const double* a, const double* b, double* c, double s, int64_t n, void* stream);
+int gv_probe_fma64(double* out, int64_t n_lanes, int32_t iters, void* stream);
+
+/* ---------------------------------------------------------- launch shapes */
+/* How the library's kernels are launched on this geometry.  These choose
+ * workgroup counts and sizes, the coarse direction cells of the basket
+ * regrouping and the register budget of the per-step kernel; none of them
+ * changes any result (every track's arithmetic is the same), only speed.  An
+ * autotuner measures them per device architecture (the Python package's
+ * tune module) and the binding applies the stored choice at load.
+ * Fields (0 = the default; cell_bits -1 = the default):
+ *   step_grid     workgroups of the per-step basket kernel, 1..1024
+ *                 (default one per four tiles of 64 tracks, at most 1024);
+ *   scatter_grid  workgroups of the regrouping kernels, 1..1024
+ *                 (default one per 4,096 tracks, at most 256);
+ *   cell_bits     0, 2 or 4: 1, 2 x 2 or 4 x 4 direction cells per logical
+ *                 volume in the regrouping key (default 2; ignored when
+ *                 volumes x cells would exceed 4,096);
+ *   solid_block   threads per workgroup of the one-lane-per-track kernels
+ *                 (solid-level queries, basket_step/_locate/_nav_*, small
+ *                 transports), a multiple of 64 in 64..1024 (default 256);
+ *   solid_grid    at most this many workgroups for those kernels (each lane
+ *                 then loops over several tracks), >= 1 (default: one lane
+ *                 per track);
+ *   step_waves    3 or 4: waves per SIMD the navigation step kernel is built
+ *                 for (default 4).
+ * A change of cell_bits re-sizes the transport workspace at the next
+ * transport.  GV_EINVAL for a field out of range (nothing changed). */
+typedef struct {
+  int32_t step_grid, scatter_grid, cell_bits, solid_block, solid_grid, step_waves;
+} gv_tuning;
+int gv_set_tuning(gv_geom* g, const gv_tuning* t);
+int gv_get_tuning(const gv_geom* g, gv_tuning* t);
 
 /* --------------------------------------------------------------- serving */
 /* A serving engine answers baskets of navigation queries that arrive over

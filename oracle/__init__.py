@@ -24,7 +24,8 @@ _LIB = None
 OUTSIDE, SURFACE, INSIDE = 0, 1, 2
 F_OVERFLOW, F_STUCK, F_LOCATE_FAIL = 1, 2, 4
 D_NEAR_TIE, D_GRAZE, D_ZERO_STEP, D_BAND_EDGE, D_NO_EXIT = 16, 32, 64, 128, 256
-D_ILL = D_NEAR_TIE | D_GRAZE | D_ZERO_STEP | D_BAND_EDGE | D_NO_EXIT
+D_COND = 512  # solid-level hit whose FP64 conditioning exceeds the 1e-12 bar (or_hit_cond)
+D_ILL = D_NEAR_TIE | D_GRAZE | D_ZERO_STEP | D_BAND_EDGE | D_NO_EXIT | D_COND
 
 _P = C.c_void_p
 _I64 = C.c_int64

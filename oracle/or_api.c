@@ -74,6 +74,7 @@ int orc_solid_distance(int type, const double* params, int np, int dir, int64_t 
     double p[3] = {x[i], y[i], z[i]}, d[3] = {dx[i], dy[i], dz[i]};
     unsigned dg = 0;
     out[i] = dir == 0 ? or_dist_in(&s, p, d, &dg) : or_dist_out(&s, p, d, &dg);
+    if (or_hit_cond(&s, p, d, out[i])) dg |= OR_D_COND;
     if (diag) diag[i] = dg;
   }
   or_solid_release(&s);

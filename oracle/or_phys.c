@@ -3,7 +3,7 @@
  *
  * Physics-limited transport.  The step of a particle is set by the mean free
  * path of each process, lambda_i = 1 / (n sigma_i) with n the number density of
- * the medium and sigma_i the process's cross section (Sec. II, Eq. (1)); the
+ * the medium and sigma_i the process's cross section (Sec. III, Eq. (1)); the
  * total rate is the sum of the process rates (Eqs. (2), (3)).  Following the
  * Physics subsection, every process draws an interaction length by Monte Carlo,
  * the shortest one is proposed, and when it is longer than the distance to the

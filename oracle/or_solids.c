@@ -558,3 +558,29 @@ double or_dist_out(const or_solid* s, const double p[3], const double d[3], unsi
   double ts = INFINITY;
   return or_dist_out_ex(s, p, d, diag, &ts);
 }
+
+/* The size of a correct FP64 hit distance's rounding, against the bar it is
+ * held to.  The inputs and the quadric coefficients carry a few units of
+ * roundoff eps of the coordinate scale L; a hit at angle theta to the surface
+ * normal moves by that over |cos theta|.  16 covers the few ulp of each
+ * coefficient; the hit is flagged when this bound exceeds the bar. */
+int or_hit_cond(const or_solid* s, const double p[3], const double d[3], double t) {
+  if (!(t > 0.0) || !isfinite(t)) return 0;
+  const double eps = 0x1p-52;
+  double q[3] = {p[0] + t * d[0], p[1] + t * d[1], p[2] + t * d[2]};
+  const double h = 1e-6 * dmax(1.0, infnorm(q));
+  double g[3];
+  for (int k = 0; k < 3; ++k) {
+    double a[3] = {q[0], q[1], q[2]}, b[3] = {q[0], q[1], q[2]};
+    a[k] += h;
+    b[k] -= h;
+    g[k] = (or_signed(s, a) - or_signed(s, b)) / (2.0 * h);
+  }
+  const double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+  const double c = gn > 0.0 ? fabs(g[0] * d[0] + g[1] * d[1] + g[2] * d[2]) / gn : 0.0;
+  const double pn2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+  const double qn2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
+  const double L = (pn2 + qn2) / dmax(1.0, sqrt(qn2));
+  const double bar = 1e-12 * dmax(t, 1.0);
+  return 16.0 * eps * L > bar * c;  /* 16 eps L / |cos theta| > bar, without dividing by 0 */
+}

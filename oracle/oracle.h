@@ -55,6 +55,11 @@ enum { OR_SAFETY_AUTO = 0, OR_SAFETY_IN = 1, OR_SAFETY_OUT = 2 };
 #define OR_D_ZERO_STEP 64u
 #define OR_D_BAND_EDGE 128u
 #define OR_D_NO_EXIT 256u
+/* A solid-level distance whose hit no FP64 code can fix to the 1e-12 relative
+ * bar: its conditioning bound 16 eps L / |cos theta| exceeds
+ * 1e-12 max(|t|, 1 mm), theta the angle between the ray and the normal of the
+ * surface hit (or_hit_cond). */
+#define OR_D_COND 512u
 
 typedef struct or_solid {
   int type;
@@ -106,6 +111,13 @@ double or_dist_in_ex(const or_solid* s, const double p[3], const double d[3], un
 double or_dist_out_ex(const or_solid* s, const double p[3], const double d[3], unsigned* diag,
                       double* t_suspect);
 int or_roots(const or_solid* s, const double p[3], const double d[3], double* roots);
+/* Conditioning of a finite hit at t > 0 along p + t d: returns 1 when
+ * 16 eps L / |cos theta| > 1e-12 max(t, 1 mm), with eps = 2^-52,
+ * L = (|p|^2 + |q|^2) / max(1 mm, |q|) (the scale of the coordinates and of the
+ * quadric's constant term |p|^2 - R^2), q = p + t d, and cos theta = n.d / |n|
+ * with n the central-difference gradient of the signed term at q
+ * (h = 1e-6 max(1 mm, |q|inf)). */
+int or_hit_cond(const or_solid* s, const double p[3], const double d[3], double t);
 
 /* ---------------------------------------------------------------- geometry */
 typedef struct {

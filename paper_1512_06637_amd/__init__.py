@@ -22,6 +22,12 @@ TO_IN, TO_OUT = 0, 1
 SAFETY_AUTO, SAFETY_IN, SAFETY_OUT = 0, 1, 2
 FP64, FP32_REFINE = 0, 1
 WORK_N = 28  # work counters returned by gv_profile_read
+PROF_EVENTS, PROF_WORK = 1, 2
+TUNING_FIELDS = ("step_grid", "scatter_grid", "cell_bits", "solid_block", "solid_grid", "step_waves")
+
+
+class _Tuning(C.Structure):
+    _fields_ = [(f, C.c_int32) for f in TUNING_FIELDS]
 PHYS_SAFETY_SHORTCUT = 1
 FLAG_OVERFLOW, FLAG_STUCK, FLAG_LOCATE_FAIL = 1, 2, 4
 
@@ -43,6 +49,10 @@ _SIGS = {
     "nav_transport": [_P, _I64] + [_P] * 7 + [_I32] + [_P] * 4 + [_I32, _P],
     "gv_profile": [_P, C.c_int],
     "gv_profile_read": [_P, _P, _P, _P],
+    "gv_set_tuning": [_P, _P],
+    "gv_probe_stream": [_P, _P, _P, C.c_double, _I64, _P],
+    "gv_probe_fma64": [_P, _I64, _I32, _P],
+    "gv_get_tuning": [_P, _P],
     "geom_set_materials": [_P, _I32, _I32, _P, _P, _P],
     "nav_transport_phys": [_P, _I64] + [_P] * 7 + [_I32, C.c_uint64] + [_P] * 5 + [_I32, _I32, _P],
     "gv_server_create": [_P, _I32, _I64, _I32, C.POINTER(_P)],
@@ -137,7 +147,9 @@ def _n(*ts):
 class Geometry:
     """A geometry resident on the current GPU (geom_load / geom_free)."""
 
-    def __init__(self, blob: bytes):
+    def __init__(self, blob: bytes, tuned: bool = True):
+        """tuned: apply the launch shapes the autotuner stored for this GPU's
+        architecture (paper_1512_06637_amd/tuned.json), if any."""
         h = C.c_void_p()
         buf = C.create_string_buffer(bytes(blob), len(blob))
         _check("geom_load", lib().geom_load(buf, len(blob), C.byref(h)))
@@ -145,6 +157,27 @@ class Geometry:
         counts = (C.c_int32 * 4)()
         _check("geom_info", lib().geom_info(self._h, counts))
         self.n_lv, self.n_pv, self.max_depth, self.world_lv = list(counts)
+        if tuned:
+            from . import tune
+            choice = tune.stored_choice()
+            if choice:
+                self.set_tuning(**choice)
+
+    def get_tuning(self) -> dict:
+        t = _Tuning()
+        _check("gv_get_tuning", lib().gv_get_tuning(self._h, C.byref(t)))
+        return {f: getattr(t, f) for f in TUNING_FIELDS}
+
+    def set_tuning(self, **fields):
+        """Launch shapes (gvgeom.h gv_tuning); fields not given keep their value.
+        None of them changes a result."""
+        cur = self.get_tuning()
+        for k, v in fields.items():
+            if k not in cur:
+                raise KeyError(f"unknown tuning field {k!r}")
+            cur[k] = int(v)
+        t = _Tuning(*[cur[f] for f in TUNING_FIELDS])
+        _check("gv_set_tuning", lib().gv_set_tuning(self._h, C.byref(t)))
 
     def close(self):
         if getattr(self, "_h", None):
@@ -246,8 +279,12 @@ class Geometry:
             _dev(out, torch.int8, "out"), _stream()))
         return out
 
-    def profile(self, enable=True):
-        _check("gv_profile", lib().gv_profile(self._h, 1 if enable else 0))
+    def profile(self, events=False, work=False):
+        """events: time every per-step kernel launch of basket transports with HIP
+        events (production kernels); work: run the instance that keeps operation
+        counters.  profile() turns both off."""
+        flags = (PROF_EVENTS if events else 0) | (PROF_WORK if work else 0)
+        _check("gv_profile", lib().gv_profile(self._h, flags))
 
     def profile_read(self):
         """(step-kernel ms, launches, work counts: [0] steps, [1] bounding-box tests,
@@ -316,6 +353,23 @@ class Geometry:
             _dev(out["nsteps"], torch.int32, "nsteps", n), _dev(out["flags"], torch.int32, "flags", n), precision,
             _stream()))
         return out
+
+
+# ------------------------------------------------------------ roof probes
+def probe_stream(a, b, c, s=1.0):
+    """c = a + s b (b None: c = a) on device float64 tensors of one even length."""
+    torch = _torch()
+    n = _n(a, b, c)
+    _check("gv_probe_stream", lib().gv_probe_stream(
+        _dev(a, torch.float64, "a"), _opt(b, torch.float64, "b"), _dev(c, torch.float64, "c"), float(s), n,
+        _stream()))
+
+
+def probe_fma64(out, iters):
+    """out: device float64 tensor, one element per lane (multiple of 256)."""
+    torch = _torch()
+    _check("gv_probe_fma64", lib().gv_probe_fma64(_dev(out, torch.float64, "out"), out.numel(), int(iters),
+                                                  _stream()))
 
 
 # ------------------------------------------------------------------ serving

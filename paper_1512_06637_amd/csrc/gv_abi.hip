@@ -16,6 +16,7 @@
 
 #include "../../include/gvgeom.h"
 #include "gv_baskets.h"
+#include "gv_probe.h"
 
 using namespace gv;
 
@@ -62,13 +63,13 @@ struct gv_geom {
   int8_t* ob_proc = nullptr;
   void* mat_mem = nullptr;  // device material tables (geom_set_materials)
   int64_t ob_cap = 0, ob_steps = 0;
-  // live count of the transport loop: one pinned, mapped word (tag << 32 |
-  // count) that the scatter kernel stores at a chunk's end and the host polls
-  unsigned long long* h_live = nullptr;
-  unsigned long long* d_live = nullptr;  // device address of h_live
-  uint32_t live_tag = 0;                 // tag of the last stored count
-  // kernel timing for measurement (gv_profile)
+  // measurement (gv_profile): HIP events around the step-kernel launches, and
+  // the step-kernel instance that keeps the work counters
   bool prof = false;
+  bool prof_work = false;
+  // launch shapes (gv_set_tuning); zero / negative fields take the defaults
+  gv_tuning tune{0, 0, -1, 0, 0, 0};
+  int ws_nl = 0;  // buckets the workspace was sized for
   std::vector<hipEvent_t> prof_ev;  // pairs around step-kernel launches
   size_t prof_used = 0;
 };
@@ -728,7 +729,6 @@ extern "C" int geom_free(gv_geom* g) {
   if (g->ob) (void)hipFree(g->ob);
   if (g->mat_mem) (void)hipFree(g->mat_mem);
   if (g->dmem) (void)hipFree(g->dmem);
-  if (g->h_live) (void)hipHostFree(g->h_live);
   for (auto& ev : g->prof_ev) (void)hipEventDestroy(ev);
   if (dev != g->device && dev >= 0) (void)hipSetDevice(dev);
   delete g;
@@ -781,10 +781,20 @@ int check_i32(const char* fn, const char* name, const void* p, bool nullable = f
 }
 
 constexpr int kBlock = 256;
-unsigned grid_for(int64_t n) {
-  int64_t b = (n + kBlock - 1) / kBlock;
-  if (b > (1 << 20)) b = 1 << 20;
-  return (unsigned)(b < 1 ? 1 : b);
+
+// Launch shape of the one-lane-per-track kernels (solid level, per-track
+// navigation): the tuned block size and workgroup cap, else 256 threads and
+// one lane per track.  Every kernel of this kind is grid-stride, so the shape
+// never changes a result.
+struct Shape {
+  unsigned grid, block;
+};
+Shape lane_shape(const gv_geom* g, int64_t n) {
+  const int64_t blk = g->tune.solid_block > 0 ? g->tune.solid_block : kBlock;
+  int64_t b = (n + blk - 1) / blk;
+  const int64_t cap = g->tune.solid_grid > 0 ? g->tune.solid_grid : (1 << 20);
+  b = std::min(b, cap);
+  return Shape{(unsigned)std::max<int64_t>(1, b), (unsigned)blk};
 }
 
 int launched(const char* fn) {
@@ -835,8 +845,8 @@ extern "C" int basket_inside(gv_geom* g, int32_t lv, int64_t n, const double* x,
   DeviceGuard dgd(g->device);
   CQ q = g->dg.par + g->lv_par[lv];
   hipStream_t s = (hipStream_t)stream;
-  unsigned gr = grid_for(n);
-#define CALL(S) hipLaunchKernelGGL(k_inside<S>, dim3(gr), dim3(kBlock), 0, s, q, n, x, y, z, out)
+  const Shape sh = lane_shape(g, n);
+#define CALL(S) hipLaunchKernelGGL(k_inside<S>, dim3(sh.grid), dim3(sh.block), 0, s, q, n, x, y, z, out)
   GV_SOLID_SWITCH(g->lv_type[lv], CALL)
 #undef CALL
   return launched(fn);
@@ -859,9 +869,9 @@ extern "C" int basket_safety(gv_geom* g, int32_t lv, int32_t side, int64_t n, co
   DeviceGuard dgd(g->device);
   CQ q = g->dg.par + g->lv_par[lv];
   hipStream_t s = (hipStream_t)stream;
-  unsigned gr = grid_for(n);
+  const Shape sh = lane_shape(g, n);
 #define CALL(S) \
-  hipLaunchKernelGGL(k_safety<S>, dim3(gr), dim3(kBlock), 0, s, q, (int)side, n, x, y, z, out_safety, out_inside)
+  hipLaunchKernelGGL(k_safety<S>, dim3(sh.grid), dim3(sh.block), 0, s, q, (int)side, n, x, y, z, out_safety, out_inside)
   GV_SOLID_SWITCH(g->lv_type[lv], CALL)
 #undef CALL
   return launched(fn);
@@ -883,13 +893,13 @@ extern "C" int basket_distance(gv_geom* g, int32_t lv, int32_t dir, int64_t n, c
   DeviceGuard dgd(g->device);
   CQ q = g->dg.par + g->lv_par[lv];
   hipStream_t s = (hipStream_t)stream;
-  unsigned gr = grid_for(n);
+  const Shape sh = lane_shape(g, n);
   if (dir == GV_TO_IN) {
-#define CALL(S) hipLaunchKernelGGL((k_distance<S, 0>), dim3(gr), dim3(kBlock), 0, s, q, n, x, y, z, dx, dy, dz, out)
+#define CALL(S) hipLaunchKernelGGL((k_distance<S, 0>), dim3(sh.grid), dim3(sh.block), 0, s, q, n, x, y, z, dx, dy, dz, out)
     GV_SOLID_SWITCH(g->lv_type[lv], CALL)
 #undef CALL
   } else {
-#define CALL(S) hipLaunchKernelGGL((k_distance<S, 1>), dim3(gr), dim3(kBlock), 0, s, q, n, x, y, z, dx, dy, dz, out)
+#define CALL(S) hipLaunchKernelGGL((k_distance<S, 1>), dim3(sh.grid), dim3(sh.block), 0, s, q, n, x, y, z, dx, dy, dz, out)
     GV_SOLID_SWITCH(g->lv_type[lv], CALL)
 #undef CALL
   }
@@ -914,9 +924,9 @@ extern "C" int basket_solid_all(gv_geom* g, int32_t lv, int64_t n, const double*
   DeviceGuard dgd(g->device);
   CQ q = g->dg.par + g->lv_par[lv];
   hipStream_t s = (hipStream_t)stream;
-  unsigned gr = grid_for(n);
+  const Shape sh = lane_shape(g, n);
 #define CALL(S)                                                                                          \
-  hipLaunchKernelGGL(k_solid_all<S>, dim3(gr), dim3(kBlock), 0, s, q, n, x, y, z, dx, dy, dz, out_inside, \
+  hipLaunchKernelGGL(k_solid_all<S>, dim3(sh.grid), dim3(sh.block), 0, s, q, n, x, y, z, dx, dy, dz, out_inside, \
                      out_safety, out_dist_in, out_dist_out)
   GV_SOLID_SWITCH(g->lv_type[lv], CALL)
 #undef CALL
@@ -934,7 +944,7 @@ extern "C" int basket_locate(gv_geom* g, int64_t n, const double* x, const doubl
   GV_TRY(check_f64(fn, "z", z));
   GV_TRY(check_i32(fn, "out_pv", out_pv));
   DeviceGuard dgd(g->device);
-  hipLaunchKernelGGL(g->has_bool ? k_locate<true> : k_locate<false>, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, g->dg, n, x, y, z, out_pv);
+  hipLaunchKernelGGL(g->has_bool ? k_locate<true> : k_locate<false>, dim3(lane_shape(g, n).grid), dim3(lane_shape(g, n).block), 0, (hipStream_t)stream, g->dg, n, x, y, z, out_pv);
   return launched(fn);
 }
 
@@ -957,7 +967,7 @@ extern "C" int basket_step(gv_geom* g, int64_t n, const double* x, const double*
   DeviceGuard dgd(g->device);
   const auto kern = g->has_bool ? (precision == GV_FP64 ? k_step_nav<false, true> : k_step_nav<true, true>)
                                 : (precision == GV_FP64 ? k_step_nav<false, false> : k_step_nav<true, false>);
-  hipLaunchKernelGGL(kern, dim3(grid_for(n)), dim3(kBlock), 0,
+  hipLaunchKernelGGL(kern, dim3(lane_shape(g, n).grid), dim3(lane_shape(g, n).block), 0,
                      (hipStream_t)stream, g->dg, n, x, y, z, dx, dy, dz, pv, pstep, out_step, out_next_pv, out_flags);
   return launched(fn);
 }
@@ -976,7 +986,7 @@ extern "C" int basket_nav_safety(gv_geom* g, int64_t n, const double* x, const d
   DeviceGuard dgd(g->device);
   const auto kern = g->has_bool ? (precision == GV_FP64 ? k_nav_safety<true> : k_nav_safety_scr<true>)
                                 : (precision == GV_FP64 ? k_nav_safety<false> : k_nav_safety_scr<false>);
-  hipLaunchKernelGGL(kern, dim3(grid_for(n)), dim3(kBlock), 0,
+  hipLaunchKernelGGL(kern, dim3(lane_shape(g, n).grid), dim3(lane_shape(g, n).block), 0,
                      (hipStream_t)stream, g->dg, n, x, y, z, pv, out);
   return launched(fn);
 }
@@ -992,7 +1002,7 @@ extern "C" int basket_nav_inside(gv_geom* g, int64_t n, const double* x, const d
   GV_TRY(check_i32(fn, "pv", pv));
   if (!out) return fail(GV_EINVAL, "%s: out is NULL", fn);
   DeviceGuard dgd(g->device);
-  hipLaunchKernelGGL(g->has_bool ? k_nav_inside<true> : k_nav_inside<false>, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, g->dg, n, x, y, z, pv,
+  hipLaunchKernelGGL(g->has_bool ? k_nav_inside<true> : k_nav_inside<false>, dim3(lane_shape(g, n).grid), dim3(lane_shape(g, n).block), 0, (hipStream_t)stream, g->dg, n, x, y, z, pv,
                      out);
   return launched(fn);
 }
@@ -1002,19 +1012,39 @@ namespace {
 
 size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// Bits of the coarse direction cell in a bucket key (LV << bits | cell): 4
-// cells (2 x 2) while LVs x cells <= 4096, else none.  Finer cells (16) gave
-// the same step time with the daughter indexes and cost more in the bucket
-// layouts of every step.
-int coarse_bits(int n_lv) { return n_lv <= 1024 ? 2 : 0; }
+// Bits of the coarse direction cell in a bucket key (LV << bits | cell): by
+// default 4 cells (2 x 2) while LVs x cells <= 4096, else none.  Finer cells
+// (16) gave the same step time with the daughter indexes and cost more in the
+// bucket layouts of every step.  The tuned value applies while LVs x cells
+// stays within 4096.
+int cell_bits(const gv_geom* g) {
+  const int t = g->tune.cell_bits;
+  if (t >= 0 && (g->n_lv << t) <= 4096) return t;
+  return g->n_lv <= 1024 ? 2 : 0;
+}
+
+// Workgroups of the regrouping kernels (1024 threads each, about 4096 list
+// entries per workgroup by default).
+unsigned scatter_grid(const gv_geom* g, int64_t n) {
+  if (g->tune.scatter_grid > 0) return (unsigned)std::min<int64_t>(g->tune.scatter_grid, n / 64 + 1);
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 4095) / 4096, 256));
+}
+
+// Workgroups of the per-step kernel: by default one per four tiles of the
+// first list, at most kMaxStepGrid (the whole grid is then resident).
+unsigned step_grid_for(const gv_geom* g, int64_t n) {
+  const int64_t max_tiles = n / kWave + g->n_lv + 1;
+  int64_t w = g->tune.step_grid > 0 ? g->tune.step_grid : (max_tiles + 3) / 4;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(w, kMaxStepGrid));
+}
 
 // Track records, two bucketed index lists, the next-LV array, and per-LV
 // counters and layouts.  Allocated with hipMalloc on first use and kept in the
 // handle.
 int ensure_workspace(gv_geom* g, int64_t n) {
-  if (g->ws && g->ws_tracks >= n) return GV_OK;
-  int64_t cap = n < 4096 ? 4096 : n;
-  int nl = g->n_lv << coarse_bits(g->n_lv);
+  const int nl = g->n_lv << cell_bits(g);
+  if (g->ws && g->ws_tracks >= n && g->ws_nl >= nl) return GV_OK;
+  int64_t cap = n < 4096 ? 4096 : std::max<int64_t>(n, g->ws_tracks);
   size_t total = al256(sizeof(TRec) * (size_t)cap) + 5 * al256(4 * (size_t)cap) + 6 * al256(4 * (size_t)nl) +
                  al256(8 * kWorkN) + al256(4) + al256(4 * (size_t)kMaxStepGrid * nl) + al256(8);
   if (g->ws) {
@@ -1026,11 +1056,8 @@ int ensure_workspace(gv_geom* g, int64_t n) {
   void* mem = nullptr;
   hipError_t e = hipMalloc(&mem, total);
   if (e != hipSuccess) return fail(GV_ENOMEM, "nav_transport: workspace hipMalloc(%zu): %s", total, hipGetErrorString(e));
-  e = hipMemset(mem, 0, total);
-  if (e != hipSuccess) {
-    (void)hipFree(mem);
-    return hip_fail(e, "nav_transport: workspace hipMemset");
-  }
+  // no clearing needed: every transport clears its counters with k_bt_clear
+  // and writes every other array before reading it
   char* p = (char*)mem;
   auto take = [&](size_t b) {
     char* r = p;
@@ -1051,50 +1078,11 @@ int ensure_workspace(gv_geom* g, int64_t n) {
   g->ctl.nlive = (int*)take(4);
   g->ctl.seg = (int*)take(4 * (size_t)kMaxStepGrid * nl);
   g->ctl.len = (int*)take(8);
-  if (!g->h_live) {
-    e = hipHostMalloc((void**)&g->h_live, sizeof(unsigned long long), hipHostMallocMapped | hipHostMallocCoherent);
-    if (e != hipSuccess) return hip_fail(e, "nav_transport: hipHostMalloc");
-    *(volatile unsigned long long*)g->h_live = 0;
-    g->live_tag = 0;
-    e = hipHostGetDevicePointer((void**)&g->d_live, g->h_live, 0);
-    if (e != hipSuccess) return hip_fail(e, "nav_transport: hipHostGetDevicePointer");
-  }
   g->ws = mem;
   g->ws_bytes = total;
   g->ws_tracks = cap;
+  g->ws_nl = nl;
   return GV_OK;
-}
-
-// Waits until the scatter kernel has stored the live count tagged `tag` into
-// the pinned word and returns the word.  The host spins on the word; every
-// 2 ms without it, it asks whether the stream has drained (an error there, or
-// a drained stream without the tag, is returned as a failure).
-int wait_live(gv_geom* g, hipStream_t s, uint32_t tag, unsigned long long* out) {
-  const volatile unsigned long long* w = g->h_live;
-  auto t0 = std::chrono::steady_clock::now();
-  for (;;) {
-    for (int i = 0; i < 1024; ++i) {
-      const unsigned long long v = *w;
-      if ((uint32_t)(v >> 32) == tag) {
-        *out = v;
-        return GV_OK;
-      }
-      _mm_pause();
-    }
-    if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2)) {
-      const hipError_t q = hipStreamQuery(s);
-      if (q == hipSuccess) {
-        const unsigned long long v = *w;
-        if ((uint32_t)(v >> 32) == tag) {
-          *out = v;
-          return GV_OK;
-        }
-        return fail(GV_EHIP, "nav_transport: live count of chunk %u not stored", tag);
-      }
-      if (q != hipErrorNotReady) return hip_fail(q, "nav_transport: hipStreamQuery");
-      t0 = std::chrono::steady_clock::now();
-    }
-  }
 }
 
 // Step-major output staging for `steps` steps of the workspace's tracks, kept
@@ -1130,6 +1118,35 @@ bool ensure_staging(gv_geom* g, int64_t steps) {
   return true;
 }
 
+// Whether the staging from an earlier call covers this one (used under stream
+// capture, where nothing is allocated).  Without it the step kernel writes the
+// rows directly, with the same results.
+bool staging_ready(const gv_geom* g, int64_t steps) {
+  return g->ob && g->ob_cap >= g->ws_tracks && g->ob_steps >= steps;
+}
+
+// The per-step kernel for this call: composites or not, FP32 screens or not,
+// physics-limited or not, the work-counting instance while counters are
+// asked for (geometries without composites), and the tuned register budget
+// of the navigation step (3 or 4 waves per SIMD).
+using StepKernel = void (*)(DevGeom, int, int, int, const int*, const int*, TRec*, const int*, int*, uint32_t*, int*,
+                            TCtl, int32_t*, double*, int32_t*, uint32_t*, const int*, double*, int*, int64_t,
+                            PhysArgs, int8_t*, int8_t*);
+StepKernel select_step_kernel(const gv_geom* g, bool fp32, bool phys) {
+  if (g->has_bool) {
+    if (phys) return fp32 ? k_bt_step<true, true, true, false, 3> : k_bt_step<false, true, true, false, 3>;
+    return fp32 ? k_bt_step<true, false, true, false, 4> : k_bt_step<false, false, true, false, 4>;
+  }
+  if (g->prof_work) {
+    if (phys) return fp32 ? k_bt_step<true, true, false, true, 3> : k_bt_step<false, true, false, true, 3>;
+    return fp32 ? k_bt_step<true, false, false, true, 4> : k_bt_step<false, false, false, true, 4>;
+  }
+  if (phys) return fp32 ? k_bt_step<true, true, false, false, 3> : k_bt_step<false, true, false, false, 3>;
+  if (g->tune.step_waves == 3)
+    return fp32 ? k_bt_step<true, false, false, false, 3> : k_bt_step<false, false, false, false, 3>;
+  return fp32 ? k_bt_step<true, false, false, false, 4> : k_bt_step<false, false, false, false, 4>;
+}
+
 constexpr int64_t kBasketMin = 8192;  // smaller batches use one lane per track
 
 unsigned stream_grid(int64_t n) {
@@ -1142,12 +1159,25 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
                      double* out_step, int32_t* out_nsteps, uint32_t* out_flags, bool fp32, bool phys,
                      PhysArgs P, int8_t* out_proc, hipStream_t s) {
   const char* fn = "nav_transport";
-  GV_TRY(ensure_workspace(g, n));
-  const int cb = coarse_bits(g->n_lv);
+  // Under stream capture nothing may be allocated or waited for: the
+  // workspace (and the output staging, when it fits) must already exist from
+  // an earlier call of at least this size.
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cap) != hipSuccess) cap = hipStreamCaptureStatusNone;
+  const bool capturing = cap == hipStreamCaptureStatusActive;
+  if (capturing) {
+    if (!g->ws || g->ws_tracks < n)
+      return fail(GV_ESTATE, "%s: stream is capturing and the workspace holds %lld < %lld tracks; call once "
+                  "outside the capture first", fn, (long long)g->ws_tracks, (long long)n);
+    if (g->prof) return fail(GV_ESTATE, "%s: profiling events cannot be recorded under stream capture", fn);
+  } else {
+    GV_TRY(ensure_workspace(g, n));
+  }
+  const int cb = cell_bits(g);
   const int nl = g->n_lv << cb;  // buckets: (LV, coarse direction cell)
   const unsigned sg = stream_grid(n);
   const size_t lds_ix = 12 * (size_t)nl + 4, lds_step = 4 * (size_t)nl + 12 * (size_t)g->n_lv + 8;
-  const unsigned rg = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 4095) / 4096, 256));
+  const unsigned rg = scatter_grid(g, n);
   TCtl& C = g->ctl;
   hipLaunchKernelGGL(k_bt_clear, dim3(1), dim3(kBlock), 0, s, C, nl);
   GV_TRY(launched(fn));
@@ -1156,37 +1186,25 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
   GV_TRY(launched(fn));
   // live track ids in bucket order (into idx[1]), then slots in that order
   hipLaunchKernelGGL(k_bt_reindex, dim3(rg), dim3(1024), lds_ix, s, (const int*)nullptr, (const int*)nullptr, 0, n,
-                     (const int*)g->nxt_lv, 0, g->idx[1], (const int*)C.cnt[0], C.cur[0], C.cnt[1], C.cur[1],
-                     (unsigned long long*)nullptr, 0u, nl);
+                     (const int*)g->nxt_lv, 0, g->idx[1], (const int*)C.cnt[0], C.cur[0], C.cnt[1], C.cur[1], nl);
   GV_TRY(launched(fn));
   hipLaunchKernelGGL(k_bt_place, dim3(sg), dim3(kBlock), 0, s, (const int*)g->idx[1], x, y, z, dx, dy, dz,
                      (const int32_t*)out_pv, max_steps, cb, nl, g->rec, g->slot_id, g->idx[0], C);
   GV_TRY(launched(fn));
-  const bool staged = ensure_staging(g, max_steps);
+  const bool staged = capturing ? staging_ready(g, max_steps) : ensure_staging(g, max_steps);
   double* ob_step = staged ? g->ob_step : nullptr;
   int* ob_pv = staged ? g->ob_pv : nullptr;
   int8_t* ob_proc = staged && phys && out_proc ? g->ob_proc : nullptr;
-  const auto step_kernel =
-      g->has_bool ? (fp32 ? (phys ? k_bt_step<true, true, true> : k_bt_step<true, false, true>)
-                          : (phys ? k_bt_step<false, true, true> : k_bt_step<false, false, true>))
-                  : (fp32 ? (phys ? k_bt_step<true, true, false> : k_bt_step<true, false, false>)
-                          : (phys ? k_bt_step<false, true, false> : k_bt_step<false, false, false>));
-  const int64_t max_tiles = n / kWave + g->n_lv + 1;
-  const unsigned step_grid =
-      (unsigned)std::max<int64_t>(1, std::min<int64_t>((max_tiles + 3) / 4, kMaxStepGrid));
+  const auto step_kernel = select_step_kernel(g, fp32, phys);
+  const unsigned step_grid = step_grid_for(g, n);
   const size_t lds_sc = 8 * (size_t)nl + 4;
-  // The host enqueues steps in chunks of kChunk; at a chunk's end the scatter
-  // kernel stores the live count, tagged with the chunk, into pinned host
-  // memory.  Before enqueueing the end of chunk m the host polls for the count
-  // of chunk m-1 and stops once it is zero, so at most about two chunks of
-  // empty steps are launched, and the device still has a chunk queued while
-  // the host looks.  The host reads the word directly rather than through
-  // stream events, which would put a system-scope fence between two steps.
-  constexpr int kChunk = 2;
-  int chunk = 0, launched_steps = 0;
-  const uint32_t tag0 = g->live_tag + 1;
+  // Every step up to max_steps is enqueued at once and the call returns: a
+  // step kernel whose list is empty leaves at once, and so does the regrouping
+  // kernel after it (which then passes the empty length on), so the launches
+  // past the longest track cost only their dispatch.  The host never waits.
   for (int k = 0; k < max_steps; ++k) {
     const int c = k & 1, k0 = k % 3, k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+    const int* len_cur = k == 0 ? C.nlive : C.len + (k & 1);
     hipEvent_t* pe = nullptr;
     if (g->prof) {
       if (g->prof_used + 2 > g->prof_ev.size()) {
@@ -1201,36 +1219,22 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
       (void)hipEventRecord(pe[0], s);
     }
     hipLaunchKernelGGL(step_kernel, dim3(step_grid), dim3(kBlock), lds_step, s, g->dg, k, max_steps, cb,
-                       (const int*)g->idx[c], g->rec, (const int*)C.cnt[k0], g->nxt_lv, g->nxt_pos, C.cnt[k1], C,
-                       out_pv,
-                       out_step, out_nsteps, out_flags, (const int*)g->slot_id, ob_step, ob_pv, g->ob_cap, P,
-                       ob_proc, out_proc);
+                       (const int*)g->idx[c], len_cur, g->rec, (const int*)C.cnt[k0], g->nxt_lv, g->nxt_pos,
+                       C.cnt[k1], C, out_pv, out_step, out_nsteps, out_flags, (const int*)g->slot_id, ob_step, ob_pv,
+                       g->ob_cap, P, ob_proc, out_proc);
     GV_TRY(launched(fn));
-    launched_steps = k + 1;
     if (pe) (void)hipEventRecord(pe[1], s);
     if (k + 1 == max_steps) break;
-    const bool report = (k + 1) % kChunk == 0;
-    if (report && chunk >= 1) {
-      unsigned long long w = 0;
-      GV_TRY(wait_live(g, s, tag0 + (uint32_t)chunk - 1, &w));
-      if ((uint32_t)w == 0) break;
-    }
-    hipLaunchKernelGGL(k_bt_scatter, dim3(rg), dim3(1024), lds_sc, s, (const int*)g->idx[c],
-                       (const int*)(k == 0 ? C.nlive : C.len + (k & 1)), (const int*)g->nxt_lv,
-                       (const uint32_t*)g->nxt_pos, (const int*)C.seg, (const int*)C.cnt[k1], g->idx[c ^ 1],
-                       C.len + ((k + 1) & 1), C.cnt[k2], report ? g->d_live : (unsigned long long*)nullptr,
-                       tag0 + (uint32_t)chunk, nl);
+    hipLaunchKernelGGL(k_bt_scatter, dim3(rg), dim3(1024), lds_sc, s, (const int*)g->idx[c], len_cur,
+                       (const int*)g->nxt_lv, (const uint32_t*)g->nxt_pos, (const int*)C.seg, (const int*)C.cnt[k1],
+                       g->idx[c ^ 1], C.len + ((k + 1) & 1), C.cnt[k2], nl);
     GV_TRY(launched(fn));
-    if (report) {
-      g->live_tag = tag0 + (uint32_t)chunk;
-      ++chunk;
-    }
   }
-  if (staged && launched_steps > 0) {
+  if (staged) {
     hipLaunchKernelGGL(ob_proc ? k_bt_emit<true> : k_bt_emit<false>, dim3((unsigned)((n + 63) / 64)), dim3(512), 0,
                        s, (const double*)ob_step,
                        (const int*)ob_pv, (const int8_t*)ob_proc, g->ob_cap, (const int*)g->slot_id, C, max_steps,
-                       launched_steps, (const int32_t*)out_nsteps, out_step, out_pv, out_proc);
+                       max_steps, (const int32_t*)out_nsteps, out_step, out_pv, out_proc);
     GV_TRY(launched(fn));
   }
   return GV_OK;
@@ -1268,7 +1272,7 @@ int transport_common(const char* fn, gv_geom* g, int64_t n, const double* x, con
                           : (phys ? k_transport_lane<false, true, true> : k_transport_lane<false, false, true>))
                   : (fp32 ? (phys ? k_transport_lane<true, true, false> : k_transport_lane<true, false, false>)
                           : (phys ? k_transport_lane<false, true, false> : k_transport_lane<false, false, false>));
-  hipLaunchKernelGGL(lane, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, g->dg, n, x, y, z, dx, dy, dz,
+  hipLaunchKernelGGL(lane, dim3(lane_shape(g, n).grid), dim3(lane_shape(g, n).block), 0, (hipStream_t)stream, g->dg, n, x, y, z, dx, dy, dz,
                      start_pv, (int)max_steps, out_pv, out_step, out_nsteps, out_flags, P, out_proc);
   return launched(fn);
 }
@@ -1337,9 +1341,61 @@ extern "C" int geom_set_materials(gv_geom* g, int32_t n_mat, int32_t n_proc, con
 }
 
 // ------------------------------------------------------------ measurement
-extern "C" int gv_profile(gv_geom* g, int enable) {
+extern "C" int gv_profile(gv_geom* g, int flags) {
   if (!g) return fail(GV_EINVAL, "gv_profile: geometry handle is NULL");
-  g->prof = enable != 0;
+  if (flags & ~(GV_PROF_EVENTS | GV_PROF_WORK)) return fail(GV_EINVAL, "gv_profile: flags %d", flags);
+  g->prof = (flags & GV_PROF_EVENTS) != 0;
+  g->prof_work = (flags & GV_PROF_WORK) != 0;
+  return GV_OK;
+}
+
+// ------------------------------------------------------------- roof probes
+extern "C" int gv_probe_stream(const double* a, const double* b, double* c, double s, int64_t n, void* stream) {
+  const char* fn = "gv_probe_stream";
+  if (n < 0 || (n & 1)) return fail(GV_EINVAL, "%s: n %lld must be even and >= 0", fn, (long long)n);
+  if (n == 0) return GV_OK;
+  if (!a || !c) return fail(GV_EINVAL, "%s: a or c is NULL", fn);
+  if (((uintptr_t)a | (uintptr_t)b | (uintptr_t)c) & 15) return fail(GV_EINVAL, "%s: arrays not 16-byte aligned", fn);
+  const int64_t n2 = n / 2;
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n2 + 255) / 256, 256 * 32));
+  hipLaunchKernelGGL(k_probe_triad, dim3(grid), dim3(256), 0, (hipStream_t)stream, (const double2*)a,
+                     (const double2*)b, (double2*)c, s, n2);
+  return launched(fn);
+}
+
+extern "C" int gv_probe_fma64(double* out, int64_t n_lanes, int32_t iters, void* stream) {
+  const char* fn = "gv_probe_fma64";
+  if (n_lanes <= 0 || n_lanes % 256) return fail(GV_EINVAL, "%s: n_lanes must be a positive multiple of 256", fn);
+  if (iters < 1) return fail(GV_EINVAL, "%s: iters < 1", fn);
+  if (!out || ((uintptr_t)out & 7)) return fail(GV_EINVAL, "%s: out NULL or misaligned", fn);
+  hipLaunchKernelGGL(k_probe_fma64, dim3((unsigned)(n_lanes / 256)), dim3(256), 0, (hipStream_t)stream, out, iters,
+                     0.999999, 1e-6);
+  return launched(fn);
+}
+
+// ------------------------------------------------------------ launch shapes
+extern "C" int gv_set_tuning(gv_geom* g, const gv_tuning* t) {
+  const char* fn = "gv_set_tuning";
+  if (!g || !t) return fail(GV_EINVAL, "%s: NULL argument", fn);
+  if (t->step_grid < 0 || t->step_grid > kMaxStepGrid)
+    return fail(GV_EINVAL, "%s: step_grid %d not in [0, %d]", fn, t->step_grid, kMaxStepGrid);
+  if (t->scatter_grid < 0 || t->scatter_grid > 1024)
+    return fail(GV_EINVAL, "%s: scatter_grid %d not in [0, 1024]", fn, t->scatter_grid);
+  if (!(t->cell_bits == -1 || t->cell_bits == 0 || t->cell_bits == 2 || t->cell_bits == 4))
+    return fail(GV_EINVAL, "%s: cell_bits %d not -1, 0, 2 or 4", fn, t->cell_bits);
+  if (t->solid_block != 0 && (t->solid_block < 64 || t->solid_block > 1024 || t->solid_block % 64))
+    return fail(GV_EINVAL, "%s: solid_block %d not 0 or a multiple of 64 in [64, 1024]", fn, t->solid_block);
+  if (t->solid_grid < 0) return fail(GV_EINVAL, "%s: solid_grid %d < 0", fn, t->solid_grid);
+  if (!(t->step_waves == 0 || t->step_waves == 3 || t->step_waves == 4))
+    return fail(GV_EINVAL, "%s: step_waves %d not 0, 3 or 4", fn, t->step_waves);
+  g->tune = *t;
+  t_err.clear();
+  return GV_OK;
+}
+
+extern "C" int gv_get_tuning(const gv_geom* g, gv_tuning* t) {
+  if (!g || !t) return fail(GV_EINVAL, "gv_get_tuning: NULL argument");
+  *t = g->tune;
   return GV_OK;
 }
 

@@ -312,16 +312,14 @@ __device__ __forceinline__ int wave_lds_reserve(int v, bool on, int* cnt) {
 // one contiguous range of positions: it counts them per bucket in LDS, reserves
 // one contiguous range per bucket with a single global atomic, then writes them
 // in a second pass, so a workgroup's entries keep their order in each bucket.
-// Workgroup 0 clears cnt_clear/cur_clear (nullable) and stores the number of
-// entries of the new list, tagged (tag << 32 | count), into `live` (nullable;
-// device memory or mapped pinned host memory).  Needs 12 * nb + 4 bytes of
-// dynamic LDS.
+// Workgroup 0 clears cnt_clear/cur_clear (nullable).  Needs 12 * nb + 4 bytes
+// of dynamic LDS.
 __global__ void __launch_bounds__(1024) k_bt_reindex(const int* __restrict__ src_idx, const int* __restrict__ cnt_src,
                                                       int nsrc_bins, int64_t nsrc_fixed, const int* __restrict__ key,
                                                       int gather, int* __restrict__ dst_idx,
                                                       const int* __restrict__ cnt_dst, int* __restrict__ cur_dst,
                                                       int* __restrict__ cnt_clear, int* __restrict__ cur_clear,
-                                                      unsigned long long* __restrict__ live, uint32_t tag, int nb) {
+                                                      int nb) {
   extern __shared__ int lds[];
   int* cnt = lds;
   int* base = lds + nb;
@@ -340,9 +338,6 @@ __global__ void __launch_bounds__(1024) k_bt_reindex(const int* __restrict__ src
     nsrc = total;
   }
   if (blockIdx.x == 0) {
-    if (threadIdx.x == 0 && live)
-      __hip_atomic_store(live, ((unsigned long long)tag << 32) | (uint32_t)start[nb], __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_SYSTEM);
     for (int b = threadIdx.x; b < nb; b += blockDim.x) {
       if (cnt_clear) cnt_clear[b] = 0;
       if (cur_clear) cur_clear[b] = 0;
@@ -383,20 +378,25 @@ __global__ void __launch_bounds__(1024) k_bt_reindex(const int* __restrict__ src
 // its rank in that share.  One pass, no atomics.  A thread's first kScatterUnroll
 // entries are loaded before the bucket layout is computed, so their latency
 // overlaps it.  len_src holds list k's length; workgroup 0 stores list k+1's
-// into len_dst and, tagged (tag << 32 | count), into `live` (nullable), and
-// clears the counts two lists ahead.  Needs 8 * nb + 4 bytes of dynamic LDS.
+// into len_dst and clears the counts two lists ahead.  An empty list k leaves
+// at once with list k+1's length 0 (the counts are then untouched and nothing
+// reads them before the next transport clears them).  Needs 8 * nb + 4 bytes
+// of dynamic LDS.
 constexpr int kScatterUnroll = 4;
 __global__ void __launch_bounds__(1024) k_bt_scatter(const int* __restrict__ src_idx, const int* __restrict__ len_src,
                                                       const int* __restrict__ nxt_lv,
                                                       const uint32_t* __restrict__ nxt_pos,
                                                       const int* __restrict__ seg, const int* __restrict__ cnt_dst,
                                                       int* __restrict__ dst_idx, int* __restrict__ len_dst,
-                                                      int* __restrict__ cnt_clear, unsigned long long* __restrict__ live,
-                                                      uint32_t tag, int nb) {
+                                                      int* __restrict__ cnt_clear, int nb) {
   extern __shared__ int lds[];
   int* base = lds;
   int* start = lds + nb;  // nb + 1 entries
   const int64_t nsrc = *len_src;
+  if (nsrc == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *len_dst = 0;
+    return;
+  }
   const int64_t chunk = (int64_t)blockDim.x * kScatterUnroll;
   int64_t j0 = (int64_t)blockIdx.x * chunk + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * chunk;
@@ -416,12 +416,7 @@ __global__ void __launch_bounds__(1024) k_bt_scatter(const int* __restrict__ src
   stage_counts(cnt_dst, nb, base);
   block_layout(base, nb, start, nullptr);
   if (blockIdx.x == 0) {
-    if (threadIdx.x == 0) {
-      *len_dst = start[nb];
-      if (live)
-        __hip_atomic_store(live, ((unsigned long long)tag << 32) | (uint32_t)start[nb], __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_SYSTEM);
-    }
+    if (threadIdx.x == 0) *len_dst = start[nb];
     for (int v = threadIdx.x; v < nb; v += blockDim.x) cnt_clear[v] = 0;
   }
   for (; j0 < nsrc; j0 += stride) {
@@ -437,19 +432,18 @@ __global__ void __launch_bounds__(1024) k_bt_scatter(const int* __restrict__ src
 }
 
 // ---------------------------------------------------------------- step
-// Register budget per variant: the navigation step fits 128 VGPRs (4 waves per
-// SIMD) without spilling and runs fastest there; the physics-limited step
+// Register budget per variant (WV waves per SIMD): the navigation step fits
+// 128 VGPRs (4 waves per SIMD) without spilling; the physics-limited step
 // (process lengths, generator state, distance still to go) spills 80 bytes per
-// lane at 128 and runs faster with 168 VGPRs at 3 waves.
-#ifndef GV_STEP_WAVES_PER_EU
-#define GV_STEP_WAVES_PER_EU 4
-#endif
-#ifndef GV_PHYS_STEP_WAVES_PER_EU
-#define GV_PHYS_STEP_WAVES_PER_EU 3
-#endif
-template <bool F32, bool PHYS, bool B>
-__global__ void __launch_bounds__(256)
-    __attribute__((amdgpu_waves_per_eu(PHYS ? GV_PHYS_STEP_WAVES_PER_EU : GV_STEP_WAVES_PER_EU))) k_bt_step(DevGeom G, int k, int max_steps, int cb, const int* __restrict__ idx,
+// lane at 128 and runs faster with 168 VGPRs at 3 waves.  The launch shape
+// chooses among the instances that are built.
+// WK selects the instance that keeps the work counters (measurement only: a
+// ballot and an LDS atomic per counted event); the production instance counts
+// nothing.  The kernel leaves at once when its list is empty (len_cur), so the
+// host may enqueue every step up to the bound without looking at the device.
+template <bool F32, bool PHYS, bool B, bool WK, int WV>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WV))) k_bt_step(DevGeom G, int k, int max_steps, int cb, const int* __restrict__ idx,
+                                                  const int* __restrict__ len_cur,
                                                   TRec* __restrict__ rec, const int* __restrict__ cnt_cur,
                                                   int* __restrict__ nxt_lv, uint32_t* __restrict__ nxt_pos,
                                                   int* __restrict__ cnt_next, TCtl C,
@@ -464,13 +458,15 @@ __global__ void __launch_bounds__(256)
   // and ordered by direction cell; tiles cover whole LV ranges (a tile may
   // span two neighbouring cells) so that cells add no partial tiles.
   extern __shared__ int lds[];
-  __shared__ unsigned long long wsum[kWorkN];
+  __shared__ unsigned long long wsum[WK ? kWorkN : 1];
+  if (*len_cur == 0) return;  // nothing left to transport: the whole grid leaves
   const int nlv = G.n_lv, nb = nlv << cb;
   int* hist = lds;
   int* lvc = lds + nb;
   int* start = lvc + nlv;
   int* tilep = start + nlv + 1;
-  for (int i = threadIdx.x; i < kWorkN; i += blockDim.x) wsum[i] = 0;
+  if (WK)
+    for (int i = threadIdx.x; i < kWorkN; i += blockDim.x) wsum[i] = 0;
   stage_counts(cnt_cur, nb, hist);  // hist is free until the layout is done
   for (int v = threadIdx.x; v < nlv; v += blockDim.x) {
     int c = 0;
@@ -481,7 +477,7 @@ __global__ void __launch_bounds__(256)
   block_layout(lvc, nlv, start, tilep);
   for (int v = threadIdx.x; v < nb; v += blockDim.x) hist[v] = 0;
   __syncthreads();
-  LdsWork w{wsum};
+  std::conditional_t<WK, LdsWork, NoWork> w{wsum};
   const int tiles = tilep[nlv];
   const int lane = __lane_id();
   const int wave = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave);
@@ -551,7 +547,7 @@ __global__ void __launch_bounds__(256)
       }
       nxt_lv[e] = nlv_out;
     }
-    if (act) count_active(&wsum[kWorkSteps]);
+    if (act) w.add(kWorkSteps);
     // place in this workgroup's share of the next bucket
     const int rank = wave_lds_reserve(nlv_out >= 0 ? nlv_out : 0, nlv_out >= 0, hist);
     if (nlv_out >= 0) nxt_pos[e] = ((uint32_t)blockIdx.x << kRankBits) | (uint32_t)rank;
@@ -560,8 +556,9 @@ __global__ void __launch_bounds__(256)
   // the workgroup's share of each next bucket starts where the count stood
   for (int v = threadIdx.x; v < nb; v += blockDim.x)
     if (hist[v]) C.seg[(size_t)blockIdx.x * nb + v] = atomicAdd(&cnt_next[v], hist[v]);
-  for (int i = threadIdx.x; i < kWorkN; i += blockDim.x)
-    if (wsum[i]) atomicAdd(&C.work[i], wsum[i]);
+  if (WK)
+    for (int i = threadIdx.x; i < kWorkN; i += blockDim.x)
+      if (wsum[i]) atomicAdd(&C.work[i], wsum[i]);
 }
 
 

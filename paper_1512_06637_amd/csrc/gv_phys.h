@@ -1,8 +1,8 @@
 // Physics-limited steps.  Each process i of the current volume's material has
-// the mean free path lambda_i = 1 / (n sigma_i) (Sec. II, Eq. (1)); every step,
+// the mean free path lambda_i = 1 / (n sigma_i) (Sec. III, Eq. (1)); every step,
 // each process draws an interaction length by Monte Carlo and the shortest is
 // proposed as the physics step (the rates add up, Eqs. (2)-(3)); the navigator
-// then takes the border instead when it is nearer (Sec. II, Physics).
+// then takes the border instead when it is nearer (Sec. III.A).
 //
 // A length is s_i = -ln(u) / (n sigma_i), u in (0, 1) from the counter-based
 // generator Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) with counter

@@ -12,6 +12,8 @@
 // bit.  A wavefront whose rays fall outside the range the FP32 margins were
 // sized for runs the FP64 screens for that step instead.
 #pragma once
+#include <type_traits>
+
 #include "gv_kernels.h"
 #include "gv_phys.h"
 
@@ -52,6 +54,7 @@ struct LdsWork {
   __device__ __forceinline__ void add(int i, unsigned mult = 1) { count_active(&c[i], mult); }
 };
 struct NoWork {
+  __device__ __forceinline__ NoWork(unsigned long long* = nullptr) {}
   __device__ __forceinline__ void add(int, unsigned = 1) {}
 };
 

@@ -25,11 +25,12 @@ OPS_WORLD_STEP = TRANSFORM + BOX_DIST_OUT + 20 * (TRANSFORM + TUBE_DIST_IN + SEL
 OPS_LAYER_STEP = TRANSFORM + TUBE_DIST_OUT + 64 * (TRANSFORM + BOX_DIST_IN + SELECT) + STEP_FIXED
 OPS_MODULE_STEP = TRANSFORM + BOX_DIST_OUT + STEP_FIXED
 
-# Algorithmic HBM bytes of one basket step of one track (k_bt_step): its list
-# entry (4), its 64-byte record read and rewritten (128), the staged step length
-# and next volume (12), its next bucket and its place in the next list (8).
-# Geometry tables (a few hundred KB) stay in the caches and are not counted.
-STEP_BYTES = 4 + 128 + 12 + 8
+# Design traffic of one basket step of one track (k_bt_step): its list entry
+# (4), its 64-byte record read and rewritten (128), the staged step length and
+# next volume (12), its next bucket and its place in the next list (8).  This is
+# what the basket design moves, not what the method needs: the algorithmic
+# bytes of a transport are transport_bytes() below (inputs once, outputs once).
+STEP_DESIGN_BYTES = 4 + 128 + 12 + 8
 
 
 # bytes that must move per track of a transport: the SoA start state in
@@ -105,3 +106,39 @@ def detector_ops_culled(world, layer, module, work) -> float:
     if len(work) > 27:
         ops += work[26] * PHI_LOOKUP + work[27] * PHI_SECTOR
     return float(ops)
+
+
+# Solid-level queries: algorithmic FP64 lane-ops per track of the minimal
+# per-track formulation (same op definition as above; a division or a square
+# root counts 1), per solid and query.  Box and tube segment are the counts
+# above; the others are estimates of their formulas (cone: two normalised
+# cone terms and a z slab; sphere shell: one radius; Trd: two normalised slab
+# pairs; polycone with 10 z-planes: the section search and, per section, a
+# cone quadric for the distances and a point-segment distance for the exact
+# meridian safety).  Fused = all four answers from one read of the track.
+SOLID_OPS = {
+    "box": {"inside": 7, "safety": 7, "dist_in": BOX_DIST_IN, "dist_out": BOX_DIST_OUT},
+    "tubs": {"inside": 16, "safety": 22, "dist_in": TUBE_DIST_IN, "dist_out": TUBE_DIST_OUT},
+    "cons": {"inside": 14, "safety": 14, "dist_in": 60, "dist_out": 45},
+    "sphere": {"inside": 6, "safety": 7, "dist_in": 25, "dist_out": 20},
+    "trd": {"inside": 12, "safety": 12, "dist_in": 45, "dist_out": 20},
+    "pcon": {"inside": 20, "safety": 110, "dist_in": 370, "dist_out": 315},
+}
+for _v in SOLID_OPS.values():
+    _v["fused"] = _v["inside"] + _v["safety"] + _v["dist_in"] + _v["dist_out"]
+
+# Algorithmic HBM bytes per track of the solid-level queries: inputs read (3 or
+# 6 doubles) and outputs written (int8 code, doubles).
+SOLID_BYTES = {"inside": 24 + 1, "safety": 24 + 8, "dist_in": 48 + 8, "dist_out": 48 + 8, "fused": 48 + 25}
+
+
+def solid_roofline(solid: str, query: str, n: int, us_per_call: float, hbm_peak=PEAK_HBM, alu_peak=PEAK_FP64_OPS):
+    """Both fractions of one solid-level call and the roof that bounds it (the
+    larger of the two roofline times)."""
+    ops = SOLID_OPS[solid][query] * n
+    byt = SOLID_BYTES[query] * n
+    s = us_per_call * 1e-6
+    t_alu, t_hbm = ops / alu_peak, byt / hbm_peak
+    return {"bound": "alu" if t_alu > t_hbm else "hbm", "frac_alu": ops / s / alu_peak,
+            "frac_hbm": byt / s / hbm_peak, "frac": max(t_alu, t_hbm) / s, "ops_per_track": SOLID_OPS[solid][query],
+            "bytes_per_track": SOLID_BYTES[query]}

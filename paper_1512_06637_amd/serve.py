@@ -12,6 +12,11 @@ Offered load = a fraction of the engine's measured saturation rate (baskets/s);
 latency = device completion of the basket's round (HIP events mapped to the
 host clock) minus its arrival time on the host clock.
 
+The serial form it is compared with is the same engine held to one slot and
+one stream: every basket is its own round (copy in, one kernel, copy out) and
+the next starts only when it has been returned, i.e. per-basket calls one
+after another, with the same arrivals.
+
     python -m paper_1512_06637_amd.serve [--baskets 20000] [--loads 0.5 0.8 0.95]
 """
 from __future__ import annotations
@@ -119,39 +124,6 @@ def open_loop(srv, baskets, count, rate, seed):
             "p50_ms": _pct(lat_ms, 50), "p99_ms": _pct(lat_ms, 99), "max_ms": float(lat_ms.max())}
 
 
-def serial_open_loop(g, baskets, count, rate, seed):
-    """The same arrivals served one basket at a time: pinned host -> device
-    copies, the per-kind entry point, copy back, synchronize."""
-    import torch
-    rng = np.random.default_rng(seed)
-    arr = np.cumsum(rng.exponential(1.0 / rate, count))
-    t0 = now() + 0.01
-    arr = arr + t0
-    lat = []
-    for j in range(count):
-        while now() < arr[j]:
-            pass
-        kind, prec, n, _, tr, pv, ps = baskets[j % len(baskets)]
-        h = [torch.from_numpy(v).pin_memory() for v in tr.arrays()]
-        a = [v.to("cuda", non_blocking=True) for v in h]
-        p = torch.from_numpy(pv).pin_memory().to("cuda", non_blocking=True)
-        if kind == Q_STEP:
-            pst = None if ps is None else torch.from_numpy(ps).pin_memory().to("cuda", non_blocking=True)
-            fl = torch.empty(n, dtype=torch.int32, device="cuda")
-            s, nx = g.step(*a, p, pstep=pst, out_flags=fl, precision=prec)
-            res = [s.to("cpu", non_blocking=True), nx.to("cpu", non_blocking=True), fl.to("cpu", non_blocking=True)]
-        elif kind == Q_SAFETY:
-            res = [g.nav_safety(*a[:3], p, precision=prec).to("cpu", non_blocking=True)]
-        else:
-            res = [g.nav_inside(*a[:3], p).to("cpu", non_blocking=True)]
-        torch.cuda.synchronize()
-        del res
-        lat.append(now() - arr[j])
-    lat_ms = np.array(lat) * 1e3
-    return {"offered_baskets_per_s": rate, "p50_ms": _pct(lat_ms, 50), "p99_ms": _pct(lat_ms, 99),
-            "max_ms": float(lat_ms.max())}
-
-
 def run(g, loads=(0.5, 0.8, 0.95), precisions=(FP64, FP32_REFINE), n_baskets=20000, serial=True,
         slots=64, hbm_budget=256 << 20, nstreams=2, distinct=256):
     pool = state_pool(g)
@@ -166,13 +138,23 @@ def run(g, loads=(0.5, 0.8, 0.95), precisions=(FP64, FP32_REFINE), n_baskets=200
             for L in loads:
                 r = open_loop(srv, bk, n_baskets, L * sat["baskets_per_s"], seed=41)
                 r["load"] = L
-                if serial and prec == FP64:
-                    s = serial_open_loop(g, bk, min(n_baskets, 2000), L * sat["baskets_per_s"], seed=41)
-                    r["serial"] = s
                 pts.append(r)
             st = srv.stats()
-        res["points"].append({"precision": "fp64" if prec == FP64 else "fp32_refine", "saturation": sat,
-                              "loads": pts, "rounds": st["rounds"], "largest_round": st["max_round"]})
+        point = {"precision": "fp64" if prec == FP64 else "fp32_refine", "saturation": sat,
+                 "loads": pts, "rounds": st["rounds"], "largest_round": st["max_round"]}
+        if serial:
+            # the serial form: one basket per round, one round at a time
+            with Server(g, 1, hbm_budget, 1) as one:
+                saturation(one, bk, min(500, n_baskets))
+                ssat = saturation(one, bk, min(2000, n_baskets))
+                spts = []
+                for L in loads:
+                    r = open_loop(one, bk, min(n_baskets, 2000), L * sat["baskets_per_s"], seed=41)
+                    r["load"] = L
+                    spts.append(r)
+            point["serial"] = {"saturation": ssat, "loads": spts,
+                               "batching_speedup": sat["baskets_per_s"] / ssat["baskets_per_s"]}
+        res["points"].append(point)
     return res
 
 

@@ -1,0 +1,230 @@
+"""Autotuner of the library's launch shapes.
+
+The choices are the fields of gvgeom.h's gv_tuning: workgroup counts of the
+per-step basket kernel and of the regrouping kernels, the coarse direction
+cells of the regrouping key, the register budget of the navigation step
+kernel (waves per SIMD), and the block size and workgroup cap of the
+one-lane-per-track kernels (solid-level queries).  None of them changes a
+result; the tuner checks that on every candidate (bitwise-equal outputs) and
+keeps the fastest, per device architecture, in tuned.json beside this file.
+Geometry() applies the stored choice at load.
+
+Search: coordinate descent from the library's defaults.  Each knob is swept
+over its candidate values with the others held at the best found so far;
+every candidate is timed with HIP events over several calls (median of
+repeats), on the stream the library launches on.
+
+Run on a GPU:  python -m paper_1512_06637_amd.tune [--n 1048576] [--write]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(HERE, "tuned.json")
+
+# candidate values per knob (0 / -1 = the library default)
+TRANSPORT_SPACE = {
+    "step_grid": [0, 512, 768, 1024],
+    "scatter_grid": [0, 128, 512],
+    "cell_bits": [-1, 0, 4],
+    "step_waves": [0, 3],
+}
+LANE_SPACE = {
+    "solid_block": [0, 64, 128, 512],
+    "solid_grid": [0, 2048, 4096],
+}
+
+
+def arch() -> str:
+    """gfx name of the current device (e.g. 'gfx950')."""
+    import torch
+    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+    return str(getattr(p, "gcnArchName", "unknown")).split(":")[0]
+
+
+def load_cache(path: str = CACHE) -> dict:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def stored_choice(path: str = CACHE) -> dict | None:
+    """The stored launch shapes for this device's architecture, or None."""
+    c = load_cache(path)
+    try:
+        a = arch()
+    except Exception:
+        return None
+    e = c.get(a)
+    return dict(e["choice"]) if e and "choice" in e else None
+
+
+def _time_ms(fn, calls, repeats=3):
+    import torch
+    stream = torch.cuda.current_stream()
+    best = []
+    for _ in range(repeats):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(calls):
+            fn()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        best.append(ev0.elapsed_time(ev1) / calls)
+    best.sort()
+    return best[len(best) // 2]
+
+
+def _same(a: dict, b: dict) -> bool:
+    """Bitwise equality of two transports' outputs (steps compared as bits)."""
+    import torch
+    if not (torch.equal(a["nsteps"], b["nsteps"]) and torch.equal(a["flags"], b["flags"])):
+        return False
+    ns = a["nsteps"].long()
+    k = torch.arange(a["step"].shape[1], device=ns.device)[None, :]
+    m = k < ns[:, None]
+    mp = torch.cat([torch.ones_like(m[:, :1]), m], dim=1)
+    return bool(torch.equal(a["pv"][mp], b["pv"][mp])
+                and torch.equal(a["step"][m].view(torch.int64), b["step"][m].view(torch.int64)))
+
+
+def tune_transport(g, a, max_steps=128, calls=5, log=print):
+    """Coordinate descent over TRANSPORT_SPACE on nav_transport of tracks `a`
+    (six device arrays).  Returns (choice, table of timings)."""
+    import torch
+    n = a[0].shape[0]
+
+    def new_out():
+        return {"pv": torch.empty((n, max_steps + 1), dtype=torch.int32, device="cuda"),
+                "step": torch.empty((n, max_steps), dtype=torch.float64, device="cuda"),
+                "nsteps": torch.empty(n, dtype=torch.int32, device="cuda"),
+                "flags": torch.empty(n, dtype=torch.int32, device="cuda")}
+
+    g.set_tuning(**{k: v[0] for k, v in TRANSPORT_SPACE.items()})
+    ref = g.transport(*a, max_steps=max_steps, out=new_out())
+    torch.cuda.synchronize()
+    out = new_out()
+    best = {k: v[0] for k, v in TRANSPORT_SPACE.items()}
+    table = []
+
+    def run(cfg):
+        g.set_tuning(**cfg)
+        g.transport(*a, max_steps=max_steps, out=out)  # warm-up (and workspace re-size)
+        torch.cuda.synchronize()
+        if not _same(ref, out):
+            raise RuntimeError(f"launch shape {cfg} changed the transport's outputs")
+        return _time_ms(lambda: g.transport(*a, max_steps=max_steps, out=out), calls)
+
+    best_ms = run(best)
+    table.append({"cfg": dict(best), "ms": best_ms})
+    log(f"tune transport: default {best} {best_ms:.3f} ms")
+    for knob, vals in TRANSPORT_SPACE.items():
+        for v in vals[1:] if best[knob] == vals[0] else vals:
+            if v == best[knob]:
+                continue
+            cfg = dict(best, **{knob: v})
+            ms = run(cfg)
+            table.append({"cfg": cfg, "ms": ms})
+            log(f"tune transport: {knob}={v} {ms:.3f} ms")
+            if ms < best_ms * 0.995:  # keep a change only for a measurable gain
+                best, best_ms = cfg, ms
+    g.set_tuning(**best)
+    return best, best_ms, table
+
+
+def tune_lanes(g, lv, a, calls=20, log=print):
+    """Coordinate descent over LANE_SPACE on the fused solid query of solid
+    `lv` for tracks `a`.  Returns (choice, ms, table)."""
+    import torch
+    n = a[0].shape[0]
+
+    def outs():
+        return [torch.empty(n, dtype=torch.int8, device="cuda")] + \
+            [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(3)]
+
+    g.set_tuning(**{k: v[0] for k, v in LANE_SPACE.items()})
+    ref = outs()
+    g.solid_all(lv, *a, *ref)
+    o = outs()
+    best = {k: v[0] for k, v in LANE_SPACE.items()}
+    table = []
+
+    def run(cfg):
+        g.set_tuning(**cfg)
+        g.solid_all(lv, *a, *o)
+        torch.cuda.synchronize()
+        for r, x in zip(ref, o):
+            if not torch.equal(r.view(torch.uint8), x.view(torch.uint8)):
+                raise RuntimeError(f"launch shape {cfg} changed the solid query's outputs")
+        return _time_ms(lambda: g.solid_all(lv, *a, *o), calls)
+
+    best_ms = run(best)
+    table.append({"cfg": dict(best), "ms": best_ms})
+    for knob, vals in LANE_SPACE.items():
+        for v in vals:
+            if v == best[knob]:
+                continue
+            cfg = dict(best, **{knob: v})
+            ms = run(cfg)
+            table.append({"cfg": cfg, "ms": ms})
+            log(f"tune lanes: {knob}={v} {ms * 1e3:.1f} us")
+            if ms < best_ms * 0.995:
+                best, best_ms = cfg, ms
+    g.set_tuning(**best)
+    return best, best_ms, table
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--write", action="store_true", help="store the choice in tuned.json")
+    ap.add_argument("--out", default=CACHE)
+    args = ap.parse_args()
+
+    import torch
+
+    import paper_1512_06637_amd as G
+    from paper_1512_06637_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    log = lambda *m: print(*m, flush=True)  # noqa: E731
+    t0 = time.time()
+    g = G.Geometry(W.detector_blob(), tuned=False)
+    tr = W.config3_tracks(args.n)
+    a = [torch.from_numpy(v).to("cuda") for v in tr.arrays()]
+    tchoice, tms, ttable = tune_transport(g, a, log=log)
+    g.close()
+    del a
+    sol = W.config_solids()
+    name = "pcon"
+    gs = G.Geometry(W.multi_solid_blob([sol[name]]), tuned=False)
+    t = W.config2_tracks(name)
+    a = [torch.from_numpy(v).to("cuda") for v in t.arrays()]
+    lchoice, lms, ltable = tune_lanes(gs, 0, a, log=log)
+    gs.close()
+    choice = dict(tchoice, **lchoice)
+    entry = {"choice": choice,
+             "transport": {"workload": f"layered detector, {args.n} origin tracks, FP64", "ms": tms,
+                           "table": ttable},
+             "lanes": {"workload": f"{name} fused query, 2^20 mixed-thirds tracks", "ms": lms, "table": ltable},
+             "seconds": time.time() - t0}
+    a_ = arch()
+    log(json.dumps({a_: {"choice": choice, "transport_ms": tms, "lanes_us": lms * 1e3}}))
+    if args.write:
+        c = load_cache(args.out)
+        c[a_] = entry
+        os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+        with open(args.out, "w") as f:
+            json.dump(c, f, indent=1, sort_keys=True)
+        log(f"wrote {args.out}")
+
+
+if __name__ == "__main__":
+    main()

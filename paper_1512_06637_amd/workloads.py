@@ -412,6 +412,65 @@ def bundle_description():
     return lvs
 
 
+# Constructed exact ties of ComputeStep (the paper fixes no tie-break; the
+# readings are: among daughters entered at the same distance the lowest
+# placement index wins, and a daughter entered exactly where the mother is
+# left wins over the exit).  Each case: (LV list, start point, unit direction,
+# index of the daughter that must be entered, step length).  Overlapping or
+# protruding daughters are what makes a tie exact; the arithmetic of every
+# case is exact in FP64 (axis-aligned slabs at integer coordinates, or two
+# daughters with identical placements and parameters).
+def tie_cases() -> dict:
+    cases = {}
+    a, b = box(10.0, 10.0, 10.0), box(5.0, 20.0, 20.0)  # entered at x = 40 from the origin
+    e = np.eye(3)
+    ray = (np.array([0.0, 3.0, -2.0]), np.array([1.0, 0.0, 0.0]))
+    # two daughters entered at the same distance: plain loop (2 daughters)
+    lvs = [LV(box(100.0, 100.0, 100.0), [(1, e, [50.0, 0.0, 0.0]), (2, e, [45.0, 0.0, 0.0])]), LV(a), LV(b)]
+    cases["daughters_plain"] = (lvs, *ray, 0, 40.0)
+    lvs = [LV(box(100.0, 100.0, 100.0), [(2, e, [45.0, 0.0, 0.0]), (1, e, [50.0, 0.0, 0.0])]), LV(a), LV(b)]
+    cases["daughters_plain_swapped"] = (lvs, *ray, 0, 40.0)
+    # the same among 10 box daughters (culled loop with its box screen and
+    # SafetyToIn bound): the tied pair at indices 3 and 7
+    small = box(2.0, 2.0, 2.0)
+    pl = [(3, e, np.array([-80.0 + 18.0 * k, -80.0, 0.0])) for k in range(10)]
+    pl[3] = (1, e, np.array([50.0, 0.0, 0.0]))
+    pl[7] = (2, e, np.array([45.0, 0.0, 0.0]))
+    lvs = [LV(box(100.0, 100.0, 100.0), pl), LV(box(10.0, 10.0, 10.0)), LV(box(10.0, 10.0, 10.0)), LV(small)]
+    # both tied daughters are the same size here: b's slab also starts at 40
+    lvs[2] = LV(box(5.0, 10.0, 10.0))
+    cases["daughters_culled"] = (lvs, *ray, 3, 40.0)
+    # phi sectors: 8 boxes on a ring around the z axis inside a holder, the
+    # box at index 2 placed again at index 6 (identical placement); the ray
+    # runs radially towards it, off the axis by 3 mm
+    ring = []
+    for k in range(8):
+        phi = TWO_PI * k / 8 + 0.1
+        ring.append((2, rot_z(phi), np.array([60.0 * math.cos(phi), 60.0 * math.sin(phi), 0.0])))
+    ring[6] = ring[2]
+    lvs = [LV(box(200.0, 200.0, 200.0), [(1, e, np.zeros(3))]), LV(box(100.0, 100.0, 50.0), ring),
+           LV(box(6.0, 9.0, 40.0))]
+    phi2 = TWO_PI * 2 / 8 + 0.1
+    u = np.array([math.cos(phi2), math.sin(phi2), 0.0])
+    v = np.array([-math.sin(phi2), math.cos(phi2), 0.0])
+    cases["daughters_phi"] = (lvs, 20.0 * u + 3.0 * v, u, 2, None)
+    # a daughter entered exactly where the mother is left (it protrudes
+    # through the mother's face x = 100): the daughter wins
+    lvs = [LV(box(100.0, 100.0, 100.0), [(1, e, [110.0, 0.0, 0.0])]), LV(a)]
+    cases["exit_plain"] = (lvs, *ray, 0, 100.0)
+    pl = [(2, e, np.array([-80.0 + 18.0 * k, -80.0, 0.0])) for k in range(10)]
+    pl[5] = (1, e, np.array([110.0, 0.0, 0.0]))
+    lvs = [LV(box(100.0, 100.0, 100.0), pl), LV(a), LV(small)]
+    cases["exit_culled"] = (lvs, *ray, 5, 100.0)
+    return cases
+
+
+def tie_tracks(case, n: int = 1) -> Tracks:
+    """n copies of a tie case's ray."""
+    _, p, d, _, _ = case
+    return Tracks(*[np.full(n, float(v)) for v in (*p, *d)])
+
+
 def uniform_world_tracks(half, n: int, seed: int, centre=(0.0, 0.0, 0.0)) -> Tracks:
     """Starts uniform in the box centre +- half (mm), isotropic directions; one
     track in eight is parallel to the z axis."""

@@ -18,3 +18,17 @@ def _oracle_built():
     from oracle import build as ob
     ob.build()
     yield
+
+
+def pytest_terminal_summary(terminalreporter, exitstatus, config):
+    """Tracks the oracle flags as ill-conditioned are excluded from the parity
+    counts; list them (always, not only with -s)."""
+    try:
+        from tests.gpu_util import FLAGGED
+    except Exception:
+        return
+    if not FLAGGED:
+        return
+    terminalreporter.section("oracle-flagged tracks (listed, not counted)")
+    for what, n, first in FLAGGED:
+        terminalreporter.write_line(f"{what}: {n} tracks, first ids {first}")

@@ -94,7 +94,7 @@ def test_composite_fused_matches_oracle(geo):
     for k, d in ((2, 0), (3, 1)):
         ref, diag = O.distance(s, d, t)
         ref = np.where(code == (O.INSIDE if d == 0 else O.OUTSIDE), -1.0, ref)
-        _, _, bad = compare_values(host(o[k]), ref, diag, what=f"fused dist {d}", solid=s, tracks=t)
+        _, _, bad = compare_values(host(o[k]), ref, diag, what=f"fused dist {d}")
         assert bad.size == 0
 
 

@@ -121,12 +121,12 @@ def test_transport_fp32_full_size(geos):
     t = W.config3_tracks()
     say(f"[transport fp32] n={t.n}")
     a = [cuda(v) for v in t.arrays()]
-    g.profile(True)
+    g.profile(work=True)
     got32 = g.transport(*a, precision=G.FP32_REFINE)
     _, _, w32 = g.profile_read()
     got64 = g.transport(*a, precision=G.FP64)
     _, _, w64 = g.profile_read()
-    g.profile(False)
+    g.profile()
     _same_transport(got32, got64)
     idx = np.sort(np.random.default_rng(15).choice(t.n, 2000, replace=False))
     compare_transport(got32, og.transport(t.take(idx)), idx)

@@ -55,10 +55,10 @@ def test_index_transport(case, n):
     ref = og.transport(t)
     a = [cuda(v) for v in t.arrays()]
     for prec in (G.FP64, G.FP32_REFINE):
-        g.profile(True)
+        g.profile(work=True)
         got = g.transport(*a, precision=prec)
         _, _, w = g.profile_read()
-        g.profile(False)
+        g.profile()
         assert compare_transport(got, ref) > 0.99 * n
         if n > 8192:  # basket path: counters of the step kernel
             say(f"  counters: radial {w[24]} lookups / {w[25]} bounds, phi {w[26]} lookups / {w[27]} sectors, "

@@ -88,12 +88,12 @@ def test_phys_transport_full_size(geos):
     t = W.config3_tracks()
     say(f"[phys transport] n={t.n}")
     a = [cuda(v) for v in t.arrays()]
-    g.profile(True)
+    g.profile(work=True)
     got = g.transport_phys(*a, SEED, max_steps=MAX_STEPS, shortcut=True)
     _, _, w = g.profile_read()
     plain = g.transport_phys(*a, SEED, max_steps=MAX_STEPS, shortcut=False)
     _, _, w0 = g.profile_read()
-    g.profile(False)
+    g.profile()
     _same(got, plain)
     idx = np.sort(np.random.default_rng(17).choice(t.n, 2000, replace=False))
     compare_phys(got, og.transport_phys(t.take(idx), MAT, SEED, max_steps=MAX_STEPS, track_id=idx), idx)

@@ -2,8 +2,9 @@
 basket_distance / basket_solid_all) against the CPU oracle, element by element.
 
 Bar: Inside codes bit-exact; FP64 distances and safeties within 1e-12 relative
-(1 mm floor) with exact sentinels; tracks the oracle marks ill-conditioned are
-listed and excused."""
+(1 mm floor) with exact sentinels; tracks the oracle marks ill-conditioned
+(including hits whose FP64 conditioning exceeds the bar) are listed in the
+session summary and not counted."""
 import math
 
 import numpy as np
@@ -76,7 +77,7 @@ def check(name, s, t, res, idx=None):
     nflag = 0
     for key, d in (("din", 0), ("dout", 1)):
         ref, diag = O.distance(s, d, tt)
-        _, flagged, bad = compare_values(sel(res[key]), ref, diag, what=f"{name} {key}", solid=s, tracks=tt)
+        _, flagged, bad = compare_values(sel(res[key]), ref, diag, what=f"{name} {key}")
         nbad += bad.size
         nflag += flagged.size
         if flagged.size:
@@ -103,14 +104,14 @@ def test_solid_parity_paper_workload(geo, name):
 
 
 @pytest.mark.parametrize("name", list(W.CONFIG2_SOLIDS))
-def test_solid_parity_full_size_sampled(geo, name):
-    """2^20 tracks of the full-solid-set workload in one launch; a seeded sample
-    of 20,000 outputs is recomputed by the oracle."""
-    say(f"[solid parity, 2^20 sampled] {name}")
+def test_solid_parity_full_size(geo, name):
+    """All 2^20 tracks of the full-solid-set workload, in the launch shape the
+    benchmark times, against the oracle element by element (every query)."""
+    say(f"[solid parity, 2^20 full] {name}")
     t = W.config2_tracks(name)
     res = run_all(geo, NAMES.index(name), t)
-    idx = np.sort(np.random.default_rng(5).choice(t.n, 20000, replace=False))
-    check(name, SOLIDS[name], t, res, idx)
+    nflag = check(name, SOLIDS[name], t, res)
+    say(f"  {name}: {t.n} tracks compared, {nflag} flagged values differ (listed)")
 
 
 @pytest.mark.parametrize("name", NAMES)

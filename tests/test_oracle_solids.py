@@ -412,3 +412,38 @@ def test_rejects_invalid_parameters():
     assert not O.solid_ok(W.tubs(10.0, 5.0, 1.0))
     assert not O.solid_ok(W.pcon([0.0, 0.0], [0.0, 0.0], [1.0, 1.0]))
     assert not O.solid_ok(W.sphere(5.0, 5.0))
+
+
+def test_hit_conditioning_flag_closed_form():
+    """The oracle's conditioning flag of a solid-level hit (D_COND) against the
+    closed form of a sphere: a ray from (0, b, -z0) along +z meets the outer
+    sphere R at t = z0 - sqrt(R^2 - b^2) with cos(theta) = sqrt(1 - (b/R)^2) to
+    the normal, q = (0, b, -sqrt(R^2 - b^2)), L = (|p|^2 + R^2) / R; flagged
+    exactly when 16 eps L / cos(theta) > 1e-12 max(t, 1 mm).  Impact
+    parameters well inside and well outside the threshold, plus a box hit at
+    normal incidence (never flagged) and a near-parallel box hit (flagged)."""
+    R, z0 = 30.0, 80.0
+    s = W.sphere(0.0, R)
+    eps = 2.0 ** -52
+    bs = np.array([0.0, 10.0, 20.0, 29.0, 29.99, 30.0 * (1 - 1e-6), 30.0 * (1 - 1e-9)])
+    for b in bs:
+        t = W.Tracks(np.array([0.0]), np.array([b]), np.array([-z0]), np.array([0.0]), np.array([0.0]),
+                     np.array([1.0]))
+        dist, diag = O.distance(s, 0, t)
+        assert np.isfinite(dist[0])
+        c = math.sqrt(max(0.0, 1.0 - (b / R) ** 2))
+        tt = z0 - math.sqrt(R * R - b * b)
+        L = (b * b + z0 * z0 + R * R) / R
+        expect = 16 * eps * L > 1e-12 * max(tt, 1.0) * c
+        margin = abs(16 * eps * L - 1e-12 * max(tt, 1.0) * c) / (16 * eps * L)
+        if margin > 0.05:  # not at the threshold itself
+            assert bool(diag[0] & O.D_COND) == expect, (b, diag[0], expect)
+    # a box face met head-on is never flagged; the top face met 1e-6 rad from
+    # parallel (5 mm along the ray, inside the face) is
+    bx = W.box(10.0, 20.0, 30.0)
+    a = 1e-6
+    t = W.Tracks(np.array([-50.0, -9.0]), np.array([0.0, 0.0]), np.array([0.0, 30.0 + 5.0 * math.sin(a)]),
+                 np.array([1.0, math.cos(a)]), np.array([0.0, 0.0]), np.array([0.0, -math.sin(a)]))
+    d, diag = O.distance(bx, 0, t)
+    assert not diag[0] & O.D_COND and d[0] == 40.0
+    assert abs(d[1] - 5.0) < 1e-6 and diag[1] & O.D_COND

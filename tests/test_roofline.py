@@ -49,6 +49,6 @@ def test_counts_are_linear_and_culling_is_cheaper():
 
 
 def test_byte_figures():
-    assert R.STEP_BYTES == 152
+    assert R.STEP_DESIGN_BYTES == 152
     # 2 tracks, 5 steps: 2 x (48 in + start PV + nsteps + flags) + 5 x (PV + step)
     assert R.transport_bytes(2, 5) == 2 * 60 + 5 * 12
