@@ -25,7 +25,10 @@ OUTSIDE, SURFACE, INSIDE = 0, 1, 2
 F_OVERFLOW, F_STUCK, F_LOCATE_FAIL = 1, 2, 4
 D_NEAR_TIE, D_GRAZE, D_ZERO_STEP, D_BAND_EDGE, D_NO_EXIT = 16, 32, 64, 128, 256
 D_COND = 512  # solid-level hit whose FP64 conditioning exceeds the 1e-12 bar (or_hit_cond)
-D_ILL = D_NEAR_TIE | D_GRAZE | D_ZERO_STEP | D_BAND_EDGE | D_NO_EXIT | D_COND
+# decisions two correct FP64 codes may take differently (the oracle's own pins
+# exclude only these; D_COND hits still meet the closed forms there)
+D_DECIDE = D_NEAR_TIE | D_GRAZE | D_ZERO_STEP | D_BAND_EDGE | D_NO_EXIT
+D_ILL = D_DECIDE | D_COND
 
 _P = C.c_void_p
 _I64 = C.c_int64

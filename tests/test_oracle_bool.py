@@ -37,7 +37,7 @@ def box_tracks(s, n, seed):
 
 
 def clean(diag):
-    return (diag & O.D_ILL) == 0
+    return (diag & O.D_DECIDE) == 0
 
 
 # ------------------------------------------------------------------ parameters

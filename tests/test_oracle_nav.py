@@ -103,7 +103,7 @@ def test_steps_midpoints_endpoints_and_closure(geo):
     t = W.config3_tracks(256)
     r = geo.transport(t)
     assert np.all(r["flags"] == 0)
-    ok = (r["diag"] & O.D_ILL) == 0
+    ok = (r["diag"] & O.D_DECIDE) == 0
     assert ok.mean() > 0.99
     world = LVS[0].solid
     dist_world, _ = O.distance(world, 1, t)

@@ -50,8 +50,8 @@ def test_box_matches_slab_closed_form():
     ins = code == O.INSIDE
     ref_in = pins.slab_box(s.params, P[:, out], D[:, out], True)
     ref_out = pins.slab_box(s.params, P[:, ins], D[:, ins], False)
-    ok_i = (dgi[out] & O.D_ILL) == 0
-    ok_o = (dgo[ins] & O.D_ILL) == 0
+    ok_i = (dgi[out] & O.D_DECIDE) == 0
+    ok_o = (dgo[ins] & O.D_DECIDE) == 0
     assert ok_i.mean() > 0.999 and ok_o.mean() > 0.999
     a, b = din[out][ok_i], ref_in[ok_i]
     assert np.array_equal(np.isinf(a), np.isinf(b))
@@ -107,10 +107,10 @@ def test_sphere_shell_matches_50_digit_closed_form():
     for i in range(t.n):
         p = (t.x[i], t.y[i], t.z[i])
         d = (t.dx[i], t.dy[i], t.dz[i])
-        if code[i] == O.OUTSIDE and not (dgi[i] & O.D_ILL):
+        if code[i] == O.OUTSIDE and not (dgi[i] & O.D_DECIDE):
             ref, cond = _sphere_ref(10.0, 30.0, p, d, True)
             got = din[i]
-        elif code[i] == O.INSIDE and not (dgo[i] & O.D_ILL):
+        elif code[i] == O.INSIDE and not (dgo[i] & O.D_DECIDE):
             ref, cond = _sphere_ref(10.0, 30.0, p, d, False)
             got = dout[i]
         else:
@@ -156,8 +156,8 @@ def test_full_cylinder_matches_closed_form():
     tout = np.minimum(chi, zhi)
     ref_in = np.where((tout > tin) & (tout > 0), np.maximum(tin, 0.0), np.inf)
     ref_out = np.maximum(tout, 0.0)
-    o = (code == O.OUTSIDE) & ((dgi & O.D_ILL) == 0)
-    i = (code == O.INSIDE) & ((dgo & O.D_ILL) == 0)
+    o = (code == O.OUTSIDE) & ((dgi & O.D_DECIDE) == 0)
+    i = (code == O.INSIDE) & ((dgo & O.D_DECIDE) == 0)
     assert o.sum() > 10000 and i.sum() > 1000
     assert np.array_equal(np.isinf(din[o]), np.isinf(ref_in[o]))
     f = o & np.isfinite(ref_in)
@@ -190,7 +190,7 @@ def test_reduction_identities(name, a, b):
     for direction in (0, 1):
         da, ga = O.distance(a, direction, t)
         db, gb = O.distance(b, direction, t)
-        ok = same & (((ga | gb) & O.D_ILL) == 0)
+        ok = same & (((ga | gb) & O.D_DECIDE) == 0)
         assert np.array_equal(np.isinf(da[ok]), np.isinf(db[ok]))
         f = ok & np.isfinite(db)
         assert np.all(np.abs(da[f] - db[f]) <= 1e-12 * np.maximum(1.0, np.abs(db[f]))), name
@@ -242,13 +242,13 @@ def test_distances_match_ray_marching(name):
     mi = _march(s, t, O.INSIDE)
     mo = _march(s, t, O.OUTSIDE)
     for i in range(t.n):
-        if code[i] == O.OUTSIDE and not (dgi[i] & O.D_ILL):
+        if code[i] == O.OUTSIDE and not (dgi[i] & O.D_DECIDE):
             if math.isinf(mi[i]):
                 assert math.isinf(din[i]), (name, i, din[i])
             else:
                 # the marcher lands within the surface band: |error| < band / |cos|
                 assert abs(din[i] - mi[i]) < 2e-6, (name, i, din[i], mi[i])
-        if code[i] == O.INSIDE and not (dgo[i] & O.D_ILL):
+        if code[i] == O.INSIDE and not (dgo[i] & O.D_DECIDE):
             assert abs(dout[i] - mo[i]) < 2e-6, (name, i, dout[i], mo[i])
 
 
@@ -260,7 +260,7 @@ def test_surface_landing(name):
         code = O.inside(s, t.x, t.y, t.z)
         for direction, side in ((0, O.OUTSIDE), (1, O.INSIDE)):
             dist, dg = O.distance(s, direction, t)
-            m = (code == side) & np.isfinite(dist) & ((dg & O.D_ILL) == 0)
+            m = (code == side) & np.isfinite(dist) & ((dg & O.D_DECIDE) == 0)
             assert m.sum() > 200
             q = [a[m] + dist[m] * b[m] for a, b in ((t.x, t.dx), (t.y, t.dy), (t.z, t.dz))]
             qc = O.inside(s, *q)
