@@ -250,13 +250,21 @@ int gv_probe_stream(const double* a, const double* b, double* c, double s, int64
 int gv_probe_fma64(double* out, int64_t n_lanes, int32_t iters, void* stream);
 
 /* ---------------------------------------------------------- launch shapes */
-/* How the library's kernels are launched on this geometry.  These choose
- * workgroup counts and sizes, the coarse direction cells of the basket
- * regrouping and the register budget of the per-step kernel; none of them
- * changes any result (every track's arithmetic is the same), only speed.  An
- * autotuner measures them per device architecture (the Python package's
- * tune module) and the binding applies the stored choice at load.
- * Fields (0 = the default; cell_bits -1 = the default):
+/* How the library's kernels are launched on this geometry.  These choose the
+ * form of the transport, workgroup counts and sizes, the coarse direction
+ * cells of the orderings and the register budget of the per-step kernel; none
+ * of them changes any result (every track's arithmetic is the same), only
+ * speed.  An autotuner measures them per device architecture (the Python
+ * package's tune module) and the binding applies the stored choice at load.
+ *
+ * The transports have two forms.  The lane form (default) orders the tracks
+ * once by a direction key (counting sort into 2^sort_bits x 2^sort_bits cells
+ * of the octahedral direction map, cells in Morton order), then one
+ * persistent kernel carries each track in one lane from its start to its end,
+ * wavefronts taking 64 places of the order at a time from an atomic counter.
+ * The basket form (Sec. II.A baskets of tracks in the same volume) regroups
+ * the live tracks by (logical volume, direction cell) before every step.
+ * Fields (0 = the default; cell_bits and sort_bits -1 = the default):
  *   step_grid     workgroups of the per-step basket kernel, 1..1024
  *                 (default one per four tiles of 64 tracks, at most 1024);
  *   scatter_grid  workgroups of the regrouping kernels, 1..1024
@@ -271,11 +279,22 @@ int gv_probe_fma64(double* out, int64_t n_lanes, int32_t iters, void* stream);
  *                 then loops over several tracks), >= 1 (default: one lane
  *                 per track);
  *   step_waves    3 or 4: waves per SIMD the navigation step kernel is built
- *                 for (default 4).
+ *                 for (default 4);
+ *   transport     1 basket form, 2 lane form (default: lane; the basket form
+ *                 needs n >= 8,192, smaller batches take the lane form);
+ *   sort_bits     0..7: the lane form's direction cells are 2^sort_bits x
+ *                 2^sort_bits (0: no ordering, tracks in index order;
+ *                 default 6);
+ *   lane_refill   1 off, 2 on: a lane whose track has ended takes the next
+ *                 track at once instead of waiting for its wavefront's
+ *                 other tracks (default off);
+ *   lane_grid     workgroups (256 threads) of the persistent lane kernel,
+ *                 >= 0 (default: as many as the device holds at once).
  * A change of cell_bits re-sizes the transport workspace at the next
  * transport.  GV_EINVAL for a field out of range (nothing changed). */
 typedef struct {
   int32_t step_grid, scatter_grid, cell_bits, solid_block, solid_grid, step_waves;
+  int32_t transport, sort_bits, lane_refill, lane_grid;
 } gv_tuning;
 int gv_set_tuning(gv_geom* g, const gv_tuning* t);
 int gv_get_tuning(const gv_geom* g, gv_tuning* t);

@@ -23,7 +23,8 @@ SAFETY_AUTO, SAFETY_IN, SAFETY_OUT = 0, 1, 2
 FP64, FP32_REFINE = 0, 1
 WORK_N = 28  # work counters returned by gv_profile_read
 PROF_EVENTS, PROF_WORK = 1, 2
-TUNING_FIELDS = ("step_grid", "scatter_grid", "cell_bits", "solid_block", "solid_grid", "step_waves")
+TUNING_FIELDS = ("step_grid", "scatter_grid", "cell_bits", "solid_block", "solid_grid", "step_waves",
+                 "transport", "sort_bits", "lane_refill", "lane_grid")
 
 
 class _Tuning(C.Structure):

@@ -16,6 +16,7 @@
 
 #include "../../include/gvgeom.h"
 #include "gv_baskets.h"
+#include "gv_lane.h"
 #include "gv_probe.h"
 
 using namespace gv;
@@ -68,7 +69,15 @@ struct gv_geom {
   bool prof = false;
   bool prof_work = false;
   // launch shapes (gv_set_tuning); zero / negative fields take the defaults
-  gv_tuning tune{0, 0, -1, 0, 0, 0};
+  gv_tuning tune{0, 0, -1, 0, 0, 0, 0, -1, 0, 0};
+  // lane-transport workspace (grown on demand): direction keys, the coherent
+  // order, key counts and the work counter
+  void* lws = nullptr;
+  int64_t lws_cap = 0;
+  LaneCtl lctl{};
+  int n_cu = 0;  // compute units of the device
+  std::pair<const void*, int> occ[16] = {};  // resident workgroups per CU of persistent kernels
+  int n_occ = 0;
   int ws_nl = 0;  // buckets the workspace was sized for
   std::vector<hipEvent_t> prof_ev;  // pairs around step-kernel launches
   size_t prof_used = 0;
@@ -658,6 +667,8 @@ extern "C" int geom_load(const void* blob, size_t nbytes, gv_geom** out) {
       delete g;
       return hip_fail(e, "geom_load: hipGetDevice");
     }
+    e = hipDeviceGetAttribute(&g->n_cu, hipDeviceAttributeMultiprocessorCount, g->device);
+    if (e != hipSuccess || g->n_cu < 1) g->n_cu = 256;
     e = hipMalloc(&g->dmem, total);
     if (e != hipSuccess) {
       delete g;
@@ -726,6 +737,7 @@ extern "C" int geom_free(gv_geom* g) {
   if (dev != g->device) (void)hipSetDevice(g->device);
   hipError_t e = hipDeviceSynchronize();
   if (g->ws) (void)hipFree(g->ws);
+  if (g->lws) (void)hipFree(g->lws);
   if (g->ob) (void)hipFree(g->ob);
   if (g->mat_mem) (void)hipFree(g->mat_mem);
   if (g->dmem) (void)hipFree(g->dmem);
@@ -1147,7 +1159,7 @@ StepKernel select_step_kernel(const gv_geom* g, bool fp32, bool phys) {
   return fp32 ? k_bt_step<true, false, false, false, 4> : k_bt_step<false, false, false, false, 4>;
 }
 
-constexpr int64_t kBasketMin = 8192;  // smaller batches use one lane per track
+constexpr int64_t kBasketMin = 8192;  // the basket form needs at least this many tracks
 
 unsigned stream_grid(int64_t n) {
   int64_t b = (n + kBlock - 1) / kBlock;
@@ -1240,20 +1252,146 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
   return GV_OK;
 }
 
+// ------------------------------------------------------- lane transport
+constexpr int kLaneSortBits = 6;  // default direction cells of the order: 64 x 64
+
+// Direction-key bits of the coherent order: the tuned sort_bits, else the
+// default; 0 runs the tracks in index order.
+int sort_bits(const gv_geom* g) { return g->tune.sort_bits >= 0 ? g->tune.sort_bits : kLaneSortBits; }
+
+size_t lane_ws_bytes(int64_t cap) {
+  return 2 * al256(4 * (size_t)cap) + al256(4 * (size_t)kSortMaxCells) + al256(4);
+}
+
+LaneCtl carve_lane_ctl(void* mem, int64_t cap) {
+  char* p = (char*)mem;
+  LaneCtl L;
+  L.key = (uint32_t*)p;
+  p += al256(4 * (size_t)cap);
+  L.perm = (int32_t*)p;
+  p += al256(4 * (size_t)cap);
+  L.cnt = (uint32_t*)p;
+  p += al256(4 * (size_t)kSortMaxCells);
+  L.queue = (uint32_t*)p;
+  return L;
+}
+
+// Keys, order and counters for `n` tracks, allocated with hipMalloc on first
+// use and grown on demand (no clearing needed: every transport clears the
+// counters with a kernel and writes the keys and the order before reading).
+int ensure_lane_workspace(gv_geom* g, int64_t n) {
+  if (g->lws && g->lws_cap >= n) return GV_OK;
+  const int64_t cap = std::max<int64_t>(n, std::max<int64_t>(4096, g->lws_cap));
+  if (g->lws) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(g->lws);
+    g->lws = nullptr;
+    g->lws_cap = 0;
+  }
+  void* mem = nullptr;
+  hipError_t e = hipMalloc(&mem, lane_ws_bytes(cap));
+  if (e != hipSuccess)
+    return fail(GV_ENOMEM, "nav_transport: workspace hipMalloc(%zu): %s", lane_ws_bytes(cap), hipGetErrorString(e));
+  g->lctl = carve_lane_ctl(mem, cap);
+  g->lws = mem;
+  g->lws_cap = cap;
+  return GV_OK;
+}
+
+using LaneKernel = void (*)(DevGeom, int64_t, const double*, const double*, const double*, const double*,
+                            const double*, const double*, const int32_t*, const int32_t*, uint32_t*, int, int32_t*,
+                            double*, int32_t*, uint32_t*, PhysArgs, int8_t*);
+
+// The lane-transport instance: composites or not, FP32 screens or not,
+// physics-limited or not, refill or not (geometries without composites).
+LaneKernel select_lane_kernel(bool has_bool, bool fp32, bool phys, bool refill) {
+  if (has_bool)
+    return fp32 ? (phys ? k_lane_transport<true, true, true, false> : k_lane_transport<true, false, true, false>)
+                : (phys ? k_lane_transport<false, true, true, false> : k_lane_transport<false, false, true, false>);
+  if (refill)
+    return fp32 ? (phys ? k_lane_transport<true, true, false, true> : k_lane_transport<true, false, false, true>)
+                : (phys ? k_lane_transport<false, true, false, true> : k_lane_transport<false, false, false, true>);
+  return fp32 ? (phys ? k_lane_transport<true, true, false, false> : k_lane_transport<true, false, false, false>)
+              : (phys ? k_lane_transport<false, true, false, false> : k_lane_transport<false, false, false, false>);
+}
+
+// Workgroups of 256 threads a CU holds at once for kernel k (cached per
+// kernel in a fixed table: nothing is allocated here).
+int resident_blocks(gv_geom* g, const void* k) {
+  for (int i = 0; i < g->n_occ; ++i)
+    if (g->occ[i].first == k) return g->occ[i].second;
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 256, 0) != hipSuccess || nb < 1) {
+    (void)hipGetLastError();
+    nb = 1;
+  }
+  if (g->n_occ < (int)(sizeof g->occ / sizeof g->occ[0])) g->occ[g->n_occ++] = {k, nb};
+  return nb;
+}
+
+// Enqueues a lane transport: order the tracks by direction key (unless sort
+// bits are 0), then one persistent launch that carries every track to its end.
+// L holds the keys, order and counters for at least n tracks.
+int lane_transport(gv_geom* g, const LaneCtl& L, int64_t n, const double* x, const double* y, const double* z,
+                   const double* dx, const double* dy, const double* dz, const int32_t* start_pv, int max_steps,
+                   int32_t* out_pv, double* out_step, int32_t* out_nsteps, uint32_t* out_flags, bool fp32,
+                   bool phys, PhysArgs P, int8_t* out_proc, hipStream_t s, const char* fn, bool events) {
+  const int h = std::min(sort_bits(g), kSortMaxBits);
+  const bool sorted = h > 0;
+  const int cells = sorted ? 1 << (2 * h) : 0;
+  hipLaunchKernelGGL(k_ls_clear, dim3((unsigned)std::max(1, (cells + 255) / 256)), dim3(256), 0, s, L, cells);
+  GV_TRY(launched(fn));
+  if (sorted) {
+    const unsigned cg = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 4095) / 4096, 256));
+    hipLaunchKernelGGL(k_ls_count, dim3(cg), dim3(1024), 4 * (size_t)cells, s, n, dx, dy, dz, h, L);
+    GV_TRY(launched(fn));
+    hipLaunchKernelGGL(k_ls_scan, dim3(1), dim3(1024), 0, s, L, cells);
+    GV_TRY(launched(fn));
+    hipLaunchKernelGGL(k_ls_scatter, dim3(stream_grid(n)), dim3(kBlock), 0, s, n, L);
+    GV_TRY(launched(fn));
+  }
+  const bool refill = g->tune.lane_refill == 2;
+  const LaneKernel k = select_lane_kernel(g->has_bool, fp32, phys, refill);
+  int64_t grid = g->tune.lane_grid > 0 ? g->tune.lane_grid
+                                       : (int64_t)resident_blocks(g, reinterpret_cast<const void*>(k)) * g->n_cu;
+  grid = std::max<int64_t>(1, std::min<int64_t>(grid, (n + 255) / 256));
+  hipEvent_t* pe = nullptr;
+  if (events) {
+    if (g->prof_used + 2 > g->prof_ev.size()) {
+      hipEvent_t e0, e1;
+      if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(GV_EHIP, "%s: hipEventCreate for profiling", fn);
+      g->prof_ev.push_back(e0);
+      g->prof_ev.push_back(e1);
+    }
+    pe = &g->prof_ev[g->prof_used];
+    g->prof_used += 2;
+    (void)hipEventRecord(pe[0], s);
+  }
+  hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(256), 0, s, g->dg, n, x, y, z, dx, dy, dz, start_pv,
+                     sorted ? (const int32_t*)L.perm : (const int32_t*)nullptr, L.queue, max_steps, out_pv, out_step,
+                     out_nsteps, out_flags, P, out_proc);
+  GV_TRY(launched(fn));
+  if (pe) (void)hipEventRecord(pe[1], s);
+  return GV_OK;
+}
+
 }  // namespace
 
 namespace {
 
-int transport_common(const char* fn, gv_geom* g, int64_t n, const double* x, const double* y, const double* z,
-                     const double* dx, const double* dy, const double* dz, const int32_t* start_pv,
-                     int32_t max_steps, int32_t* out_pv, double* out_step, int32_t* out_nsteps,
-                     uint32_t* out_flags, int32_t precision, bool phys, PhysArgs P, int8_t* out_proc,
-                     void* stream) {
+// Argument checks shared by the transports (n == 0 passes; the caller
+// returns before enqueuing anything).
+int transport_args(const char* fn, gv_geom* g, int64_t n, const double* x, const double* y, const double* z,
+                   const double* dx, const double* dy, const double* dz, const int32_t* start_pv, int32_t max_steps,
+                   int32_t* out_pv, double* out_step, int32_t* out_nsteps, uint32_t* out_flags, int32_t precision,
+                   bool phys) {
   GV_TRY(check_common(fn, g, n));
   GV_TRY(check_nav_precision(fn, precision));
   if (max_steps < 1 || max_steps > 4096) return fail(GV_EINVAL, "%s: max_steps %d not in [1, 4096]", fn, max_steps);
   if (phys && g->dg.n_mat < 1) return fail(GV_ESTATE, "%s: no materials (geom_set_materials first)", fn);
   if (n == 0) return GV_OK;
+  if (n > (1L << 30)) return fail(GV_EINVAL, "%s: n %lld > 2^30", fn, (long long)n);
   const double* in[6] = {x, y, z, dx, dy, dz};
   const char* nm[6] = {"x", "y", "z", "dx", "dy", "dz"};
   for (int i = 0; i < 6; ++i) GV_TRY(check_f64(fn, nm[i], in[i]));
@@ -1262,19 +1400,39 @@ int transport_common(const char* fn, gv_geom* g, int64_t n, const double* x, con
   GV_TRY(check_f64(fn, "out_step", out_step));
   GV_TRY(check_i32(fn, "out_nsteps", out_nsteps));
   GV_TRY(check_i32(fn, "out_flags", out_flags));
+  return GV_OK;
+}
+
+int transport_common(const char* fn, gv_geom* g, int64_t n, const double* x, const double* y, const double* z,
+                     const double* dx, const double* dy, const double* dz, const int32_t* start_pv,
+                     int32_t max_steps, int32_t* out_pv, double* out_step, int32_t* out_nsteps,
+                     uint32_t* out_flags, int32_t precision, bool phys, PhysArgs P, int8_t* out_proc,
+                     void* stream) {
+  GV_TRY(transport_args(fn, g, n, x, y, z, dx, dy, dz, start_pv, max_steps, out_pv, out_step, out_nsteps, out_flags,
+                        precision, phys));
+  if (n == 0) return GV_OK;
   DeviceGuard dgd(g->device);
   const bool fp32 = precision == GV_FP32_REFINE;
-  if (n >= kBasketMin && n <= (1L << 30) && g->n_lv <= 4096)
+  const hipStream_t s = (hipStream_t)stream;
+  // the basket form when it is asked for (or its work counters are), else
+  // the lane form
+  if ((g->tune.transport == 1 || g->prof_work) && n >= kBasketMin && g->n_lv <= 4096)
     return basket_transport(g, n, x, y, z, dx, dy, dz, start_pv, max_steps, out_pv, out_step, out_nsteps, out_flags,
-                            fp32, phys, P, out_proc, (hipStream_t)stream);
-  const auto lane =
-      g->has_bool ? (fp32 ? (phys ? k_transport_lane<true, true, true> : k_transport_lane<true, false, true>)
-                          : (phys ? k_transport_lane<false, true, true> : k_transport_lane<false, false, true>))
-                  : (fp32 ? (phys ? k_transport_lane<true, true, false> : k_transport_lane<true, false, false>)
-                          : (phys ? k_transport_lane<false, true, false> : k_transport_lane<false, false, false>));
-  hipLaunchKernelGGL(lane, dim3(lane_shape(g, n).grid), dim3(lane_shape(g, n).block), 0, (hipStream_t)stream, g->dg, n, x, y, z, dx, dy, dz,
-                     start_pv, (int)max_steps, out_pv, out_step, out_nsteps, out_flags, P, out_proc);
-  return launched(fn);
+                            fp32, phys, P, out_proc, s);
+  // Under stream capture nothing may be allocated: the workspace must already
+  // hold n tracks from an earlier call.
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cap) != hipSuccess) cap = hipStreamCaptureStatusNone;
+  if (cap == hipStreamCaptureStatusActive) {
+    if (!g->lws || g->lws_cap < n)
+      return fail(GV_ESTATE, "%s: stream is capturing and the workspace holds %lld < %lld tracks; call once "
+                  "outside the capture first", fn, (long long)g->lws_cap, (long long)n);
+    if (g->prof) return fail(GV_ESTATE, "%s: profiling events cannot be recorded under stream capture", fn);
+  } else {
+    GV_TRY(ensure_lane_workspace(g, n));
+  }
+  return lane_transport(g, g->lctl, n, x, y, z, dx, dy, dz, start_pv, max_steps, out_pv, out_step, out_nsteps,
+                        out_flags, fp32, phys, P, out_proc, s, fn, g->prof);
 }
 
 }  // namespace
@@ -1388,6 +1546,12 @@ extern "C" int gv_set_tuning(gv_geom* g, const gv_tuning* t) {
   if (t->solid_grid < 0) return fail(GV_EINVAL, "%s: solid_grid %d < 0", fn, t->solid_grid);
   if (!(t->step_waves == 0 || t->step_waves == 3 || t->step_waves == 4))
     return fail(GV_EINVAL, "%s: step_waves %d not 0, 3 or 4", fn, t->step_waves);
+  if (t->transport < 0 || t->transport > 2) return fail(GV_EINVAL, "%s: transport %d not 0, 1 or 2", fn, t->transport);
+  if (t->sort_bits < -1 || t->sort_bits > kSortMaxBits)
+    return fail(GV_EINVAL, "%s: sort_bits %d not in [-1, %d]", fn, t->sort_bits, kSortMaxBits);
+  if (t->lane_refill < 0 || t->lane_refill > 2)
+    return fail(GV_EINVAL, "%s: lane_refill %d not 0, 1 or 2", fn, t->lane_refill);
+  if (t->lane_grid < 0) return fail(GV_EINVAL, "%s: lane_grid %d < 0", fn, t->lane_grid);
   g->tune = *t;
   t_err.clear();
   return GV_OK;

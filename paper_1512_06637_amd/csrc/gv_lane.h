@@ -1,0 +1,273 @@
+// Whole-track transport with one lane per track, persistent over the batch
+// (Sec. III.A: a particle is stepped, volume after volume, until it leaves the
+// geometry).
+//
+// The basket regrouping of gv_baskets.h keeps a wavefront's tracks in one
+// logical volume by moving 16 bytes of indices per track and step and a
+// 64-byte record through HBM.  With the daughter indexes of gv_step.h a step
+// evaluates one or two daughter distances in any volume, so the divergence
+// the regrouping avoids has become cheaper than the traffic it costs.  The
+// form here keeps each track's state in registers for its whole life:
+//
+//  * coherent order -- the tracks are counting-sorted once by a direction
+//    key (the octahedral map of the direction cut into 2^h x 2^h cells,
+//    numbered along a Morton curve).  Straight tracks leaving a common region
+//    in neighbouring directions cross the same volumes in the same order, so
+//    the 64 lanes of a wavefront mostly run the same branch of the step and
+//    read the same table entries.  The order changes no result: every track's
+//    arithmetic is its own.
+//  * persistent workers -- as many workgroups as the device holds at once;
+//    each wavefront takes 64 consecutive places of the order from an atomic
+//    counter and steps its tracks to the end, then takes the next 64.  With
+//    refill, a lane whose track has ended takes a new place at once (one
+//    atomic per wavefront and refill), so no lane idles until the wavefront's
+//    longest track ends.
+//
+// Every output row is written by the lane that owns the track, so the results
+// (sequences, lengths, counts, flags) are independent of the order, the grid
+// and the refill policy.
+#pragma once
+#include "gv_step.h"
+
+namespace gv {
+
+constexpr int kSortMaxBits = 7;  // at most 2^7 x 2^7 direction cells
+constexpr int kSortMaxCells = 1 << (2 * kSortMaxBits);
+
+// Interleaves the low 7 bits of x with zeros (bit b to bit 2b).
+__device__ __forceinline__ uint32_t spread_bits7(uint32_t x) {
+  x &= 0x7Fu;
+  x = (x | (x << 4)) & 0x0F0Fu;
+  x = (x | (x << 2)) & 0x3333u;
+  x = (x | (x << 1)) & 0x5555u;
+  return x;
+}
+
+// Direction key: the octahedral map of the direction onto [-1, 1]^2 (the
+// lower hemisphere folded over the diagonals), cut into 2^h x 2^h cells and
+// numbered in Morton order, so that consecutive keys are neighbouring cones.
+// Only the order of the work depends on it.
+__device__ __forceinline__ uint32_t direction_key(double dx, double dy, double dz, int h) {
+  const double a = fabs(dx) + fabs(dy) + fabs(dz);
+  double u = dx / a, v = dy / a;
+  if (dz < 0.0) {
+    const double uu = (1.0 - fabs(v)) * (u < 0.0 ? -1.0 : 1.0), vv = (1.0 - fabs(u)) * (v < 0.0 ? -1.0 : 1.0);
+    u = uu;
+    v = vv;
+  }
+  const int side = 1 << h, m = side - 1;
+  // a NaN converts to some integer, clamped into the grid: order only
+  const uint32_t iu = (uint32_t)min(m, max(0, (int)((u + 1.0) * (0.5 * side))));
+  const uint32_t iv = (uint32_t)min(m, max(0, (int)((v + 1.0) * (0.5 * side))));
+  return spread_bits7(iu) | (spread_bits7(iv) << 1);
+}
+
+// Lane-transport control words (device workspace): cnt[cells] key counts,
+// then the running place of each cell during the scatter, and the work
+// counter the persistent workers take places from.
+struct LaneCtl {
+  uint32_t* key;    // [n] direction key of each track
+  int32_t* perm;    // [n] track of each place in the coherent order
+  uint32_t* cnt;    // [cells] tracks per key
+  uint32_t* queue;  // [1] next place to hand out
+};
+
+// Zeroes the key counts and the work counter before a transport.
+__global__ void k_ls_clear(LaneCtl L, int cells) {
+  for (int64_t i = gtid(); i < cells; i += gstride()) L.cnt[i] = 0u;
+  if (gtid() == 0) *L.queue = 0u;
+}
+
+// Key of every track and the per-key counts (workgroup histogram in LDS,
+// 4 cells bytes of dynamic LDS, one global atomic per workgroup and key).
+__global__ void k_ls_count(int64_t n, const double* __restrict__ dx, const double* __restrict__ dy,
+                           const double* __restrict__ dz, int h, LaneCtl L) {
+  extern __shared__ uint32_t key_hist[];
+  const int cells = 1 << (2 * h);
+  for (int c = threadIdx.x; c < cells; c += blockDim.x) key_hist[c] = 0u;
+  __syncthreads();
+  for (int64_t i = gtid(); i < n; i += gstride()) {
+    const uint32_t k = direction_key(dx[i], dy[i], dz[i], h);
+    L.key[i] = k;
+    atomicAdd(&key_hist[k], 1u);
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < cells; c += blockDim.x)
+    if (key_hist[c]) atomicAdd(&L.cnt[c], key_hist[c]);
+}
+
+// Exclusive scan of the key counts in place (one workgroup of 1024 threads):
+// cnt[c] becomes the first place of key c.
+__global__ void __launch_bounds__(1024) k_ls_scan(LaneCtl L, int cells) {
+  __shared__ uint32_t part[1024];
+  const int t = threadIdx.x;
+  const int per = (cells + 1023) / 1024;
+  const int c0 = t * per, c1 = min(cells, c0 + per);
+  uint32_t s = 0;
+  for (int c = c0; c < c1; ++c) s += L.cnt[c];
+  part[t] = s;
+  __syncthreads();
+  // Hillis-Steele inclusive scan over the 1024 partial sums
+  for (int o = 1; o < 1024; o <<= 1) {
+    const uint32_t v = t >= o ? part[t - o] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  uint32_t run = t > 0 ? part[t - 1] : 0u;
+  for (int c = c0; c < c1; ++c) {
+    const uint32_t v = L.cnt[c];
+    L.cnt[c] = run;
+    run += v;
+  }
+}
+
+// Places: each track takes the next free place of its key (the order inside
+// a key depends on the atomics' order, which changes no result).
+__global__ void k_ls_scatter(int64_t n, LaneCtl L) {
+  for (int64_t i = gtid(); i < n; i += gstride()) {
+    const uint32_t pos = atomicAdd(&L.cnt[L.key[i]], 1u);
+    L.perm[pos] = (int32_t)i;
+  }
+}
+
+// One track's state while a lane carries it.
+struct LaneTrack {
+  V3 p, d;
+  double safe;  // physics: distance still to go to the last boundary found
+  int64_t i;    // track index
+  int pv, k, zero_run;
+  uint32_t fl;
+};
+
+// Starts track i: its volume (given or located) and entry 0 of its sequence.
+// Returns false (and writes the track's zero count and flags) when it starts
+// outside the world.
+template <bool B>
+__device__ __forceinline__ bool lane_begin(const DevGeom& G, LaneTrack& T, int64_t i, const double* __restrict__ x,
+                                           const double* __restrict__ y, const double* __restrict__ z,
+                                           const double* __restrict__ dx, const double* __restrict__ dy,
+                                           const double* __restrict__ dz, const int32_t* __restrict__ start_pv,
+                                           int max_steps, int32_t* __restrict__ out_pv,
+                                           int32_t* __restrict__ out_nsteps, uint32_t* __restrict__ out_flags) {
+  T.i = i;
+  T.p = ld3(x, y, z, i);
+  T.d = ld3(dx, dy, dz, i);
+  T.fl = 0u;
+  T.k = 0;
+  T.zero_run = 0;
+  T.safe = 0.0;
+  int pv = start_pv ? start_pv[i] : locate<B>(G, T.p);
+  if (pv < -1 || pv >= G.n_pv) {
+    pv = -1;
+    T.fl = kFlagLocateFail;
+  }
+  T.pv = pv;
+  out_pv[(size_t)i * (max_steps + 1)] = pv;
+  if (pv < 0) {
+    out_nsteps[i] = 0;
+    out_flags[i] = T.fl;
+    return false;
+  }
+  return true;
+}
+
+// One step of a carried track; returns true when the track has ended (left
+// the world, stuck, or out of steps), after writing its count and flags.
+template <bool F32, bool PHYS, bool B>
+__device__ __forceinline__ bool lane_step(const DevGeom& G, LaneTrack& T, int max_steps, int32_t* __restrict__ out_pv,
+                                          double* __restrict__ out_step, int32_t* __restrict__ out_nsteps,
+                                          uint32_t* __restrict__ out_flags, const PhysArgs& P,
+                                          int8_t* __restrict__ out_proc) {
+  NoWork w;
+  int nx;
+  double st;
+  if (PHYS) {
+    int proc;
+    st = step_physics<F32, B>(G, G.pv_lv[T.pv], T.pv, T.p, T.d, (uint32_t)T.i, T.k, P, T.safe, &nx, &proc, &T.fl, w);
+    if (out_proc) out_proc[(size_t)T.i * max_steps + T.k] = (int8_t)proc;
+  } else {
+    st = step_culled<F32, B>(G, G.pv_lv[T.pv], T.pv, T.p, T.d, &nx, &T.fl, w);
+    T.p = advance(T.p, st, T.d);
+  }
+  out_step[(size_t)T.i * max_steps + T.k] = st;
+  out_pv[(size_t)T.i * (max_steps + 1) + T.k + 1] = nx;
+  ++T.k;
+  bool end = nx < 0;
+  if (!end) {
+    T.zero_run = st < kTol ? T.zero_run + 1 : 0;
+    if (T.zero_run >= 8) {
+      T.fl |= kFlagStuck;
+      end = true;
+    } else if (T.k == max_steps) {
+      T.fl |= kFlagOverflow;
+      end = true;
+    }
+  }
+  T.pv = nx;
+  if (end) {
+    out_nsteps[T.i] = T.k;
+    out_flags[T.i] = T.fl;
+  }
+  return end;
+}
+
+// Persistent whole-track transport.  Places 0..n-1 of the order (perm, or the
+// identity when perm is NULL) are handed out from *queue, which must be 0 at
+// launch.  REFILL: a lane whose track ended takes the next place at once;
+// otherwise a wavefront takes 64 places when all of its tracks have ended.
+template <bool F32, bool PHYS, bool B, bool REFILL>
+__global__ void __launch_bounds__(256) k_lane_transport(
+    DevGeom G, int64_t n, const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
+    const double* __restrict__ dx, const double* __restrict__ dy, const double* __restrict__ dz,
+    const int32_t* __restrict__ start_pv, const int32_t* __restrict__ perm, uint32_t* __restrict__ queue,
+    int max_steps, int32_t* __restrict__ out_pv, double* __restrict__ out_step, int32_t* __restrict__ out_nsteps,
+    uint32_t* __restrict__ out_flags, PhysArgs P, int8_t* __restrict__ out_proc) {
+  const int lane = __lane_id();
+  LaneTrack T;
+  if (!REFILL) {
+    for (;;) {
+      uint32_t b = 0;
+      if (lane == 0) b = atomicAdd(queue, 64u);
+      const int64_t base = (int64_t)__shfl(b, 0);
+      if (base >= n) break;
+      const int64_t j = base + lane;
+      if (j < n) {
+        const int64_t i = perm ? perm[j] : j;
+        if (lane_begin<B>(G, T, i, x, y, z, dx, dy, dz, start_pv, max_steps, out_pv, out_nsteps, out_flags)) {
+          while (!lane_step<F32, PHYS, B>(G, T, max_steps, out_pv, out_step, out_nsteps, out_flags, P, out_proc)) {
+          }
+        }
+      }
+    }
+    return;
+  }
+  bool has = false, drained = false;
+  for (;;) {
+    if (!drained) {
+      const uint64_t need = __ballot(!has);
+      if (need) {
+        const int c = __popcll(need);
+        const int leader = __ffsll((unsigned long long)need) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(queue, (uint32_t)c);
+        base = __shfl(base, leader);
+        if ((int64_t)base + c >= n) drained = true;
+        if (!has) {
+          const int64_t j = (int64_t)base + __popcll(need & ((1ull << lane) - 1ull));
+          if (j < n) {
+            const int64_t i = perm ? perm[j] : j;
+            has = lane_begin<B>(G, T, i, x, y, z, dx, dy, dz, start_pv, max_steps, out_pv, out_nsteps, out_flags);
+          }
+        }
+      }
+    }
+    if (__ballot(has) == 0) {
+      if (drained) break;
+      continue;  // every new track of this round started outside the world
+    }
+    if (has) has = !lane_step<F32, PHYS, B>(G, T, max_steps, out_pv, out_step, out_nsteps, out_flags, P, out_proc);
+  }
+}
+
+}  // namespace gv

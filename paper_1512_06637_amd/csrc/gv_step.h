@@ -615,58 +615,4 @@ __global__ void k_nav_safety_scr(DevGeom G, int64_t n, const double* __restrict_
   }
 }
 
-// Whole-track transport, one lane per track, until the track leaves the world
-// (used for batches too small to fill the device with per-volume tiles);
-// with PHYS, physics-limited steps (track index = counter of the draws).
-template <bool F32, bool PHYS, bool B>
-__global__ void k_transport_lane(DevGeom G, int64_t n, const double* __restrict__ x, const double* __restrict__ y,
-                                 const double* __restrict__ z, const double* __restrict__ dx,
-                                 const double* __restrict__ dy, const double* __restrict__ dz,
-                                 const int32_t* __restrict__ start_pv, int max_steps, int32_t* __restrict__ out_pv,
-                                 double* __restrict__ out_step, int32_t* __restrict__ out_nsteps,
-                                 uint32_t* __restrict__ out_flags, PhysArgs P, int8_t* __restrict__ out_proc) {
-  NoWork w;
-  for (int64_t i = gtid(); i < n; i += gstride()) {
-    V3 p = ld3(x, y, z, i), d = ld3(dx, dy, dz, i);
-    uint32_t fl = 0;
-    int pv = start_pv ? start_pv[i] : locate<B>(G, p);
-    if (pv < -1 || pv >= G.n_pv) {
-      pv = -1;
-      fl |= kFlagLocateFail;
-    }
-    int32_t* rp = out_pv + (size_t)i * (max_steps + 1);
-    double* rs = out_step + (size_t)i * max_steps;
-    rp[0] = pv;
-    int k = 0;
-    if (pv >= 0) {
-      int zero_run = 0, nx = pv;
-      double safe = 0.0;
-      while (k < max_steps) {
-        double st;
-        if (PHYS) {
-          int proc;
-          st = step_physics<F32, B>(G, G.pv_lv[pv], pv, p, d, (uint32_t)i, k, P, safe, &nx, &proc, &fl, w);
-          if (out_proc) out_proc[(size_t)i * max_steps + k] = (int8_t)proc;
-        } else {
-          st = step_culled<F32, B>(G, G.pv_lv[pv], pv, p, d, &nx, &fl, w);
-          p = advance(p, st, d);
-        }
-        rs[k] = st;
-        rp[k + 1] = nx;
-        ++k;
-        if (nx < 0) break;
-        zero_run = st < kTol ? zero_run + 1 : 0;
-        if (zero_run >= 8) {
-          fl |= kFlagStuck;
-          break;
-        }
-        pv = nx;
-      }
-      if (k == max_steps && nx >= 0 && !(fl & kFlagStuck)) fl |= kFlagOverflow;
-    }
-    out_nsteps[i] = k;
-    out_flags[i] = fl;
-  }
-}
-
 }  // namespace gv

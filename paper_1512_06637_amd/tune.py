@@ -1,18 +1,21 @@
 """Autotuner of the library's launch shapes.
 
-The choices are the fields of gvgeom.h's gv_tuning: workgroup counts of the
-per-step basket kernel and of the regrouping kernels, the coarse direction
-cells of the regrouping key, the register budget of the navigation step
-kernel (waves per SIMD), and the block size and workgroup cap of the
-one-lane-per-track kernels (solid-level queries).  None of them changes a
-result; the tuner checks that on every candidate (bitwise-equal outputs) and
-keeps the fastest, per device architecture, in tuned.json beside this file.
-Geometry() applies the stored choice at load.
+The choices are the fields of gvgeom.h's gv_tuning: the form of the
+transport (lane form: one persistent kernel carrying each track in one lane,
+tracks ordered by a direction key; basket form: regrouping by volume before
+every step), the lane form's direction cells, refill policy and persistent
+grid, the basket form's workgroup counts, direction cells and register
+budget, and the block size and workgroup cap of the one-lane-per-track
+kernels (solid-level queries).  None of them changes a result; the tuner
+checks that on every candidate (bitwise-equal outputs) and keeps the fastest,
+per device architecture, in tuned.json beside this file.  Geometry() applies
+the stored choice at load.
 
-Search: coordinate descent from the library's defaults.  Each knob is swept
-over its candidate values with the others held at the best found so far;
-every candidate is timed with HIP events over several calls (median of
-repeats), on the stream the library launches on.
+Search: coordinate descent from the library's defaults, for each transport
+form separately, then the faster form.  Each knob is swept over its candidate
+values with the others held at the best found so far; every candidate is
+timed with HIP events over several calls (median of repeats), on the stream
+the library launches on.
 
 Run on a GPU:  python -m paper_1512_06637_amd.tune [--n 1048576] [--write]
 """
@@ -27,7 +30,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuned.json")
 
 # candidate values per knob (0 / -1 = the library default)
-TRANSPORT_SPACE = {
+LANE_FORM_SPACE = {
+    "transport": [2],
+    "sort_bits": [-1, 0, 4, 5, 7],
+    "lane_refill": [0, 2],
+    "lane_grid": [0, 512, 1024, 2048],
+}
+BASKET_FORM_SPACE = {
+    "transport": [1],
     "step_grid": [0, 512, 768, 1024],
     "scatter_grid": [0, 128, 512],
     "cell_bits": [-1, 0, 4],
@@ -96,8 +106,18 @@ def _same(a: dict, b: dict) -> bool:
 
 
 def tune_transport(g, a, max_steps=128, calls=5, log=print):
-    """Coordinate descent over TRANSPORT_SPACE on nav_transport of tracks `a`
-    (six device arrays).  Returns (choice, table of timings)."""
+    """Both transport forms tuned on nav_transport of tracks `a` (six device
+    arrays); the faster wins.  Returns (choice, ms, table of timings)."""
+    lane, lane_ms, lt = tune_form(g, a, LANE_FORM_SPACE, max_steps, calls, log)
+    basket, basket_ms, bt = tune_form(g, a, BASKET_FORM_SPACE, max_steps, calls, log)
+    best, best_ms = (lane, lane_ms) if lane_ms <= basket_ms else (basket, basket_ms)
+    log(f"tune transport: lane form {lane_ms:.3f} ms, basket form {basket_ms:.3f} ms")
+    g.set_tuning(**best)
+    return best, best_ms, lt + bt
+
+
+def tune_form(g, a, space, max_steps=128, calls=5, log=print):
+    """Coordinate descent over one form's knobs.  Returns (choice, ms, table)."""
     import torch
     n = a[0].shape[0]
 
@@ -107,11 +127,11 @@ def tune_transport(g, a, max_steps=128, calls=5, log=print):
                 "nsteps": torch.empty(n, dtype=torch.int32, device="cuda"),
                 "flags": torch.empty(n, dtype=torch.int32, device="cuda")}
 
-    g.set_tuning(**{k: v[0] for k, v in TRANSPORT_SPACE.items()})
+    g.set_tuning(**{k: v[0] for k, v in space.items()})
     ref = g.transport(*a, max_steps=max_steps, out=new_out())
     torch.cuda.synchronize()
     out = new_out()
-    best = {k: v[0] for k, v in TRANSPORT_SPACE.items()}
+    best = {k: v[0] for k, v in space.items()}
     table = []
 
     def run(cfg):
@@ -125,7 +145,7 @@ def tune_transport(g, a, max_steps=128, calls=5, log=print):
     best_ms = run(best)
     table.append({"cfg": dict(best), "ms": best_ms})
     log(f"tune transport: default {best} {best_ms:.3f} ms")
-    for knob, vals in TRANSPORT_SPACE.items():
+    for knob, vals in space.items():
         for v in vals[1:] if best[knob] == vals[0] else vals:
             if v == best[knob]:
                 continue
@@ -135,7 +155,6 @@ def tune_transport(g, a, max_steps=128, calls=5, log=print):
             log(f"tune transport: {knob}={v} {ms:.3f} ms")
             if ms < best_ms * 0.995:  # keep a change only for a measurable gain
                 best, best_ms = cfg, ms
-    g.set_tuning(**best)
     return best, best_ms, table
 
 

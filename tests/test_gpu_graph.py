@@ -61,16 +61,18 @@ def test_graph_replays_match_eager():
     g.close()
 
 
-def test_transport_captured_in_graph_matches_eager():
-    """nav_transport on the basket path (20,011 tracks) only enqueues work, so it
-    can be captured into a HIP graph once its workspace exists; every replay,
-    with new inputs copied into the captured buffers and eager transports in
-    between, equals the eager result bit for bit, and the eager result matches
-    the oracle."""
+@pytest.mark.parametrize("transport", [0, 1])
+def test_transport_captured_in_graph_matches_eager(transport):
+    """nav_transport (20,011 tracks; lane form, then basket form) only enqueues
+    work, so it can be captured into a HIP graph once its workspace exists;
+    every replay, with new inputs copied into the captured buffers and eager
+    transports in between, equals the eager result bit for bit, and the eager
+    result matches the oracle."""
     import torch
     import paper_1512_06637_amd as G
     blob = W.detector_blob()
     g = G.Geometry(blob)
+    g.set_tuning(transport=transport)
     n = 20011
     t = W.config3_tracks(n)
     static = [cuda(v) for v in t.arrays()]
@@ -117,12 +119,14 @@ def test_transport_captured_in_graph_matches_eager():
     g.close()
 
 
-def test_transport_capture_without_workspace_is_refused():
+@pytest.mark.parametrize("transport", [0, 1])
+def test_transport_capture_without_workspace_is_refused(transport):
     """Under capture nothing may be allocated: a geometry that has never
     transported this many tracks refuses with GV_ESTATE (nothing recorded)."""
     import torch
     import paper_1512_06637_amd as G
     g = G.Geometry(W.detector_blob())
+    g.set_tuning(transport=transport)
     n = 9000
     t = W.config3_tracks(n)
     a = [cuda(v) for v in t.arrays()]

@@ -10,17 +10,12 @@ import pytest
 
 import oracle as O
 from paper_1512_06637_amd import workloads as W
-from tests.gpu_util import compare_values, cuda, host, say
+from tests.gpu_util import (STEP_ABS, STEP_REL, compare_values, cuda, host, oracle_detector_transport, say,
+                            transport_bits_equal, transport_rows_compare)
 
 pytestmark = pytest.mark.gpu
 
 BLOB = W.detector_blob()
-# Step lengths: both codes move the global point by p += s d in FP64; after k
-# steps the points differ by up to ~k ulp(|p|) (ulp(2048 mm) = 4.5e-13 mm, k <= 81
-# here, so ~4e-11 mm), and a step measured from a shifted point shifts by the same
-# amount over cos(angle).  Observed worst over 7,399 tracks: 3.8e-11 mm.
-STEP_REL = 1e-12
-STEP_ABS = 1e-10
 
 
 @pytest.fixture(scope="module")
@@ -115,36 +110,67 @@ def compare_transport(got, ref, idx=None):
     return int(ok.sum())
 
 
+# the transport forms (gvgeom.h gv_tuning): lane form with the default order,
+# lane form in index order with refill, basket form (8,192 tracks or more)
+FORMS = {"lane": {"transport": 0, "sort_bits": -1, "lane_refill": 0},
+         "lane_unsorted_refill": {"transport": 2, "sort_bits": 0, "lane_refill": 2},
+         "basket": {"transport": 1, "sort_bits": -1, "lane_refill": 0}}
+
+
+@pytest.mark.parametrize("form", list(FORMS))
 @pytest.mark.parametrize("n", [4099, 20011])
-def test_transport_full_compare(geos, n):
-    """Below 8,192 tracks one lane transports one track; above, tracks are
-    regrouped into per-volume baskets every step.  Both compared in full."""
+def test_transport_full_compare(geos, n, form):
+    """Every track against the oracle, in each transport form (batches below
+    8,192 tracks asked for the basket form run the lane form)."""
     g, og = geos
     t = W.config3_tracks(n)
-    say(f"[transport] n={n}")
-    got = g.transport(*[cuda(v) for v in t.arrays()])
+    say(f"[transport] n={n} form={form}")
+    g.set_tuning(**FORMS[form])
+    try:
+        got = g.transport(*[cuda(v) for v in t.arrays()])
+    finally:
+        g.set_tuning(**FORMS["lane"])
     ref = og.transport(t)
     assert compare_transport(got, ref) > 0.99 * n
 
 
-def test_transport_full_size_sampled(geos):
-    """All 2^20 tracks in the benchmark's launch; 3,000 sampled tracks are
-    transported again by the oracle."""
+def full_reference(og):
+    """The oracle's transport of all 2^20 benchmark tracks (once per session)."""
+    return oracle_detector_transport(og, "fp64", lambda o: o.transport(W.config3_tracks()))
+
+
+def test_transport_full_size(geos):
+    """All 2^20 tracks in the benchmark's launch (lane form), every track
+    against the oracle; the basket form gives the same outputs bit for bit."""
     g, og = geos
     t = W.config3_tracks()
-    say(f"[transport] n={t.n} (sampled compare)")
-    got = g.transport(*[cuda(v) for v in t.arrays()])
-    idx = np.sort(np.random.default_rng(9).choice(t.n, 3000, replace=False))
-    ref = og.transport(t.take(idx))
-    compare_transport(got, ref, idx)
+    say(f"[transport] n={t.n} (full compare)")
+    a = [cuda(v) for v in t.arrays()]
+    got = g.transport(*a)
+    n_ok, worst = transport_rows_compare(got, full_reference(og), what="transport 2^20")
+    assert n_ok > 0.99 * t.n
     ns = host(got["nsteps"])
     say(f"  total track-steps {int(ns.sum())}, mean {ns.mean():.2f}, max {ns.max()}")
     assert np.all(host(got["flags"]) == 0)
+    g.set_tuning(**FORMS["basket"])
+    try:
+        assert transport_bits_equal(got, g.transport(*a))
+    finally:
+        g.set_tuning(**FORMS["lane"])
 
 
+@pytest.mark.parametrize("form", ["lane", "basket"])
 @pytest.mark.parametrize("n", [300, 9000])
-def test_transport_edges(geos, n):
+def test_transport_edges(geos, n, form):
     g, og = geos
+    g.set_tuning(**FORMS[form])
+    try:
+        _edges(g, og, n)
+    finally:
+        g.set_tuning(**FORMS["lane"])
+
+
+def _edges(g, og, n):
     t = W.config3_tracks(n)
     # tight step budget -> OVERFLOW, and explicit start PV
     got = g.transport(*[cuda(v) for v in t.arrays()], start_pv=cuda(np.zeros(n, np.int32)), max_steps=7)

@@ -8,7 +8,7 @@ import pytest
 
 import oracle as O
 from paper_1512_06637_amd import workloads as W
-from tests.gpu_util import cuda, host, say
+from tests.gpu_util import cuda, host, say, transport_rows_compare
 from tests.test_gpu_nav import STEP_ABS, STEP_REL
 
 pytestmark = pytest.mark.gpu
@@ -81,8 +81,9 @@ def test_phys_transport_full_compare(geos, n):
 
 
 def test_phys_transport_full_size(geos):
-    """2^20 tracks in the benchmark's launch: 2,000 sampled tracks against the
-    oracle; the short-cut and the FP32 screens change nothing; counters."""
+    """2^20 tracks in the benchmark's launch: every track against the oracle;
+    the short-cut changes nothing; the basket form's counters (its outputs
+    equal the lane form's)."""
     import paper_1512_06637_amd as G
     g, og = geos
     t = W.config3_tracks()
@@ -95,8 +96,10 @@ def test_phys_transport_full_size(geos):
     _, _, w0 = g.profile_read()
     g.profile()
     _same(got, plain)
-    idx = np.sort(np.random.default_rng(17).choice(t.n, 2000, replace=False))
-    compare_phys(got, og.transport_phys(t.take(idx), MAT, SEED, max_steps=MAX_STEPS, track_id=idx), idx)
+    lane = g.transport_phys(*a, SEED, max_steps=MAX_STEPS, shortcut=True)  # the default (lane) form
+    _same(lane, got)
+    ref = og.transport_phys(t, MAT, SEED, max_steps=MAX_STEPS)
+    transport_rows_compare(lane, ref, what="phys transport 2^20", proc=True)
     ns = host(got["nsteps"])
     say(f"  track-steps {int(ns.sum())}, physics-limited {w[22]}, by short-cut {w[23]} (without: {w0[22]}, {w0[23]})")
     assert w[22] == w0[22] > 0 and w[23] > 0 and w0[23] == 0

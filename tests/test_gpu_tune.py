@@ -1,8 +1,9 @@
 """Launch shapes never change a result: every shape the autotuner may pick
-(and the stored choice) gives outputs bitwise equal to the defaults', for the
-basket transport (FP64 and FP32_REFINE) and the solid-level queries; repeated
-transports are bitwise equal (the regrouping's atomics only reorder work);
-and the roof probes compute what they claim."""
+(and the stored choice) gives outputs bitwise equal to the defaults', for both
+transport forms (FP64 and FP32_REFINE) and the solid-level queries; repeated
+transports are bitwise equal (the atomics of the ordering, the work counter and
+the regrouping only reorder work); and the roof probes compute what they
+claim."""
 import numpy as np
 import pytest
 
@@ -11,15 +12,28 @@ from tests.gpu_util import cuda, host, say
 
 pytestmark = pytest.mark.gpu
 
+BASKET = {"transport": 1}
 SHAPES = [
-    {"step_grid": 256},
-    {"step_grid": 1024, "scatter_grid": 64},
-    {"scatter_grid": 1024},
-    {"cell_bits": 0},
-    {"cell_bits": 4},
-    {"step_waves": 3},
-    {"step_grid": 97, "scatter_grid": 3, "cell_bits": 4, "step_waves": 3},
+    # lane form (default): orderings, refill, persistent grid sizes
+    {"sort_bits": 0},
+    {"sort_bits": 3},
+    {"sort_bits": 7},
+    {"lane_refill": 2},
+    {"lane_refill": 2, "sort_bits": 0},
+    {"lane_grid": 7},
+    {"lane_grid": 300, "lane_refill": 2},
+    # basket form: step and regrouping grids, direction cells, register budget
+    dict(BASKET),
+    dict(BASKET, step_grid=256),
+    dict(BASKET, step_grid=1024, scatter_grid=64),
+    dict(BASKET, scatter_grid=1024),
+    dict(BASKET, cell_bits=0),
+    dict(BASKET, cell_bits=4),
+    dict(BASKET, step_waves=3),
+    dict(BASKET, step_grid=97, scatter_grid=3, cell_bits=4, step_waves=3),
 ]
+DEFAULTS = {"step_grid": 0, "scatter_grid": 0, "cell_bits": -1, "step_waves": 0, "transport": 0, "sort_bits": -1,
+            "lane_refill": 0, "lane_grid": 0}
 
 
 def _bits(out):
@@ -48,7 +62,7 @@ def test_transport_shapes_and_repeats_bitwise(precision):
         assert _equal(ref, _bits(g.transport(*a, precision=precision))), f"repeat {r}"
     stored = tune.stored_choice() or {}
     for sh in SHAPES + ([stored] if stored else []):
-        g.set_tuning(**{**{"step_grid": 0, "scatter_grid": 0, "cell_bits": -1, "step_waves": 0}, **sh})
+        g.set_tuning(**{**DEFAULTS, **sh})
         got = _bits(g.transport(*a, precision=precision))
         torch.cuda.synchronize()
         assert _equal(ref, got), sh
@@ -82,7 +96,8 @@ def test_solid_lane_shapes_bitwise(name):
 def test_tuning_rejects_bad_fields():
     import paper_1512_06637_amd as G
     g = G.Geometry(W.detector_blob(), tuned=False)
-    for bad in [{"step_grid": 5000}, {"cell_bits": 3}, {"solid_block": 100}, {"step_waves": 5}]:
+    for bad in [{"step_grid": 5000}, {"cell_bits": 3}, {"solid_block": 100}, {"step_waves": 5}, {"transport": 3},
+                {"sort_bits": 8}, {"lane_refill": 3}, {"lane_grid": -1}]:
         with pytest.raises(G.GVError):
             g.set_tuning(**bad)
     assert g.get_tuning()["step_grid"] == 0
