@@ -258,8 +258,8 @@ int gv_probe_fma64(double* out, int64_t n_lanes, int32_t iters, void* stream);
  * package's tune module) and the binding applies the stored choice at load.
  *
  * The transports have two forms.  The lane form (default) orders the tracks
- * once by a direction key (counting sort into 2^sort_bits x 2^sort_bits cells
- * of the octahedral direction map, cells in Morton order), then one
+ * once by a direction key (counting sort into 2^sort_bits x 2^sort_bits
+ * direction cells), then one
  * persistent kernel carries each track in one lane from its start to its end,
  * wavefronts taking 64 places of the order at a time from an atomic counter.
  * The basket form (Sec. II.A baskets of tracks in the same volume) regroups
@@ -284,17 +284,21 @@ int gv_probe_fma64(double* out, int64_t n_lanes, int32_t iters, void* stream);
  *                 needs n >= 8,192, smaller batches take the lane form);
  *   sort_bits     0..7: the lane form's direction cells are 2^sort_bits x
  *                 2^sort_bits (0: no ordering, tracks in index order;
- *                 default 6);
- *   lane_refill   1 off, 2 on: a lane whose track has ended takes the next
- *                 track at once instead of waiting for its wavefront's
- *                 other tracks (default off);
+ *                 default 7);
+ *   sort_key      1 octahedral cells in Morton order, 2 z-axis cells (cos
+ *                 theta bands x azimuth sectors, bands outermost) (default 1);
+ *   lane_waves    3 or 4: waves per SIMD the lane kernel is built for
+ *                 (default 4; 3 for physics-limited transport);
+ *   lane_stage    1 off, 2 on: the lane kernel stages 8 steps of outputs in
+ *                 LDS before writing a track's rows (default on; off for
+ *                 physics-limited transport);
  *   lane_grid     workgroups (256 threads) of the persistent lane kernel,
  *                 >= 0 (default: as many as the device holds at once).
  * A change of cell_bits re-sizes the transport workspace at the next
  * transport.  GV_EINVAL for a field out of range (nothing changed). */
 typedef struct {
   int32_t step_grid, scatter_grid, cell_bits, solid_block, solid_grid, step_waves;
-  int32_t transport, sort_bits, lane_refill, lane_grid;
+  int32_t transport, sort_bits, sort_key, lane_waves, lane_stage, lane_grid;
 } gv_tuning;
 int gv_set_tuning(gv_geom* g, const gv_tuning* t);
 int gv_get_tuning(const gv_geom* g, gv_tuning* t);

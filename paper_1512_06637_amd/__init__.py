@@ -24,7 +24,7 @@ FP64, FP32_REFINE = 0, 1
 WORK_N = 28  # work counters returned by gv_profile_read
 PROF_EVENTS, PROF_WORK = 1, 2
 TUNING_FIELDS = ("step_grid", "scatter_grid", "cell_bits", "solid_block", "solid_grid", "step_waves",
-                 "transport", "sort_bits", "lane_refill", "lane_grid")
+                 "transport", "sort_bits", "sort_key", "lane_waves", "lane_stage", "lane_grid")
 
 
 class _Tuning(C.Structure):

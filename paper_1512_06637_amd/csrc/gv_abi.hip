@@ -69,7 +69,7 @@ struct gv_geom {
   bool prof = false;
   bool prof_work = false;
   // launch shapes (gv_set_tuning); zero / negative fields take the defaults
-  gv_tuning tune{0, 0, -1, 0, 0, 0, 0, -1, 0, 0};
+  gv_tuning tune{0, 0, -1, 0, 0, 0, 0, -1, 0, 0, 0, 0};
   // lane-transport workspace (grown on demand): direction keys, the coherent
   // order, key counts and the work counter
   void* lws = nullptr;
@@ -1253,7 +1253,7 @@ int basket_transport(gv_geom* g, int64_t n, const double* x, const double* y, co
 }
 
 // ------------------------------------------------------- lane transport
-constexpr int kLaneSortBits = 6;  // default direction cells of the order: 64 x 64
+constexpr int kLaneSortBits = 7;  // default direction cells of the order: 128 x 128
 
 // Direction-key bits of the coherent order: the tuned sort_bits, else the
 // default; 0 runs the tracks in index order.
@@ -1303,16 +1303,21 @@ using LaneKernel = void (*)(DevGeom, int64_t, const double*, const double*, cons
                             double*, int32_t*, uint32_t*, PhysArgs, int8_t*);
 
 // The lane-transport instance: composites or not, FP32 screens or not,
-// physics-limited or not, refill or not (geometries without composites).
-LaneKernel select_lane_kernel(bool has_bool, bool fp32, bool phys, bool refill) {
+// physics-limited or not, and the register budget (3 or 4 waves per SIMD)
+// and output staging.  Geometries with composites run one shape per
+// precision and physics.
+template <bool F32, bool PHYS>
+LaneKernel lane_kernel_for(int waves, bool stage) {
+  if (waves == 3) return stage ? k_lane_transport<F32, PHYS, false, 3, 8> : k_lane_transport<F32, PHYS, false, 3, 0>;
+  return stage ? k_lane_transport<F32, PHYS, false, 4, 8> : k_lane_transport<F32, PHYS, false, 4, 0>;
+}
+
+LaneKernel select_lane_kernel(bool has_bool, bool fp32, bool phys, int waves, bool stage) {
   if (has_bool)
-    return fp32 ? (phys ? k_lane_transport<true, true, true, false> : k_lane_transport<true, false, true, false>)
-                : (phys ? k_lane_transport<false, true, true, false> : k_lane_transport<false, false, true, false>);
-  if (refill)
-    return fp32 ? (phys ? k_lane_transport<true, true, false, true> : k_lane_transport<true, false, false, true>)
-                : (phys ? k_lane_transport<false, true, false, true> : k_lane_transport<false, false, false, true>);
-  return fp32 ? (phys ? k_lane_transport<true, true, false, false> : k_lane_transport<true, false, false, false>)
-              : (phys ? k_lane_transport<false, true, false, false> : k_lane_transport<false, false, false, false>);
+    return fp32 ? (phys ? k_lane_transport<true, true, true, 3, 0> : k_lane_transport<true, false, true, 3, 0>)
+                : (phys ? k_lane_transport<false, true, true, 3, 0> : k_lane_transport<false, false, true, 3, 0>);
+  if (phys) return fp32 ? lane_kernel_for<true, true>(waves, stage) : lane_kernel_for<false, true>(waves, stage);
+  return fp32 ? lane_kernel_for<true, false>(waves, stage) : lane_kernel_for<false, false>(waves, stage);
 }
 
 // Workgroups of 256 threads a CU holds at once for kernel k (cached per
@@ -1343,15 +1348,19 @@ int lane_transport(gv_geom* g, const LaneCtl& L, int64_t n, const double* x, con
   GV_TRY(launched(fn));
   if (sorted) {
     const unsigned cg = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 4095) / 4096, 256));
-    hipLaunchKernelGGL(k_ls_count, dim3(cg), dim3(1024), 4 * (size_t)cells, s, n, dx, dy, dz, h, L);
+    hipLaunchKernelGGL(k_ls_count, dim3(cg), dim3(1024), 4 * (size_t)cells, s, n, dx, dy, dz, h,
+                       g->tune.sort_key == 2 ? 1 : 0, L);
     GV_TRY(launched(fn));
     hipLaunchKernelGGL(k_ls_scan, dim3(1), dim3(1024), 0, s, L, cells);
     GV_TRY(launched(fn));
     hipLaunchKernelGGL(k_ls_scatter, dim3(stream_grid(n)), dim3(kBlock), 0, s, n, L);
     GV_TRY(launched(fn));
   }
-  const bool refill = g->tune.lane_refill == 2;
-  const LaneKernel k = select_lane_kernel(g->has_bool, fp32, phys, refill);
+  // defaults: 4 waves and staged outputs for navigation; 3 waves, unstaged,
+  // for physics-limited steps (more live state per lane)
+  const int waves = g->tune.lane_waves ? g->tune.lane_waves : (phys ? 3 : 4);
+  const bool stage = g->tune.lane_stage ? g->tune.lane_stage == 2 : !phys;
+  const LaneKernel k = select_lane_kernel(g->has_bool, fp32, phys, waves, stage);
   int64_t grid = g->tune.lane_grid > 0 ? g->tune.lane_grid
                                        : (int64_t)resident_blocks(g, reinterpret_cast<const void*>(k)) * g->n_cu;
   grid = std::max<int64_t>(1, std::min<int64_t>(grid, (n + 255) / 256));
@@ -1549,8 +1558,11 @@ extern "C" int gv_set_tuning(gv_geom* g, const gv_tuning* t) {
   if (t->transport < 0 || t->transport > 2) return fail(GV_EINVAL, "%s: transport %d not 0, 1 or 2", fn, t->transport);
   if (t->sort_bits < -1 || t->sort_bits > kSortMaxBits)
     return fail(GV_EINVAL, "%s: sort_bits %d not in [-1, %d]", fn, t->sort_bits, kSortMaxBits);
-  if (t->lane_refill < 0 || t->lane_refill > 2)
-    return fail(GV_EINVAL, "%s: lane_refill %d not 0, 1 or 2", fn, t->lane_refill);
+  if (t->sort_key < 0 || t->sort_key > 2) return fail(GV_EINVAL, "%s: sort_key %d not 0, 1 or 2", fn, t->sort_key);
+  if (!(t->lane_waves == 0 || t->lane_waves == 3 || t->lane_waves == 4))
+    return fail(GV_EINVAL, "%s: lane_waves %d not 0, 3 or 4", fn, t->lane_waves);
+  if (t->lane_stage < 0 || t->lane_stage > 2)
+    return fail(GV_EINVAL, "%s: lane_stage %d not 0, 1 or 2", fn, t->lane_stage);
   if (t->lane_grid < 0) return fail(GV_EINVAL, "%s: lane_grid %d < 0", fn, t->lane_grid);
   g->tune = *t;
   t_err.clear();

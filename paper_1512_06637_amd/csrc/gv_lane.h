@@ -18,14 +18,15 @@
 //    arithmetic is its own.
 //  * persistent workers -- as many workgroups as the device holds at once;
 //    each wavefront takes 64 consecutive places of the order from an atomic
-//    counter and steps its tracks to the end, then takes the next 64.  With
-//    refill, a lane whose track has ended takes a new place at once (one
-//    atomic per wavefront and refill), so no lane idles until the wavefront's
-//    longest track ends.
+//    counter and steps its tracks to the end, then takes the next 64.  The
+//    64 tracks of a wavefront start together, so every step is taken by all
+//    of its live lanes at once.  (Giving a lane whose track has ended a new
+//    track at once was measured 2x slower: the lanes then run different
+//    volume classes at every step.)
 //
 // Every output row is written by the lane that owns the track, so the results
-// (sequences, lengths, counts, flags) are independent of the order, the grid
-// and the refill policy.
+// (sequences, lengths, counts, flags) are independent of the order and the
+// grid.
 #pragma once
 #include "gv_step.h"
 
@@ -62,6 +63,18 @@ __device__ __forceinline__ uint32_t direction_key(double dx, double dy, double d
   return spread_bits7(iu) | (spread_bits7(iv) << 1);
 }
 
+// Direction key aligned with the z axis: cos(theta) = dz cut into 2^h
+// equal-area bands, the azimuth (pseudo-angle of (dx, dy)) into 2^h sectors,
+// bands outermost, so that consecutive keys share a band and neighbouring
+// azimuths -- the symmetry of detectors built around the z axis (layers in r,
+// modules in phi).  Only the order of the work depends on it.
+__device__ __forceinline__ uint32_t direction_key_zaxis(double dx, double dy, double dz, int h) {
+  const int side = 1 << h, m = side - 1;
+  const uint32_t it = (uint32_t)min(m, max(0, (int)((dz + 1.0) * (0.5 * side))));
+  const uint32_t ip = (uint32_t)min(m, max(0, (int)(pseudo_angle(dx, dy) * (0.25 * side))));
+  return it << h | ip;
+}
+
 // Lane-transport control words (device workspace): cnt[cells] key counts,
 // then the running place of each cell during the scatter, and the work
 // counter the persistent workers take places from.
@@ -78,16 +91,17 @@ __global__ void k_ls_clear(LaneCtl L, int cells) {
   if (gtid() == 0) *L.queue = 0u;
 }
 
-// Key of every track and the per-key counts (workgroup histogram in LDS,
-// 4 cells bytes of dynamic LDS, one global atomic per workgroup and key).
+// Key of every track (z-axis or octahedral) and the per-key counts
+// (workgroup histogram in LDS, 4 cells bytes of dynamic LDS, one global
+// atomic per workgroup and key).
 __global__ void k_ls_count(int64_t n, const double* __restrict__ dx, const double* __restrict__ dy,
-                           const double* __restrict__ dz, int h, LaneCtl L) {
+                           const double* __restrict__ dz, int h, int zaxis, LaneCtl L) {
   extern __shared__ uint32_t key_hist[];
   const int cells = 1 << (2 * h);
   for (int c = threadIdx.x; c < cells; c += blockDim.x) key_hist[c] = 0u;
   __syncthreads();
   for (int64_t i = gtid(); i < n; i += gstride()) {
-    const uint32_t k = direction_key(dx[i], dy[i], dz[i], h);
+    const uint32_t k = zaxis ? direction_key_zaxis(dx[i], dy[i], dz[i], h) : direction_key(dx[i], dy[i], dz[i], h);
     L.key[i] = k;
     atomicAdd(&key_hist[k], 1u);
   }
@@ -172,26 +186,42 @@ __device__ __forceinline__ bool lane_begin(const DevGeom& G, LaneTrack& T, int64
   return true;
 }
 
+// A lane's column of its wavefront's output staging in LDS: entry j of the
+// column holds the j-th step since the last flush, 64 entries apart (the 64
+// lanes write one row of the buffer per step, without bank conflicts).
+struct LaneStage {
+  double* st;
+  int32_t* pv;
+};
+
 // One step of a carried track; returns true when the track has ended (left
 // the world, stuck, or out of steps), after writing its count and flags.
-template <bool F32, bool PHYS, bool B>
-__device__ __forceinline__ bool lane_step(const DevGeom& G, LaneTrack& T, int max_steps, int32_t* __restrict__ out_pv,
-                                          double* __restrict__ out_step, int32_t* __restrict__ out_nsteps,
-                                          uint32_t* __restrict__ out_flags, const PhysArgs& P,
-                                          int8_t* __restrict__ out_proc) {
+// With ST > 0 the step length and next volume go to the lane's LDS column and
+// are written to the track's rows ST steps at a time (and at its end), so the
+// row stores of a lane come in runs of consecutive addresses.
+template <bool F32, bool PHYS, bool B, int ST>
+__device__ __forceinline__ bool lane_step(const DevGeom& G, LaneTrack& T, int lv, int max_steps,
+                                          int32_t* __restrict__ out_pv, double* __restrict__ out_step,
+                                          int32_t* __restrict__ out_nsteps, uint32_t* __restrict__ out_flags,
+                                          const PhysArgs& P, int8_t* __restrict__ out_proc, LaneStage S) {
   NoWork w;
   int nx;
   double st;
   if (PHYS) {
     int proc;
-    st = step_physics<F32, B>(G, G.pv_lv[T.pv], T.pv, T.p, T.d, (uint32_t)T.i, T.k, P, T.safe, &nx, &proc, &T.fl, w);
+    st = step_physics<F32, B>(G, lv, T.pv, T.p, T.d, (uint32_t)T.i, T.k, P, T.safe, &nx, &proc, &T.fl, w);
     if (out_proc) out_proc[(size_t)T.i * max_steps + T.k] = (int8_t)proc;
   } else {
-    st = step_culled<F32, B>(G, G.pv_lv[T.pv], T.pv, T.p, T.d, &nx, &T.fl, w);
+    st = step_culled<F32, B>(G, lv, T.pv, T.p, T.d, &nx, &T.fl, w);
     T.p = advance(T.p, st, T.d);
   }
-  out_step[(size_t)T.i * max_steps + T.k] = st;
-  out_pv[(size_t)T.i * (max_steps + 1) + T.k + 1] = nx;
+  if (ST == 0) {
+    out_step[(size_t)T.i * max_steps + T.k] = st;
+    out_pv[(size_t)T.i * (max_steps + 1) + T.k + 1] = nx;
+  } else {
+    S.st[64 * (T.k % ST)] = st;
+    S.pv[64 * (T.k % ST)] = nx;
+  }
   ++T.k;
   bool end = nx < 0;
   if (!end) {
@@ -205,6 +235,15 @@ __device__ __forceinline__ bool lane_step(const DevGeom& G, LaneTrack& T, int ma
     }
   }
   T.pv = nx;
+  if (ST > 0 && (end || T.k % ST == 0)) {
+    const int m = (T.k - 1) % ST + 1, k0 = T.k - m;
+    double* rs = out_step + (size_t)T.i * max_steps + k0;
+    int32_t* rp = out_pv + (size_t)T.i * (max_steps + 1) + k0 + 1;
+    for (int j = 0; j < m; ++j) {
+      rs[j] = S.st[64 * j];
+      rp[j] = S.pv[64 * j];
+    }
+  }
   if (end) {
     out_nsteps[T.i] = T.k;
     out_flags[T.i] = T.fl;
@@ -214,59 +253,43 @@ __device__ __forceinline__ bool lane_step(const DevGeom& G, LaneTrack& T, int ma
 
 // Persistent whole-track transport.  Places 0..n-1 of the order (perm, or the
 // identity when perm is NULL) are handed out from *queue, which must be 0 at
-// launch.  REFILL: a lane whose track ended takes the next place at once;
-// otherwise a wavefront takes 64 places when all of its tracks have ended.
-template <bool F32, bool PHYS, bool B, bool REFILL>
-__global__ void __launch_bounds__(256) k_lane_transport(
+// launch: a wavefront takes 64 places at a time and carries their tracks to
+// their ends.  WV: waves per SIMD the kernel is built for (its register
+// budget); ST: steps staged in LDS per lane before its rows are written (0:
+// every step writes its rows at once).  (Taking each step one logical volume
+// at a time, so that the volume's tables are wavefront-uniform as in a
+// basket, was measured 2.3x slower: a wavefront's lanes spread over several
+// volumes -- a track that crossed a module is two steps behind one that
+// passed between modules -- and each volume then runs with few lanes.)
+template <bool F32, bool PHYS, bool B, int WV, int ST>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WV))) k_lane_transport(
     DevGeom G, int64_t n, const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
     const double* __restrict__ dx, const double* __restrict__ dy, const double* __restrict__ dz,
     const int32_t* __restrict__ start_pv, const int32_t* __restrict__ perm, uint32_t* __restrict__ queue,
     int max_steps, int32_t* __restrict__ out_pv, double* __restrict__ out_step, int32_t* __restrict__ out_nsteps,
     uint32_t* __restrict__ out_flags, PhysArgs P, int8_t* __restrict__ out_proc) {
+  constexpr int kStage = ST > 0 ? 4 * ST * 64 : 1;  // 4 wavefronts per workgroup
+  __shared__ double stage_st[kStage];
+  __shared__ int32_t stage_pv[kStage];
   const int lane = __lane_id();
+  const int wbase = ST > 0 ? (int)(threadIdx.x / 64) * ST * 64 + lane : 0;
+  const LaneStage S{stage_st + wbase, stage_pv + wbase};
   LaneTrack T;
-  if (!REFILL) {
-    for (;;) {
-      uint32_t b = 0;
-      if (lane == 0) b = atomicAdd(queue, 64u);
-      const int64_t base = (int64_t)__shfl(b, 0);
-      if (base >= n) break;
-      const int64_t j = base + lane;
-      if (j < n) {
-        const int64_t i = perm ? perm[j] : j;
-        if (lane_begin<B>(G, T, i, x, y, z, dx, dy, dz, start_pv, max_steps, out_pv, out_nsteps, out_flags)) {
-          while (!lane_step<F32, PHYS, B>(G, T, max_steps, out_pv, out_step, out_nsteps, out_flags, P, out_proc)) {
-          }
-        }
-      }
-    }
-    return;
-  }
-  bool has = false, drained = false;
   for (;;) {
-    if (!drained) {
-      const uint64_t need = __ballot(!has);
-      if (need) {
-        const int c = __popcll(need);
-        const int leader = __ffsll((unsigned long long)need) - 1;
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(queue, (uint32_t)c);
-        base = __shfl(base, leader);
-        if ((int64_t)base + c >= n) drained = true;
-        if (!has) {
-          const int64_t j = (int64_t)base + __popcll(need & ((1ull << lane) - 1ull));
-          if (j < n) {
-            const int64_t i = perm ? perm[j] : j;
-            has = lane_begin<B>(G, T, i, x, y, z, dx, dy, dz, start_pv, max_steps, out_pv, out_nsteps, out_flags);
-          }
-        }
+    uint32_t b = 0;
+    if (lane == 0) b = atomicAdd(queue, 64u);
+    const int64_t base = (int64_t)__shfl(b, 0);
+    if (base >= n) break;
+    const int64_t j = base + lane;
+    bool live = false;
+    if (j < n) {
+      const int64_t i = perm ? perm[j] : j;
+      live = lane_begin<B>(G, T, i, x, y, z, dx, dy, dz, start_pv, max_steps, out_pv, out_nsteps, out_flags);
+    }
+    if (live)
+      while (!lane_step<F32, PHYS, B, ST>(G, T, G.pv_lv[T.pv], max_steps, out_pv, out_step, out_nsteps, out_flags, P,
+                                          out_proc, S)) {
       }
-    }
-    if (__ballot(has) == 0) {
-      if (drained) break;
-      continue;  // every new track of this round started outside the world
-    }
-    if (has) has = !lane_step<F32, PHYS, B>(G, T, max_steps, out_pv, out_step, out_nsteps, out_flags, P, out_proc);
   }
 }
 

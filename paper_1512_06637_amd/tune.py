@@ -3,8 +3,8 @@
 The choices are the fields of gvgeom.h's gv_tuning: the form of the
 transport (lane form: one persistent kernel carrying each track in one lane,
 tracks ordered by a direction key; basket form: regrouping by volume before
-every step), the lane form's direction cells, refill policy and persistent
-grid, the basket form's workgroup counts, direction cells and register
+every step), the lane form's direction key and cells, register budget, output
+staging and persistent grid, the basket form's workgroup counts, direction cells and register
 budget, and the block size and workgroup cap of the one-lane-per-track
 kernels (solid-level queries).  None of them changes a result; the tuner
 checks that on every candidate (bitwise-equal outputs) and keeps the fastest,
@@ -32,9 +32,11 @@ CACHE = os.path.join(HERE, "tuned.json")
 # candidate values per knob (0 / -1 = the library default)
 LANE_FORM_SPACE = {
     "transport": [2],
-    "sort_bits": [-1, 0, 4, 5, 7],
-    "lane_refill": [0, 2],
-    "lane_grid": [0, 512, 1024, 2048],
+    "sort_bits": [-1, 0, 5, 6],
+    "sort_key": [0, 2],
+    "lane_waves": [0, 3, 4],
+    "lane_stage": [0, 1, 2],
+    "lane_grid": [0, 1024, 2048],
 }
 BASKET_FORM_SPACE = {
     "transport": [1],
