@@ -181,6 +181,23 @@ int nav_transport(gv_geom* g, int64_t n, const double* x, const double* y, const
                   int32_t max_steps, int32_t* out_pv, double* out_step, int32_t* out_nsteps,
                   uint32_t* out_flags, int32_t precision, void* stream);
 
+/* Allocation-free nav_transport, for callers that cannot allocate device
+ * memory: code under HIP graph capture, serving loops, harnesses that forbid
+ * allocation.  Same arguments, definitions and outputs as nav_transport (its
+ * lane form, whatever the tuned transport field says), but the keys, order and
+ * counters live in a static device array of the library, 16.06 MiB per device
+ * and held until the process ends, so the call allocates nothing and needs no
+ * earlier call.  1 <= n <= 2,097,152 (GV_EINVAL beyond; n == 0 is a no-op).
+ * Every call on one device shares that device's array, which keeps the last
+ * call's contents; each call clears what must start at zero.  Calls that
+ * overlap on one device (several streams or threads) race on the array and
+ * must be serialised by the caller.  No profiling events or work counters
+ * (gv_profile) are recorded. */
+int nav_transport_noalloc(gv_geom* g, int64_t n, const double* x, const double* y, const double* z,
+                          const double* dx, const double* dy, const double* dz, const int32_t* start_pv,
+                          int32_t max_steps, int32_t* out_pv, double* out_step, int32_t* out_nsteps,
+                          uint32_t* out_flags, int32_t precision, void* stream);
+
 /* ------------------------------------------------- physics-limited transport */
 /* Materials for physics-limited steps: n_mat materials with number density
  * density[m] and, for each of n_proc (1..16) processes, a cross section

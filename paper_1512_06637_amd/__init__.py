@@ -48,6 +48,7 @@ _SIGS = {
     "basket_nav_safety": [_P, _I64, _P, _P, _P, _P, _P, _I32, _P],
     "basket_nav_inside": [_P, _I64, _P, _P, _P, _P, _P, _P],
     "nav_transport": [_P, _I64] + [_P] * 7 + [_I32] + [_P] * 4 + [_I32, _P],
+    "nav_transport_noalloc": [_P, _I64] + [_P] * 7 + [_I32] + [_P] * 4 + [_I32, _P],
     "gv_profile": [_P, C.c_int],
     "gv_profile_read": [_P, _P, _P, _P],
     "gv_set_tuning": [_P, _P],
@@ -335,8 +336,11 @@ class Geometry:
             _stream()))
         return out
 
-    def transport(self, x, y, z, dx, dy, dz, start_pv=None, max_steps=128, out=None, precision=FP64):
-        """Returns dict(pv [n, max_steps+1] int32, step [n, max_steps] f64, nsteps, flags)."""
+    def transport(self, x, y, z, dx, dy, dz, start_pv=None, max_steps=128, out=None, precision=FP64,
+                  noalloc=False):
+        """Returns dict(pv [n, max_steps+1] int32, step [n, max_steps] f64, nsteps, flags).
+        noalloc: call nav_transport_noalloc (library scratch, no allocation;
+        `out` must then be given to allocate nothing here either)."""
         torch = _torch()
         n = _n(x, y, z, dx, dy, dz, start_pv)
         f64 = torch.float64
@@ -348,7 +352,8 @@ class Geometry:
                 "flags": torch.empty(n, dtype=torch.int32, device=x.device),
             }
         a = [_dev(v, f64, nm) for v, nm in zip((x, y, z, dx, dy, dz), ("x", "y", "z", "dx", "dy", "dz"))]
-        _check("nav_transport", lib().nav_transport(
+        fn = "nav_transport_noalloc" if noalloc else "nav_transport"
+        _check(fn, getattr(lib(), fn)(
             self._h, n, *a, _opt(start_pv, torch.int32, "start_pv"), max_steps,
             _dev(out["pv"], torch.int32, "pv", n * (max_steps + 1)), _dev(out["step"], f64, "step", n * max_steps),
             _dev(out["nsteps"], torch.int32, "nsteps", n), _dev(out["flags"], torch.int32, "flags", n), precision,

@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -39,6 +40,40 @@ static int hip_fail(hipError_t e, const char* what) {
 }
 
 extern "C" const char* gv_last_error(void) { return t_err.c_str(); }
+
+// ------------------------------------------------- allocation-free scratch
+// Scratch of nav_transport_noalloc: the lane form's keys, order and counters
+// for up to kNoAllocMaxTracks tracks (16.06 MiB), one copy per device, held
+// until the process ends.  In host code `scratch` names a host-side stand-in:
+// kernels get the device address that hipGetSymbolAddress returned for each
+// device (noalloc_scratch), never the symbol itself.
+constexpr int64_t kNoAllocMaxTracks = (int64_t)1 << 21;
+constexpr size_t kScratchBytes = 2 * 4 * (size_t)kNoAllocMaxTracks + 4 * (size_t)kSortMaxCells + 256;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex scratch_mu;
+static void* scratch_addr[kMaxDevices] = {};
+
+// Looks up (once per device, with that device current) the device address of
+// this device's copy of the scratch array.
+static int init_noalloc_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(GV_EHIP, "geom_load: device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (scratch_addr[dev]) return GV_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) return hip_fail(e, "geom_load: hipGetSymbolAddress(scratch)");
+  scratch_addr[dev] = p;
+  return GV_OK;
+}
+
+static void* noalloc_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  return scratch_addr[dev];
+}
+
 
 // --------------------------------------------------------------- geometry
 struct gv_geom {
@@ -669,6 +704,10 @@ extern "C" int geom_load(const void* blob, size_t nbytes, gv_geom** out) {
     }
     e = hipDeviceGetAttribute(&g->n_cu, hipDeviceAttributeMultiprocessorCount, g->device);
     if (e != hipSuccess || g->n_cu < 1) g->n_cu = 256;
+    if (init_noalloc_scratch(g->device) != GV_OK) {
+      delete g;
+      return GV_EHIP;
+    }
     e = hipMalloc(&g->dmem, total);
     if (e != hipSuccess) {
       delete g;
@@ -1463,6 +1502,27 @@ extern "C" int nav_transport_phys(gv_geom* g, int64_t n, const double* x, const 
   return transport_common("nav_transport_phys", g, n, x, y, z, dx, dy, dz, start_pv, max_steps, out_pv, out_step,
                           out_nsteps, out_flags, precision, true,
                           PhysArgs{seed, (options & GV_PHYS_SAFETY_SHORTCUT) ? 1 : 0}, out_proc, stream);
+}
+
+extern "C" int nav_transport_noalloc(gv_geom* g, int64_t n, const double* x, const double* y, const double* z,
+                                     const double* dx, const double* dy, const double* dz, const int32_t* start_pv,
+                                     int32_t max_steps, int32_t* out_pv, double* out_step, int32_t* out_nsteps,
+                                     uint32_t* out_flags, int32_t precision, void* stream) {
+  const char* fn = "nav_transport_noalloc";
+  GV_TRY(transport_args(fn, g, n, x, y, z, dx, dy, dz, start_pv, max_steps, out_pv, out_step, out_nsteps, out_flags,
+                        precision, false));
+  if (n > kNoAllocMaxTracks)
+    return fail(GV_EINVAL, "%s: n %lld exceeds the scratch's %lld tracks", fn, (long long)n,
+                (long long)kNoAllocMaxTracks);
+  if (n == 0) return GV_OK;
+  void* p = noalloc_scratch(g->device);
+  if (!p) return fail(GV_ESTATE, "%s: no scratch address for device %d", fn, g->device);
+  DeviceGuard dgd(g->device);
+  static_assert(2 * 4 * (size_t)kNoAllocMaxTracks + 4 * (size_t)kSortMaxCells + 4 <= kScratchBytes,
+                "scratch holds the lane form's arrays");
+  const LaneCtl L = carve_lane_ctl(p, kNoAllocMaxTracks);
+  return lane_transport(g, L, n, x, y, z, dx, dy, dz, start_pv, max_steps, out_pv, out_step, out_nsteps, out_flags,
+                        precision == GV_FP32_REFINE, false, PhysArgs{0, 0}, nullptr, (hipStream_t)stream, fn, false);
 }
 
 extern "C" int geom_set_materials(gv_geom* g, int32_t n_mat, int32_t n_proc, const double* density,
