@@ -158,9 +158,11 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(path=os.path.join(ROOT, "profiles", "k_bt_step_detector_2p20_traffic.txt")):
-    """HBM bytes per k_bt_step launch from the committed counter summary, or
-    None when the kernel sources changed since the counters were taken."""
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` (k_lane_transport or k_bt_step) on this
+    workload from the committed counter summary, or None when the kernel
+    sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_detector_2p20_traffic.txt")
     try:
         txt = open(path).read()
     except OSError:
@@ -528,20 +530,24 @@ def main():
     ms = _time_calls(run, args.steps)
     wall = time.perf_counter() - t0
 
-    # the per-step kernel alone: HIP events around each of its launches, on the
-    # stream the library launches on, over the same number of calls
+    # the transport kernel alone (the persistent lane kernel, or each launch of
+    # the basket form's per-step kernel): HIP events around its launches, on
+    # the stream the library launches on, over the same number of calls
+    lane_form = g.get_tuning()["transport"] != 1
+    kernel = "k_lane_transport" if lane_form else "k_bt_step"
     g.profile(events=True)
     for _ in range(args.steps):
         run()
     step_ms_total, launches, _ = g.profile_read()
-    # operation counts: one call of the counting instance of the step kernel
+    # operation counts: one call of the basket form's counting instance (every
+    # track takes the same steps, with the same daughter work, in both forms)
     g.profile(work=True)
     run()
     _, _, work = g.profile_read()
     g.profile()
     run()  # outputs of the production kernels for the parity check below
     torch.cuda.synchronize()
-    step_ms = step_ms_total / args.steps  # step-kernel time per transport
+    step_ms = step_ms_total / args.steps  # transport-kernel time per transport
     launches_per = launches / args.steps
     launch_ms = step_ms_total / max(1, launches)
 
@@ -554,15 +560,15 @@ def main():
     ops_plain = R.detector_ops(world, layer, module)
     ops = R.detector_ops_culled(world, layer, module, work)
     alg_bytes = R.transport_bytes(n, total_steps)
-    design_bytes = total_steps * R.STEP_DESIGN_BYTES
+    design_bytes = alg_bytes + 8 * n if lane_form else total_steps * R.STEP_DESIGN_BYTES
     intensity = ops / alg_bytes
     balance = R.PEAK_FP64_OPS / R.PEAK_HBM
     achieved = ops / (step_ms * 1e-3)  # = ops per launch / average launch duration
-    traffic = measured_traffic()
+    traffic = measured_traffic(kernel)
     roofs = None if args.no_probes else roof_probes()
     roofline = {
         "bound": "alu" if intensity > balance else "hbm",
-        "kernel": "k_bt_step",
+        "kernel": kernel,
         "achieved": achieved / 1e12,
         "peak": R.PEAK_FP64_OPS / 1e12,
         "unit": "T FP64 lane-ops/s (an FMA counts 1; peak = 256 CU x 64 lanes x 2.4 GHz = 78.6 TFLOP/s)",
@@ -584,7 +590,9 @@ def main():
                 "measured_traffic_over_algorithmic": (traffic * launches_per / alg_bytes) if traffic else None,
                 "frac_measured_traffic": (traffic / (launch_ms * 1e-3) / R.PEAK_HBM) if traffic else None},
         "accounting": "ops = the culled navigator's own work from its operation counters x the per-operation "
-                      "table of roofline.py; bytes = inputs once + outputs once (transport_bytes)",
+                      "table of roofline.py; bytes = inputs once + outputs once (transport_bytes); design bytes = "
+                      "those plus the lane form's direction keys and order (8 B per track), or the basket form's "
+                      "152 B per track-step",
     }
     res = {
         "metric": "track-steps/s",
