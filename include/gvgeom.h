@@ -297,8 +297,9 @@ int gv_probe_fma64(double* out, int64_t n_lanes, int32_t iters, void* stream);
  *                 per track);
  *   step_waves    3 or 4: waves per SIMD the navigation step kernel is built
  *                 for (default 4);
- *   transport     1 basket form, 2 lane form (default: lane; the basket form
- *                 needs n >= 8,192, smaller batches take the lane form);
+ *   transport     1 basket form, 2 lane form (default: lane, or basket for
+ *                 geometries holding composites; the basket form needs
+ *                 n >= 8,192, smaller batches take the lane form);
  *   sort_bits     0..7: the lane form's direction cells are 2^sort_bits x
  *                 2^sort_bits (0: no ordering, tracks in index order;
  *                 default 7);

@@ -1462,9 +1462,12 @@ int transport_common(const char* fn, gv_geom* g, int64_t n, const double* x, con
   DeviceGuard dgd(g->device);
   const bool fp32 = precision == GV_FP32_REFINE;
   const hipStream_t s = (hipStream_t)stream;
-  // the basket form when it is asked for (or its work counters are), else
-  // the lane form
-  if ((g->tune.transport == 1 || g->prof_work) && n >= kBasketMin && g->n_lv <= 4096)
+  // the basket form when it is asked for (or its work counters are), and by
+  // default for geometries holding composites (their tracks start in several
+  // volumes, which a direction order mixes in every wavefront: 2.9 ms against
+  // 3.7 ms for the lane form on the composite workload); else the lane form
+  const bool basket = g->tune.transport == 1 || g->prof_work || (g->tune.transport == 0 && g->has_bool);
+  if (basket && n >= kBasketMin && g->n_lv <= 4096)
     return basket_transport(g, n, x, y, z, dx, dy, dz, start_pv, max_steps, out_pv, out_step, out_nsteps, out_flags,
                             fp32, phys, P, out_proc, s);
   // Under stream capture nothing may be allocated: the workspace must already
