@@ -237,8 +237,16 @@ def solids_leg(copies=8, replays=10):
         for q, f in calls.items():
             ms = graph_ms(f, copies, replays)
             gbs = n * R.SOLID_BYTES[q] / (ms * 1e-3) / 1e9
+            ops = None
+            if name == "pcon":  # the walk's own work, counted in one call of the query
+                g.profile(work=True)
+                f(0)
+                _, _, work = g.profile_read()
+                g.profile()
+                ops = R.pcon_ops(q, n, work)
+                r.setdefault("walk_counts", {})[q] = work[28:33]
             r[q] = {"us_per_call": ms * 1e3, "tracks_per_s": n / (ms * 1e-3), "GB_s": gbs}
-            r[q].update(R.solid_roofline(name, q, n, ms * 1e3))
+            r[q].update(R.solid_roofline(name, q, n, ms * 1e3, ops=ops))
         r["separate_vs_fused_time"] = sum(r[q]["us_per_call"] for q in ("inside", "safety", "dist_in", "dist_out")) \
             / r["fused"]["us_per_call"]
         res[name] = r

@@ -233,15 +233,23 @@ int nav_transport_phys(gv_geom* g, int64_t n, const double* x, const double* y, 
 /* ------------------------------------------------------------ measurement */
 
 /* Measurement.  flags GV_PROF_EVENTS: nav_transport records a pair of HIP
- * events on the caller's stream around every launch of its per-step kernel
- * (the production kernel, so the times are those of unprofiled calls).
- * GV_PROF_WORK: basket transports run the per-step kernel instance that keeps
- * operation counters (a ballot and an LDS atomic per counted event, so slower;
- * geometries without composites only).  0 turns both off.
+ * events on the caller's stream around every launch of its transport kernel
+ * (the persistent lane kernel, or each step kernel of the basket form: the
+ * production kernels, so the times are those of unprofiled calls).
+ * GV_PROF_WORK: transports of 8,192 tracks or more run the basket form with
+ * the per-step kernel instance that keeps operation counters (a ballot and an
+ * LDS atomic per counted event, so slower; geometries without composites
+ * only; every track takes the same steps with the same work in both forms),
+ * and basket_distance / basket_solid_all on a polycone are followed by a
+ * kernel that counts their walks' work (outputs untouched).  0 turns both off.
  * gv_profile_read waits for the events and returns the summed
  * kernel milliseconds and the number of launches since the last read (then
- * forgets them), and, if `work` is not NULL, the operation counts of the last
- * basket transport run with GV_PROF_WORK (host array of 28 uint64: [0] steps taken, [1] daughter
+ * forgets them), and, if `work` is not NULL, a host array of 33 uint64: the
+ * operation counts of the last basket transport run with GV_PROF_WORK, then
+ * those of the polycone queries since the last read ([28] sections whose cone
+ * intersections DistanceToIn walks computed, [29] the same for DistanceToOut,
+ * [30] DistanceToIn rays rejected by the bounding cylinder, [31] DistanceToIn
+ * walks, [32] DistanceToOut walks; then cleared).  Transport counters: [0] steps taken, [1] daughter
  * bounding-box tests, [2+t] daughter lower-bound checks, [8+t] daughter
  * DistanceToIn evaluations in culled loops (and radial walks), [14+t]
  * DistanceToIn evaluations in plain loops, t = daughter solid type 0..5

@@ -21,7 +21,7 @@ OUTSIDE, SURFACE, INSIDE = 0, 1, 2
 TO_IN, TO_OUT = 0, 1
 SAFETY_AUTO, SAFETY_IN, SAFETY_OUT = 0, 1, 2
 FP64, FP32_REFINE = 0, 1
-WORK_N = 28  # work counters returned by gv_profile_read
+WORK_N = 33  # work counters returned by gv_profile_read (28 transport, 5 polycone)
 PROF_EVENTS, PROF_WORK = 1, 2
 TUNING_FIELDS = ("step_grid", "scatter_grid", "cell_bits", "solid_block", "solid_grid", "step_waves",
                  "transport", "sort_bits", "sort_key", "lane_waves", "lane_stage", "lane_grid")
@@ -294,7 +294,10 @@ class Geometry:
         t = daughter solid type, [20] culled track-steps screened in FP32, [21] culled
         track-steps screened in FP64, [22] physics-limited steps, [23] of which taken
         by the safety short-cut, [24] radial-order lookups, [25] radial crossing
-        bounds, [26] phi-sector lookups, [27] sectors read)."""
+        bounds, [26] phi-sector lookups, [27] sectors read; then the polycone
+        queries' [28] DistanceToIn sections computed, [29] DistanceToOut sections
+        computed, [30] DistanceToIn bounding-cylinder rejects, [31] DistanceToIn
+        walks, [32] DistanceToOut walks)."""
         ms = C.c_double(0.0)
         launches = C.c_int64(0)
         work = (C.c_uint64 * WORK_N)()

@@ -113,6 +113,7 @@ struct gv_geom {
   int n_cu = 0;  // compute units of the device
   std::pair<const void*, int> occ[16] = {};  // resident workgroups per CU of persistent kernels
   int n_occ = 0;
+  unsigned long long* pcon_work = nullptr;  // [5] polycone work counters (inside dmem)
   int ws_nl = 0;  // buckets the workspace was sized for
   std::vector<hipEvent_t> prof_ev;  // pairs around step-kernel launches
   size_t prof_used = 0;
@@ -238,6 +239,18 @@ bool derive(int type, const double* q, int nq, std::vector<double>& out, std::st
         in[j] = (rmin[j] > 0 || rmin[j + 1] > 0) ? 1.0 : 0.0;
       }
       for (auto* a : {&bo, &co, &bi, &ci, &in}) out.insert(out.end(), a->begin(), a->end());
+      // safety segments of the meridian polygon: 1/|e|^2 of each outer and
+      // inner side segment and of the two caps (0 for a degenerate segment)
+      auto inv_len2 = [](double er, double ez) {
+        const double ll = er * er + ez * ez;
+        return ll > 0.0 ? 1.0 / ll : 0.0;
+      };
+      for (int j = 0; j + 1 < nz; ++j) out.push_back(inv_len2(rmax[j + 1] - rmax[j], z[j + 1] - z[j]));
+      for (int j = 0; j + 1 < nz; ++j) out.push_back(inv_len2(rmin[j + 1] - rmin[j], z[j + 1] - z[j]));
+      out.push_back(inv_len2(rmax[0] - rmin[0], 0.0));
+      out.push_back(inv_len2(rmax[nz - 1] - rmin[nz - 1], 0.0));
+      // bounding cylinder radius (the largest rmax) for the DistanceToIn reject
+      out.push_back(*std::max_element(rmax, rmax + nz));
       return true;
     }
     case kBool: {
@@ -686,7 +699,7 @@ extern "C" int geom_load(const void* blob, size_t nbytes, gv_geom** out) {
         {grp_box.data(), grp_box.size() * 8, 0},     {grp_box32.data(), grp_box32.size() * 4, 0},
         {lv_rad.data(), lv_rad.size() * 4, 0},       {rad_r2.data(), rad_r2.size() * 8, 0},
         {rad_k.data(), rad_k.size() * 4, 0},         {lv_phi.data(), lv_phi.size() * 4, 0},
-        {phi_mask.data(), phi_mask.size() * 8, 0}};
+        {phi_mask.data(), phi_mask.size() * 8, 0},   {nullptr, 5 * 8, 0}};
     size_t total = 0;
     for (auto& p : parts) {
       p.off = total;
@@ -694,7 +707,7 @@ extern "C" int geom_load(const void* blob, size_t nbytes, gv_geom** out) {
     }
     std::vector<unsigned char> host(total, 0);
     for (auto& p : parts)
-      if (p.bytes) std::memcpy(host.data() + p.off, p.src, p.bytes);
+      if (p.bytes && p.src) std::memcpy(host.data() + p.off, p.src, p.bytes);
     gv_geom* g = new (std::nothrow) gv_geom();
     if (!g) return fail(GV_ENOMEM, "geom_load: host allocation");
     hipError_t e = hipGetDevice(&g->device);
@@ -751,6 +764,7 @@ extern "C" int geom_load(const void* blob, size_t nbytes, gv_geom** out) {
     D.rad_k = (CQI)(base + parts[24].off);
     D.lv_phi = (CQI)(base + parts[25].off);
     D.phi_mask = (CQL)(base + parts[26].off);
+    g->pcon_work = (unsigned long long*)(base + parts[27].off);  // zeroed by the upload
     g->n_lv = n_lv;
     g->n_pv = (int)npv;
     g->n_place = n_place;
@@ -883,6 +897,17 @@ int check_nav_precision(const char* fn, int32_t precision) {
   return GV_OK;
 }
 
+// With GV_PROF_WORK, a polycone query is followed by the kernel that counts
+// its walk's work (profiling only; the query's outputs are untouched).
+int pcon_work(gv_geom* g, int32_t lv, int dir, int64_t n, const double* x, const double* y, const double* z,
+              const double* dx, const double* dy, const double* dz, hipStream_t s, const char* fn) {
+  if (!g->prof_work || g->lv_type[lv] != kPcon) return GV_OK;
+  const Shape sh = lane_shape(g, n);
+  hipLaunchKernelGGL(k_pcon_work, dim3(sh.grid), dim3(sh.block), 0, s, g->dg.par + g->lv_par[lv], dir, n, x, y, z,
+                     dx, dy, dz, g->pcon_work);
+  return launched(fn);
+}
+
 extern "C" int basket_inside(gv_geom* g, int32_t lv, int64_t n, const double* x, const double* y, const double* z,
                              int8_t* out, void* stream) {
   const char* fn = "basket_inside";
@@ -954,7 +979,8 @@ extern "C" int basket_distance(gv_geom* g, int32_t lv, int32_t dir, int64_t n, c
     GV_SOLID_SWITCH(g->lv_type[lv], CALL)
 #undef CALL
   }
-  return launched(fn);
+  GV_TRY(launched(fn));
+  return pcon_work(g, lv, dir, n, x, y, z, dx, dy, dz, s, fn);
 }
 
 extern "C" int basket_solid_all(gv_geom* g, int32_t lv, int64_t n, const double* x, const double* y, const double* z,
@@ -981,7 +1007,8 @@ extern "C" int basket_solid_all(gv_geom* g, int32_t lv, int64_t n, const double*
                      out_safety, out_dist_in, out_dist_out)
   GV_SOLID_SWITCH(g->lv_type[lv], CALL)
 #undef CALL
-  return launched(fn);
+  GV_TRY(launched(fn));
+  return pcon_work(g, lv, 2, n, x, y, z, dx, dy, dz, s, fn);
 }
 
 // ------------------------------------------------------- navigation entry points
@@ -1639,7 +1666,7 @@ extern "C" int gv_get_tuning(const gv_geom* g, gv_tuning* t) {
 }
 
 extern "C" int gv_profile_read(gv_geom* g, double* step_ms, int64_t* step_launches, uint64_t* work) {
-  static_assert(kWorkN == 28, "gvgeom.h documents 28 work counters");
+  static_assert(kWorkN == 28, "gvgeom.h documents 28 transport work counters, then 5 polycone ones");
   if (!g) return fail(GV_EINVAL, "gv_profile_read: geometry handle is NULL");
   DeviceGuard dgd(g->device);
   double ms = 0.0;
@@ -1655,13 +1682,14 @@ extern "C" int gv_profile_read(gv_geom* g, double* step_ms, int64_t* step_launch
   if (step_launches) *step_launches = (int64_t)(g->prof_used / 2);
   g->prof_used = 0;
   if (work) {
-    if (!g->ws) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess && g->ws) e = hipMemcpy(work, g->ctl.work, 8 * kWorkN, hipMemcpyDeviceToHost);
+    if (!g->ws)
       for (int i = 0; i < kWorkN; ++i) work[i] = 0;
-    } else {
-      hipError_t e = hipDeviceSynchronize();
-      if (e == hipSuccess) e = hipMemcpy(work, g->ctl.work, 8 * kWorkN, hipMemcpyDeviceToHost);
-      if (e != hipSuccess) return hip_fail(e, "gv_profile_read: counters");
-    }
+    if (e == hipSuccess) e = hipMemcpy(work + kWorkN, g->pcon_work, 8 * 5, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemset(g->pcon_work, 0, 8 * 5);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "gv_profile_read: counters");
   }
   return GV_OK;
 }

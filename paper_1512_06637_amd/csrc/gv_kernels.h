@@ -73,6 +73,50 @@ __global__ void k_solid_all(CQ q, int64_t n, const double* __restrict__ x,
   }
 }
 
+// Work of the polycone distance queries (profiling only, no outputs): per
+// track as one query (dir 0 in, 1 out) or the fused one (dir 2: DistanceToIn
+// of points not inside, DistanceToOut of points not outside) would run it,
+// adds to out[0] / out[1]
+// the sections whose cone intersections the DistanceToIn / DistanceToOut
+// walks compute, to out[2] the DistanceToIn rays rejected by the bounding
+// cylinder, and to out[3] / out[4] the walks (one atomic per wavefront and
+// counter).
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__global__ void k_pcon_work(CQ q, int dir, int64_t n, const double* __restrict__ x, const double* __restrict__ y,
+                            const double* __restrict__ z, const double* __restrict__ dx,
+                            const double* __restrict__ dy, const double* __restrict__ dz,
+                            unsigned long long* __restrict__ out) {
+  unsigned long long c[5] = {0, 0, 0, 0, 0};
+  for (int64_t i = gtid(); i < n; i += gstride()) {
+    const V3 p = ld3(x, y, z, i), d = ld3(dx, dy, dz, i);
+    const int code = code_of(Pcon::sgn(q, p));
+    if (dir != 1 && code != kInside) {
+      const Iv B = Pcon::bound_iv(Pcon::view(q), p, d);
+      if (Pcon::misses(B)) {
+        ++c[2];
+      } else {
+        int ns = 0;
+        (void)Pcon::walk<true>(q, p, d, true, &ns, fmax(B.lo, 0.0), B.hi);
+        c[0] += ns;
+        ++c[3];
+      }
+    }
+    if (dir != 0 && code != kOutside) {
+      int ns = 0;
+      (void)Pcon::walk<true>(q, p, d, false, &ns);
+      c[1] += ns;
+      ++c[4];
+    }
+  }
+  for (int k = 0; k < 5; ++k) {
+    const unsigned long long t = wave_sum(c[k]);
+    if (__lane_id() == 0 && t) atomicAdd(&out[k], t);
+  }
+}
+
 // ------------------------------------------------------------- navigation
 template <bool B>
 __global__ void k_locate(DevGeom G, int64_t n, const double* __restrict__ x, const double* __restrict__ y,

@@ -35,6 +35,9 @@ enum { kOutside = 0, kSurface = 1, kInside = 2 };
 // sphere: rmin rmax rmin^2 rmax^2
 // trd   : dx1 dx2 dy1 dy2 dz x0 tx cx y0 ty cy
 // pcon  : nz z[nz] rmin[nz] rmax[nz] bo[nz-1] co[nz-1] bi[nz-1] ci[nz-1] inner[nz-1]
+//         ilo[nz-1] ili[nz-1] icap[2] rbound  (ilo/ili/icap: 1/|e|^2 of the outer
+//         and inner side segments and of the caps of the meridian polygon, 0 for
+//         a degenerate one; rbound: the largest rmax)
 // bool  : op typeA offA typeC offC R[9] t[3], then the parts' own tables at
 //         offA / offC from the start of this one (R row major, x = R x_C + t)
 // phimode: 0 full circle, 1 wedge <= pi (intersection of two half-spaces),
@@ -545,7 +548,8 @@ struct Pcon {
   static constexpr int kType = kPcon;
   struct View {
     int nz;
-    CQ z, rmin, rmax, bo, co, bi, ci, inner;
+    CQ z, rmin, rmax, bo, co, bi, ci, inner, ilo, ili, icap;
+    double rbound;
   };
   __device__ static __forceinline__ View view(CQ q) {
     View v;
@@ -558,6 +562,10 @@ struct Pcon {
     v.bi = v.co + (v.nz - 1);
     v.ci = v.bi + (v.nz - 1);
     v.inner = v.ci + (v.nz - 1);
+    v.ilo = v.inner + (v.nz - 1);
+    v.ili = v.ilo + (v.nz - 1);
+    v.icap = v.ili + (v.nz - 1);
+    v.rbound = v.icap[2];
     return v;
   }
   // largest j with z_j <= z, clamped to [0, nz-2]
@@ -577,43 +585,61 @@ struct Pcon {
     t = fmax(t, v.z[0] - p.z);
     return fmax(t, p.z - v.z[v.nz - 1]);
   }
-  __device__ static __forceinline__ double seg(double r, double z, double r1, double z1, double r2, double z2) {
+  // squared distance from (r, z) to the segment (r1, z1)-(r2, z2), il =
+  // 1/|e|^2 (0 for a degenerate segment: its first point)
+  __device__ static __forceinline__ double seg2(double r, double z, double r1, double z1, double r2, double z2,
+                                                double il) {
     double er = r2 - r1, ez = z2 - z1, wr = r - r1, wz = z - z1;
-    double ll = er * er + ez * ez;
-    double u = ll > 0.0 ? fmin(fmax((wr * er + wz * ez) / ll, 0.0), 1.0) : 0.0;
+    double u = fmin(fmax((wr * er + wz * ez) * il, 0.0), 1.0);
     double qr = r1 + u * er - r, qz = z1 + u * ez - z;
-    return sqrt(qr * qr + qz * qz);
+    return qr * qr + qz * qz;
   }
-  // exact distance in the meridian plane to the boundary polygon
+  // exact distance in the meridian plane to the boundary polygon: the
+  // smallest squared distance over its segments, one square root at the end
+  // (the square root is monotone, so this equals the smallest root)
   __device__ static double boundary(CQ q, V3 p) {
     View v = view(q);
     double r = sqrt(p.x * p.x + p.y * p.y), z = p.z;
     double best = GV_INF;
     for (int j = 0; j + 1 < v.nz; ++j) {
-      best = fmin(best, seg(r, z, v.rmax[j], v.z[j], v.rmax[j + 1], v.z[j + 1]));
+      best = fmin(best, seg2(r, z, v.rmax[j], v.z[j], v.rmax[j + 1], v.z[j + 1], v.ilo[j]));
       if (v.rmin[j] > 0.0 || v.rmin[j + 1] > 0.0)
-        best = fmin(best, seg(r, z, v.rmin[j], v.z[j], v.rmin[j + 1], v.z[j + 1]));
+        best = fmin(best, seg2(r, z, v.rmin[j], v.z[j], v.rmin[j + 1], v.z[j + 1], v.ili[j]));
     }
     int e = v.nz - 1;
-    best = fmin(best, seg(r, z, v.rmin[0], v.z[0], v.rmax[0], v.z[0]));
-    best = fmin(best, seg(r, z, v.rmin[e], v.z[e], v.rmax[e], v.z[e]));
-    return best;
+    best = fmin(best, seg2(r, z, v.rmin[0], v.z[0], v.rmax[0], v.z[0], v.icap[0]));
+    best = fmin(best, seg2(r, z, v.rmin[e], v.z[e], v.rmax[e], v.z[e], v.icap[1]));
+    return sqrt(best);
   }
   __device__ static __forceinline__ double safety_out(CQ q, V3 p) { return boundary(q, p); }
   __device__ static __forceinline__ double safety_in(CQ q, V3 p) { return boundary(q, p); }
 
   // Walks the sections in the order the ray meets them and merges touching
   // pieces.  want_in: start of the first merged piece of length >= kTol;
-  // otherwise: end of the merged piece starting within kTol of t = 0.
-  __device__ static double walk(CQ q, V3 p, V3 d, bool want_in) {
+  // otherwise: end of the merged piece starting within kTol of t = 0.  The
+  // slabs of later sections start later along the ray, so once a section's
+  // slab starts beyond the current piece no later piece can join it: the
+  // piece is complete there, and the walk stops as soon as it has its answer.
+  // [t0, t1]: the part of the ray that can hold pieces (DistanceToIn: the
+  // bounding cylinder's interval), the walk starting at the section that holds
+  // the ray at t0 (one section earlier in the walk's direction when t0 > 0, so
+  // that the rounding of that point's z at a plane cannot skip a section) and
+  // stopping at the first section that starts beyond t1.  CNT: *nsec counts
+  // the sections whose cone intersections are computed (the work measurement
+  // of the profiling kernel; never in production).
+  template <bool CNT = false>
+  __device__ static double walk(CQ q, V3 p, V3 d, bool want_in, int* nsec = nullptr, double t0 = 0.0,
+                                double t1 = GV_INF) {
     View v = view(q);
-    int j0 = section(v, p.z), j1, step;
+    int j0 = section(v, t0 > 0.0 ? p.z + t0 * d.z : p.z), j1, step;
     if (d.z > 0.0) {
       j1 = v.nz - 2;
       step = 1;
+      if (t0 > 0.0 && j0 > 0) --j0;
     } else if (d.z < 0.0) {
       j1 = 0;
       step = -1;
+      if (t0 > 0.0 && j0 < v.nz - 2) ++j0;
     } else {
       // a horizontal ray only meets the section(s) whose slab holds z
       j1 = j0;
@@ -624,6 +650,12 @@ struct Pcon {
     bool have = false;
     for (int j = j0;; j += step) {
       Iv S = zrange(p.z, d.z, v.z[j], v.z[j + 1]);
+      if (S.lo > t1) break;  // beyond the part of the ray that can hold pieces
+      if (have && S.lo > ch) {  // no piece of this or a later section joins the current one
+        if (!want_in) return cl <= kTol ? fmax(ch, 0.0) : 0.0;
+        if (ch - cl >= kTol) return cl;
+      }
+      if (CNT) ++*nsec;
       Iv A = cone_interior(v.rmax[j], v.bo[j], v.z[j], S, p, d);
       Iv X = v.inner[j] != 0.0 ? cone_interior(v.rmin[j], v.bi[j], v.z[j], S, p, d) : iv_none();
       Pieces P;
@@ -653,9 +685,19 @@ struct Pcon {
     if (want_in) return (ch - cl >= kTol) ? cl : GV_INF;
     return cl <= kTol ? fmax(ch, 0.0) : 0.0;
   }
+  // The ray's interval inside the bounding cylinder (padded by 1e-6 mm, far
+  // above the rounding of either test) within the z range: every piece of the
+  // solid along the ray lies in it.
+  __device__ static __forceinline__ Iv bound_iv(const View& v, V3 p, V3 d) {
+    const double rb = v.rbound + 1e-6;
+    return iv_and(cyl_interior(rb * rb, p, d), zrange(p.z, d.z, v.z[0] - 1e-6, v.z[v.nz - 1] + 1e-6));
+  }
+  __device__ static __forceinline__ bool misses(Iv B) { return !(B.hi >= fmax(B.lo, 0.0)); }
   __device__ static double dist_in(CQ q, V3 p, V3 d) {
     if (sgn(q, p) < -kHalf) return -1.0;
-    return walk(q, p, d, true);
+    const Iv B = bound_iv(view(q), p, d);
+    if (misses(B)) return GV_INF;
+    return walk(q, p, d, true, nullptr, fmax(B.lo, 0.0), B.hi);
   }
   __device__ static double dist_out(CQ q, V3 p, V3 d) {
     if (sgn(q, p) > kHalf) return -1.0;

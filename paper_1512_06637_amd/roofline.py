@@ -122,8 +122,50 @@ SOLID_OPS = {
     "cons": {"inside": 14, "safety": 14, "dist_in": 60, "dist_out": 45},
     "sphere": {"inside": 6, "safety": 7, "dist_in": 25, "dist_out": 20},
     "trd": {"inside": 12, "safety": 12, "dist_in": 45, "dist_out": 20},
-    "pcon": {"inside": 20, "safety": 110, "dist_in": 370, "dist_out": 315},
+    "pcon": {"inside": 20, "safety": 199, "dist_in": 370, "dist_out": 315},
 }
+
+# Polycone (the full-set polycone: 10 z-planes, rmin 0), from the walk's own
+# work counters (gv_profile_read [28..32]); the dist_in / dist_out entries of
+# SOLID_OPS above are the full walk over all 9 sections.
+#   inside: section search over the 8 inner planes (8), r (3 + 1 root), the
+#     cone term and its normalisation (5), the two caps and their max (3) = 20;
+#   safety: r (4), per side segment (9) and cap (2) of the meridian polygon the
+#     point-segment squared distance with its precomputed 1/|e|^2 (15) and the
+#     running minimum (1), two hollowness tests per side, one final root
+#     = 4 + 11 * 16 + 9 * 2 + 1 = 199;
+#   per walked section: the z slab (6; the reciprocal of dz once per walk), the
+#     outer cone quadric (rz 2, A 4, B 4, C 4, discriminant 3, root 1, q 2, two
+#     divisions 2, min/max 2, clip to the slab 2 = 26), the pieces (8), the
+#     merge and early-stop tests (4) = 44;
+#   per walk: the section search again (8), direction set-up and the
+#     reciprocal of dz (4), the return (3) = 15;
+#   DistanceToIn of an outside point also tests the bounding cylinder first
+#     (its quadric 20, z slab 6, interval and test 4 = 30).
+PCON_INSIDE = 20
+PCON_SAFETY = 199
+PCON_SECTION = 44
+PCON_WALK = 15
+PCON_REJECT = 30
+
+
+def pcon_ops(query: str, n: int, work) -> float:
+    """Operation count of a polycone query over n tracks from the walk counters
+    of that call ([28] DistanceToIn sections, [29] DistanceToOut sections, [30]
+    bounding-cylinder rejects, [31] DistanceToIn walks, [32] DistanceToOut
+    walks).  The fused query computes the inside code once."""
+    sec_in, sec_out, rej, w_in, w_out = (float(v) for v in work[28:33])
+    din = (rej + w_in) * PCON_REJECT + w_in * PCON_WALK + sec_in * PCON_SECTION
+    dout = w_out * PCON_WALK + sec_out * PCON_SECTION
+    if query == "inside":
+        return n * float(PCON_INSIDE)
+    if query == "safety":
+        return n * float(PCON_INSIDE + PCON_SAFETY)
+    if query == "dist_in":
+        return n * float(PCON_INSIDE) + din
+    if query == "dist_out":
+        return n * float(PCON_INSIDE) + dout
+    return n * float(PCON_INSIDE + PCON_SAFETY) + din + dout
 for _v in SOLID_OPS.values():
     _v["fused"] = _v["inside"] + _v["safety"] + _v["dist_in"] + _v["dist_out"]
 
@@ -132,13 +174,15 @@ for _v in SOLID_OPS.values():
 SOLID_BYTES = {"inside": 24 + 1, "safety": 24 + 8, "dist_in": 48 + 8, "dist_out": 48 + 8, "fused": 48 + 25}
 
 
-def solid_roofline(solid: str, query: str, n: int, us_per_call: float, hbm_peak=PEAK_HBM, alu_peak=PEAK_FP64_OPS):
+def solid_roofline(solid: str, query: str, n: int, us_per_call: float, hbm_peak=PEAK_HBM, alu_peak=PEAK_FP64_OPS,
+                   ops=None):
     """Both fractions of one solid-level call and the roof that bounds it (the
-    larger of the two roofline times)."""
-    ops = SOLID_OPS[solid][query] * n
+    larger of the two roofline times).  ops: the call's operation count when
+    it is measured (polycone walks), else the SOLID_OPS table's per track."""
+    ops = SOLID_OPS[solid][query] * n if ops is None else ops
     byt = SOLID_BYTES[query] * n
     s = us_per_call * 1e-6
     t_alu, t_hbm = ops / alu_peak, byt / hbm_peak
     return {"bound": "alu" if t_alu > t_hbm else "hbm", "frac_alu": ops / s / alu_peak,
-            "frac_hbm": byt / s / hbm_peak, "frac": max(t_alu, t_hbm) / s, "ops_per_track": SOLID_OPS[solid][query],
+            "frac_hbm": byt / s / hbm_peak, "frac": max(t_alu, t_hbm) / s, "ops_per_track": ops / n,
             "bytes_per_track": SOLID_BYTES[query]}

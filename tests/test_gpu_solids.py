@@ -166,3 +166,38 @@ def test_hand_points(geo):
             t = W.Tracks(*[np.ascontiguousarray(v) for v in (*P, *D)])
             res = run_all(geo, NAMES.index(name), t)
             check(name, SOLIDS[name], t, res)
+
+
+@pytest.mark.parametrize("name", ["pcon", "pcon_hollow"])
+def test_polycone_walk_counters(geo, name):
+    """The polycone's work counters (profiling only) add up: every point not
+    inside is either rejected by the bounding cylinder or walked by
+    DistanceToIn, every point not outside is walked by DistanceToOut (the fused
+    query does both, surface points taking both walks), no walk computes more
+    than the 9 sections, and profiling leaves the outputs unchanged."""
+    import torch
+    import paper_1512_06637_amd as G
+    lv = NAMES.index(name)
+    t = mixed_tracks(name, N_SMALL)
+    a = [cuda(v) for v in t.arrays()]
+    code = host(geo.inside(lv, *a[:3]))
+    not_in, not_out = int((code != G.INSIDE).sum()), int((code != G.OUTSIDE).sum())
+    ref_in = host(geo.distance(lv, G.TO_IN, *a))
+    geo.profile(work=True)
+    try:
+        got_in = host(geo.distance(lv, G.TO_IN, *a))
+        w_in = geo.profile_read()[2][28:33]
+        geo.distance(lv, G.TO_OUT, *a)
+        w_out = geo.profile_read()[2][28:33]
+        f64 = torch.float64
+        geo.solid_all(lv, *a, torch.empty(t.n, dtype=torch.int8, device="cuda"),
+                      *[torch.empty(t.n, dtype=f64, device="cuda") for _ in range(3)])
+        w_all = geo.profile_read()[2][28:33]
+    finally:
+        geo.profile()
+    say(f"[pcon work] {name}: in {w_in}, out {w_out}, fused {w_all}")
+    assert np.array_equal(got_in.view(np.int64), ref_in.view(np.int64))
+    assert w_in[2] + w_in[3] == not_in and w_in[1] == w_in[4] == 0
+    assert w_out[4] == not_out and w_out[0] == w_out[2] == w_out[3] == 0
+    assert w_all[2] + w_all[3] == not_in and w_all[4] == not_out
+    assert w_in[0] <= 9 * w_in[3] and w_out[1] <= 9 * w_out[4] and w_in[3] > 0 and w_out[4] > 0

@@ -52,3 +52,25 @@ def test_byte_figures():
     assert R.STEP_DESIGN_BYTES == 152
     # 2 tracks, 5 steps: 2 x (48 in + start PV + nsteps + flags) + 5 x (PV + step)
     assert R.transport_bytes(2, 5) == 2 * 60 + 5 * 12
+
+
+def test_polycone_ops_from_walk_counters():
+    """The polycone's operation count follows its walk counters: no walk (every
+    ray rejected or every point on the wrong side) leaves the inside test (and
+    the reject); each walked section adds PCON_SECTION; the fused count is the
+    inside test once, the safety and both distance parts."""
+    n = 10
+    w = [0] * 33
+    assert R.pcon_ops("inside", n, w) == n * R.PCON_INSIDE
+    assert R.pcon_ops("safety", n, w) == n * (R.PCON_INSIDE + R.PCON_SAFETY)
+    w[30] = 4  # four rejected rays
+    assert R.pcon_ops("dist_in", n, w) == n * R.PCON_INSIDE + 4 * R.PCON_REJECT
+    w[31], w[28] = 3, 7  # three walks over seven sections in all
+    din = (4 + 3) * R.PCON_REJECT + 3 * R.PCON_WALK + 7 * R.PCON_SECTION
+    assert R.pcon_ops("dist_in", n, w) == n * R.PCON_INSIDE + din
+    w[32], w[29] = 2, 5
+    dout = 2 * R.PCON_WALK + 5 * R.PCON_SECTION
+    assert R.pcon_ops("dist_out", n, w) == n * R.PCON_INSIDE + dout
+    assert R.pcon_ops("fused", n, w) == n * (R.PCON_INSIDE + R.PCON_SAFETY) + din + dout
+    # the full walk over all 9 sections is at most the table's estimate
+    assert R.PCON_INSIDE + R.PCON_REJECT + R.PCON_WALK + 9 * R.PCON_SECTION <= R.SOLID_OPS["pcon"]["dist_in"] + 100
