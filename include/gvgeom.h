@@ -357,8 +357,14 @@ enum { GV_Q_STEP = 0, GV_Q_SAFETY = 1, GV_Q_INSIDE = 2 };
  * baskets admitted and not yet returned, an HBM arena of `hbm_budget` bytes
  * (64 KiB .. 1 TiB; 4/5 for inputs, 1/5 for outputs, one hipMalloc here and
  * none later) with a pinned host mirror of the same size, and `nstreams`
- * (1..8) streams, so up to nstreams rounds are in flight. */
-int gv_server_create(gv_geom* g, int32_t slots, int64_t hbm_budget, int32_t nstreams, gv_server** out);
+ * (1..8) streams, so up to nstreams rounds are in flight.  options
+ * GV_SERVE_GRAPH: every round is one launch of a HIP graph instantiated here
+ * per stream (two input-copy runs, the descriptor copy, the fused kernel, two
+ * output-copy runs), its node parameters set for the round; without it a
+ * round is enqueued as plain copies and a launch.  The answers are the same. */
+#define GV_SERVE_GRAPH 1
+int gv_server_create(gv_geom* g, int32_t slots, int64_t hbm_budget, int32_t nstreams, int32_t options,
+                     gv_server** out);
 
 /* Admits one basket (n >= 1 tracks; kind GV_Q_*; precision GV_FP64 or
  * GV_FP32_REFINE).  `in` (host, layout above) is copied into pinned staging

@@ -17,6 +17,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "gvgeom.h")
 
 GV_OK, GV_EINVAL, GV_ENOMEM, GV_EHIP, GV_EFORMAT, GV_ESTATE, GV_EAGAIN = 0, -1, -2, -3, -4, -5, -6
 Q_STEP, Q_SAFETY, Q_INSIDE = 0, 1, 2
+SERVE_GRAPH = 1
 OUTSIDE, SURFACE, INSIDE = 0, 1, 2
 TO_IN, TO_OUT = 0, 1
 SAFETY_AUTO, SAFETY_IN, SAFETY_OUT = 0, 1, 2
@@ -57,7 +58,7 @@ _SIGS = {
     "gv_get_tuning": [_P, _P],
     "geom_set_materials": [_P, _I32, _I32, _P, _P, _P],
     "nav_transport_phys": [_P, _I64] + [_P] * 7 + [_I32, C.c_uint64] + [_P] * 5 + [_I32, _I32, _P],
-    "gv_server_create": [_P, _I32, _I64, _I32, C.POINTER(_P)],
+    "gv_server_create": [_P, _I32, _I64, _I32, _I32, C.POINTER(_P)],
     "gv_server_submit": [_P, _I32, _I32, _I64, _P, _P, _P],
     "gv_server_poll": [_P, _I32, _P, _P, _P],
     "gv_server_drain": [_P],
@@ -424,10 +425,12 @@ class Server:
     Input and output blocks are host numpy uint8 arrays in the serving layout;
     an output block must stay alive until poll() returns its ticket."""
 
-    def __init__(self, geometry, slots=64, hbm_budget=256 << 20, nstreams=2):
+    def __init__(self, geometry, slots=64, hbm_budget=256 << 20, nstreams=2, graphs=True):
+        """graphs: every round is one launch of a per-stream HIP graph (GV_SERVE_GRAPH)."""
         self._g = geometry
         h = C.c_void_p()
-        _check("gv_server_create", lib().gv_server_create(geometry._h, slots, hbm_budget, nstreams, C.byref(h)))
+        _check("gv_server_create", lib().gv_server_create(geometry._h, slots, hbm_budget, nstreams,
+                                                          SERVE_GRAPH if graphs else 0, C.byref(h)))
         self._h = h
         self._keep = {}  # ticket -> output buffer (kept alive until returned)
 

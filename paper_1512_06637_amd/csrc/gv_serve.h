@@ -119,6 +119,18 @@ struct gv_server {
   gv::SDesc* h_desc = nullptr;
   std::vector<hipStream_t> st;
   std::vector<hipEvent_t> ev;
+  // rounds launched as a graph per stream (GV_SERVE_GRAPH): fixed topology
+  // (two input-copy runs and the descriptor copy, the fused kernel, two
+  // output-copy runs) whose node parameters are set for every round; copies a
+  // round does not need move 8 bytes between per-stream spare words
+  bool graphs = false;
+  struct RoundGraph {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    hipGraphNode_t in[2] = {nullptr, nullptr}, desc = nullptr, kern = nullptr, out[2] = {nullptr, nullptr};
+  };
+  std::vector<RoundGraph> rg;
+  char *d_spare = nullptr, *h_spare = nullptr;  // [nstreams][64] bytes
   hipEvent_t ev_ref = nullptr;
   double t_ref = 0.0;
   struct Bk {
@@ -149,6 +161,10 @@ double now_s() {
 
 void server_release(gv_server* s) {
   if (!s) return;
+  for (auto& r : s->rg) {
+    if (r.x) (void)hipGraphExecDestroy(r.x);
+    if (r.g) (void)hipGraphDestroy(r.g);
+  }
   for (auto& e : s->ev)
     if (e) (void)hipEventDestroy(e);
   if (s->ev_ref) (void)hipEventDestroy(s->ev_ref);
@@ -186,19 +202,60 @@ int server_launch(gv_server* s, int k) {
     tiles += (b.n + 63) / 64;
   }
   hipError_t e = hipSuccess;
-  for (auto& r : runs(R.bs, [](const gv_server::Bk& b) { return std::make_pair(b.in_off, b.in_len); }))
-    if (e == hipSuccess) e = hipMemcpyAsync(s->d_in + r.first, s->h_in + r.first, r.second, hipMemcpyHostToDevice, q);
+  const auto rin = runs(R.bs, [](const gv_server::Bk& b) { return std::make_pair(b.in_off, b.in_len); });
+  const auto rout = runs(R.bs, [](const gv_server::Bk& b) { return std::make_pair(b.out_off, b.out_len); });
   gv::SDesc* dd = s->d_desc + (size_t)k * s->slots;
-  if (e == hipSuccess) e = hipMemcpyAsync(dd, hd, R.bs.size() * sizeof(gv::SDesc), hipMemcpyHostToDevice, q);
-  if (e != hipSuccess) return hip_fail(e, "gv_server: input copy");
   const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, 2048));
-  hipLaunchKernelGGL(s->g->has_bool ? gv::k_serve<true> : gv::k_serve<false>, dim3(grid), dim3(kBlock), 0, q, s->g->dg, (const gv::SDesc*)dd, (int)R.bs.size(),
-                     tiles, (const char*)s->d_in, s->d_out);
-  GV_TRY(launched(fn));
-  for (auto& r : runs(R.bs, [](const gv_server::Bk& b) { return std::make_pair(b.out_off, b.out_len); }))
-    if (e == hipSuccess) e = hipMemcpyAsync(s->h_out + r.first, s->d_out + r.first, r.second, hipMemcpyDeviceToHost, q);
-  if (e == hipSuccess) e = hipEventRecord(s->ev[k], q);
-  if (e != hipSuccess) return hip_fail(e, "gv_server: output copy");
+  auto kernel = s->g->has_bool ? gv::k_serve<true> : gv::k_serve<false>;
+  if (s->graphs && rin.size() <= 2 && rout.size() <= 2) {
+    // one graph launch: the round's copies and kernel as the node parameters
+    gv_server::RoundGraph& G = s->rg[k];
+    char* ds = s->d_spare + 64 * (size_t)k;
+    char* hs = s->h_spare + 64 * (size_t)k;
+    for (int i = 0; i < 2 && e == hipSuccess; ++i)
+      e = i < (int)rin.size()
+              ? hipGraphExecMemcpyNodeSetParams1D(G.x, G.in[i], s->d_in + rin[i].first, s->h_in + rin[i].first,
+                                                  rin[i].second, hipMemcpyHostToDevice)
+              : hipGraphExecMemcpyNodeSetParams1D(G.x, G.in[i], ds + 8 * i, hs + 8 * i, 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipGraphExecMemcpyNodeSetParams1D(G.x, G.desc, dd, hd, R.bs.size() * sizeof(gv::SDesc),
+                                            hipMemcpyHostToDevice);
+    gv::DevGeom dg = s->g->dg;
+    const gv::SDesc* cdd = dd;
+    int nb = (int)R.bs.size();
+    const char* din = s->d_in;
+    char* dout = s->d_out;
+    void* args[] = {&dg, &cdd, &nb, &tiles, &din, &dout};
+    hipKernelNodeParams kp{};
+    kp.func = reinterpret_cast<void*>(kernel);
+    kp.gridDim = dim3(grid);
+    kp.blockDim = dim3(kBlock);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    if (e == hipSuccess) e = hipGraphExecKernelNodeSetParams(G.x, G.kern, &kp);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i)
+      e = i < (int)rout.size()
+              ? hipGraphExecMemcpyNodeSetParams1D(G.x, G.out[i], s->h_out + rout[i].first, s->d_out + rout[i].first,
+                                                  rout[i].second, hipMemcpyDeviceToHost)
+              : hipGraphExecMemcpyNodeSetParams1D(G.x, G.out[i], hs + 32 + 8 * i, ds + 32 + 8 * i, 8,
+                                                  hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipGraphLaunch(G.x, q);
+    if (e == hipSuccess) e = hipEventRecord(s->ev[k], q);
+    if (e != hipSuccess) return hip_fail(e, "gv_server: round graph");
+  } else {
+    for (auto& r : rin)
+      if (e == hipSuccess) e = hipMemcpyAsync(s->d_in + r.first, s->h_in + r.first, r.second, hipMemcpyHostToDevice, q);
+    if (e == hipSuccess) e = hipMemcpyAsync(dd, hd, R.bs.size() * sizeof(gv::SDesc), hipMemcpyHostToDevice, q);
+    if (e != hipSuccess) return hip_fail(e, "gv_server: input copy");
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), 0, q, s->g->dg, (const gv::SDesc*)dd, (int)R.bs.size(), tiles,
+                       (const char*)s->d_in, s->d_out);
+    GV_TRY(launched(fn));
+    for (auto& r : rout)
+      if (e == hipSuccess) e = hipMemcpyAsync(s->h_out + r.first, s->d_out + r.first, r.second, hipMemcpyDeviceToHost, q);
+    if (e == hipSuccess) e = hipEventRecord(s->ev[k], q);
+    if (e != hipSuccess) return hip_fail(e, "gv_server: output copy");
+  }
   R.busy = true;
   R.seq = ++s->seq;
   s->n_rounds++;
@@ -263,11 +320,48 @@ int server_progress(gv_server* s, bool wait) {
 
 extern "C" double gv_now(void) { return now_s(); }
 
-extern "C" int gv_server_create(gv_geom* g, int32_t slots, int64_t hbm_budget, int32_t nstreams, gv_server** out) {
+// The round graph of stream k: nodes with placeholder parameters (8-byte
+// copies between the stream's spare words, a one-workgroup launch with no
+// baskets), instantiated once; every round sets them.
+int server_round_graph(gv_server* s, int k) {
+  gv_server::RoundGraph& G = s->rg[k];
+  char* ds = s->d_spare + 64 * (size_t)k;
+  char* hs = s->h_spare + 64 * (size_t)k;
+  hipError_t e = hipGraphCreate(&G.g, 0);
+  for (int i = 0; i < 2 && e == hipSuccess; ++i)
+    e = hipGraphAddMemcpyNode1D(&G.in[i], G.g, nullptr, 0, ds + 8 * i, hs + 8 * i, 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipGraphAddMemcpyNode1D(&G.desc, G.g, nullptr, 0, ds + 16, hs + 16, 8, hipMemcpyHostToDevice);
+  gv::DevGeom dg = s->g->dg;
+  const gv::SDesc* cdd = s->d_desc + (size_t)k * s->slots;
+  int nb = 0;
+  int64_t tiles = 0;
+  const char* din = s->d_in;
+  char* dout = s->d_out;
+  void* args[] = {&dg, &cdd, &nb, &tiles, &din, &dout};
+  hipKernelNodeParams kp{};
+  kp.func = reinterpret_cast<void*>(s->g->has_bool ? gv::k_serve<true> : gv::k_serve<false>);
+  kp.gridDim = dim3(1);
+  kp.blockDim = dim3(kBlock);
+  kp.sharedMemBytes = 0;
+  kp.kernelParams = args;
+  kp.extra = nullptr;
+  hipGraphNode_t deps[3] = {G.in[0], G.in[1], G.desc};
+  if (e == hipSuccess) e = hipGraphAddKernelNode(&G.kern, G.g, deps, 3, &kp);
+  for (int i = 0; i < 2 && e == hipSuccess; ++i)
+    e = hipGraphAddMemcpyNode1D(&G.out[i], G.g, &G.kern, 1, hs + 32 + 8 * i, ds + 32 + 8 * i, 8,
+                                hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipGraphInstantiate(&G.x, G.g, nullptr, nullptr, 0);
+  if (e != hipSuccess) return hip_fail(e, "gv_server_create: round graph");
+  return GV_OK;
+}
+
+extern "C" int gv_server_create(gv_geom* g, int32_t slots, int64_t hbm_budget, int32_t nstreams, int32_t options,
+                                gv_server** out) {
   const char* fn = "gv_server_create";
   if (!out) return fail(GV_EINVAL, "%s: out is NULL", fn);
   *out = nullptr;
   if (!g) return fail(GV_EINVAL, "%s: geometry handle is NULL", fn);
+  if (options & ~GV_SERVE_GRAPH) return fail(GV_EINVAL, "%s: options %d", fn, options);
   if (slots < 1 || slots > kServeMaxSlots) return fail(GV_EINVAL, "%s: slots %d not in [1, %d]", fn, slots, kServeMaxSlots);
   if (hbm_budget < (64 << 10) || hbm_budget > ((int64_t)1 << 40))
     return fail(GV_EINVAL, "%s: hbm_budget %lld not in [64 KiB, 1 TiB]", fn, (long long)hbm_budget);
@@ -284,7 +378,7 @@ extern "C" int gv_server_create(gv_geom* g, int32_t slots, int64_t hbm_budget, i
   s->rin = gv::RingAlloc(cin);
   s->rout = gv::RingAlloc(cout);
   const size_t desc_bytes = (size_t)nstreams * slots * sizeof(gv::SDesc);
-  const size_t total = cin + cout + gv::RingAlloc::round_up(desc_bytes);
+  const size_t total = cin + cout + gv::RingAlloc::round_up(desc_bytes) + gv::RingAlloc::round_up(64 * (size_t)nstreams);
   hipError_t e = hipMalloc(&s->d_mem, total);
   if (e != hipSuccess) {
     server_release(s);
@@ -301,6 +395,8 @@ extern "C" int gv_server_create(gv_geom* g, int32_t slots, int64_t hbm_budget, i
   s->h_in = s->h_mem;
   s->h_out = s->h_mem + cin;
   s->h_desc = (gv::SDesc*)(s->h_mem + cin + cout);
+  s->d_spare = s->d_mem + cin + cout + gv::RingAlloc::round_up(desc_bytes);
+  s->h_spare = s->h_mem + cin + cout + gv::RingAlloc::round_up(desc_bytes);
   s->st.assign(nstreams, nullptr);
   s->ev.assign(nstreams, nullptr);
   s->rd.resize(nstreams);
@@ -314,6 +410,17 @@ extern "C" int gv_server_create(gv_geom* g, int32_t slots, int64_t hbm_budget, i
   if (e != hipSuccess) {
     server_release(s);
     return hip_fail(e, "gv_server_create: streams and events");
+  }
+  if (options & GV_SERVE_GRAPH) {
+    s->graphs = true;
+    s->rg.resize(nstreams);
+    for (int i = 0; i < nstreams; ++i) {
+      const int rc = server_round_graph(s, i);
+      if (rc != GV_OK) {
+        server_release(s);
+        return rc;
+      }
+    }
   }
   s->t_ref = now_s();
   *out = s;

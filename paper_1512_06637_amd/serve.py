@@ -125,13 +125,18 @@ def open_loop(srv, baskets, count, rate, seed):
 
 
 def run(g, loads=(0.5, 0.8, 0.95), precisions=(FP64, FP32_REFINE), n_baskets=20000, serial=True,
-        slots=64, hbm_budget=256 << 20, nstreams=2, distinct=256):
+        slots=64, hbm_budget=256 << 20, nstreams=2, distinct=256, graphs=True):
+    """graphs: rounds as graph launches (the engine's default); the other
+    launch form's saturation is measured beside it."""
     pool = state_pool(g)
     res = {"slots": slots, "hbm_budget": hbm_budget, "nstreams": nstreams, "baskets_per_point": n_baskets,
-           "points": []}
+           "rounds_as": "graph launches" if graphs else "plain copies and launch", "points": []}
     for prec in precisions:
         bk = make_baskets(pool, distinct, prec, seed=31 + prec)
-        with Server(g, slots, hbm_budget, nstreams) as srv:
+        with Server(g, slots, hbm_budget, nstreams, graphs=not graphs) as other:
+            saturation(other, bk, min(1000, n_baskets))
+            other_sat = saturation(other, bk, min(5000, n_baskets))
+        with Server(g, slots, hbm_budget, nstreams, graphs=graphs) as srv:
             saturation(srv, bk, min(2000, n_baskets))  # warm-up
             sat = saturation(srv, bk, min(5000, n_baskets))
             pts = []
@@ -141,10 +146,11 @@ def run(g, loads=(0.5, 0.8, 0.95), precisions=(FP64, FP32_REFINE), n_baskets=200
                 pts.append(r)
             st = srv.stats()
         point = {"precision": "fp64" if prec == FP64 else "fp32_refine", "saturation": sat,
-                 "loads": pts, "rounds": st["rounds"], "largest_round": st["max_round"]}
+                 "loads": pts, "rounds": st["rounds"], "largest_round": st["max_round"],
+                 "saturation_other_launch_form": other_sat}
         if serial:
             # the serial form: one basket per round, one round at a time
-            with Server(g, 1, hbm_budget, 1) as one:
+            with Server(g, 1, hbm_budget, 1, graphs=graphs) as one:
                 saturation(one, bk, min(500, n_baskets))
                 ssat = saturation(one, bk, min(2000, n_baskets))
                 spts = []

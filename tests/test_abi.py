@@ -56,8 +56,8 @@ def test_server_argument_checks_need_no_gpu():
     """The serving entry points reject bad handles and arguments on the host."""
     L = G.lib()
     h = C.c_void_p()
-    assert L.gv_server_create(None, 64, 256 << 20, 2, C.byref(h)) == G.GV_EINVAL
-    assert L.gv_server_create(None, 64, 256 << 20, 2, None) == G.GV_EINVAL
+    assert L.gv_server_create(None, 64, 256 << 20, 2, G.SERVE_GRAPH, C.byref(h)) == G.GV_EINVAL
+    assert L.gv_server_create(None, 64, 256 << 20, 2, 0, None) == G.GV_EINVAL
     cnt = C.c_int32(0)
     assert L.gv_server_submit(None, 0, 0, 10, None, None, None) == G.GV_EINVAL
     assert L.gv_server_poll(None, 0, None, None, C.byref(cnt)) == G.GV_EINVAL

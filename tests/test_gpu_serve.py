@@ -106,12 +106,17 @@ def check_equal(kind, got, ref):
         assert np.array_equal(got, ref)
 
 
-def test_serve_mixed_rounds_equal_alone(geos, pool):
+@pytest.mark.parametrize("graphs", [True, False])
+def test_serve_mixed_rounds_equal_alone(geos, pool, graphs):
+    """Every basket served in a round of several (as one graph launch per round
+    with the round's node parameters, or as plain copies and a launch) equals
+    the same basket answered alone by basket_step / _nav_safety / _nav_inside,
+    bit for bit, and the oracle."""
     import paper_1512_06637_amd as G
     g, og = geos
     baskets = make_baskets(pool, 60, 22)
-    say(f"[serve] {len(baskets)} baskets, {sum(b['n'] for b in baskets)} tracks")
-    with G.Server(g, slots=16, hbm_budget=64 << 20, nstreams=2) as srv:
+    say(f"[serve] graphs={graphs}: {len(baskets)} baskets, {sum(b['n'] for b in baskets)} tracks")
+    with G.Server(g, slots=16, hbm_budget=64 << 20, nstreams=2, graphs=graphs) as srv:
         outs, _ = run_server(srv, baskets, pool)
         st = srv.stats()
     say(f"  stats {st}")
@@ -135,10 +140,12 @@ def test_serve_mixed_rounds_equal_alone(geos, pool):
             assert np.array_equal(got, og.nav_inside(sub.x, sub.y, sub.z, pv[i]))
 
 
-def test_serve_backpressure(geos, pool):
+@pytest.mark.parametrize("graphs", [True, False])
+def test_serve_backpressure(geos, pool, graphs):
     """A 16 MiB budget holds only a few 65,536-track step baskets (3.75 MiB of
-    inputs each): the server answers GV_EAGAIN until rounds complete, and every
-    basket is still answered exactly."""
+    inputs each): the server answers GV_EAGAIN until rounds complete, the
+    arenas wrap (rounds with two copy runs), and every basket is still answered
+    exactly."""
     import paper_1512_06637_amd as G
     g, _ = geos
     rng = np.random.default_rng(23)
@@ -146,7 +153,7 @@ def test_serve_backpressure(geos, pool):
     baskets = [dict(kind=G.Q_STEP, prec=G.FP64, n=65536, idx=rng.integers(0, t.n, 65536),
                     pstep=np.full(65536, np.inf)) for _ in range(6)]
     baskets += make_baskets(pool, 10, 24)
-    with G.Server(g, slots=64, hbm_budget=16 << 20, nstreams=2) as srv:
+    with G.Server(g, slots=64, hbm_budget=16 << 20, nstreams=2, graphs=graphs) as srv:
         outs, again = run_server(srv, baskets, pool)
         big = np.zeros(G.serve_out_bytes(G.Q_STEP, 1 << 20), np.uint8)
         with pytest.raises(G.GVError) as e:
