@@ -405,8 +405,6 @@ extern "C" int gv_server_create(gv_geom* g, int32_t slots, int64_t hbm_budget, i
     if (e == hipSuccess) e = hipEventCreate(&s->ev[i]);
   }
   if (e == hipSuccess) e = hipEventCreate(&s->ev_ref);
-  if (e == hipSuccess) e = hipEventRecord(s->ev_ref, s->st[0]);
-  if (e == hipSuccess) e = hipEventSynchronize(s->ev_ref);
   if (e != hipSuccess) {
     server_release(s);
     return hip_fail(e, "gv_server_create: streams and events");
@@ -421,6 +419,14 @@ extern "C" int gv_server_create(gv_geom* g, int32_t slots, int64_t hbm_budget, i
         return rc;
       }
     }
+  }
+  // the device clock's reference: an event and the host time right after it
+  // completes (nothing else may come between the two)
+  e = hipEventRecord(s->ev_ref, s->st[0]);
+  if (e == hipSuccess) e = hipEventSynchronize(s->ev_ref);
+  if (e != hipSuccess) {
+    server_release(s);
+    return hip_fail(e, "gv_server_create: reference event");
   }
   s->t_ref = now_s();
   *out = s;
