@@ -316,8 +316,7 @@ int gv_probe_fma64(double* out, int64_t n_lanes, int32_t iters, void* stream);
  *   lane_waves    3 or 4: waves per SIMD the lane kernel is built for
  *                 (default 4; 3 for physics-limited transport);
  *   lane_stage    1 off, 2 on: the lane kernel stages 8 steps of outputs in
- *                 LDS before writing a track's rows (default on; off for
- *                 physics-limited transport);
+ *                 LDS before writing a track's rows (default on);
  *   lane_grid     workgroups (256 threads) of the persistent lane kernel,
  *                 >= 0 (default: as many as the device holds at once).
  * A change of cell_bits re-sizes the transport workspace at the next

@@ -1422,10 +1422,11 @@ int lane_transport(gv_geom* g, const LaneCtl& L, int64_t n, const double* x, con
     hipLaunchKernelGGL(k_ls_scatter, dim3(stream_grid(n)), dim3(kBlock), 0, s, n, L);
     GV_TRY(launched(fn));
   }
-  // defaults: 4 waves and staged outputs for navigation; 3 waves, unstaged,
-  // for physics-limited steps (more live state per lane)
+  // defaults: staged outputs; 4 waves per SIMD for navigation, 3 for
+  // physics-limited steps (more live state per lane: 9.6 ms at 3 against
+  // 11.5 ms at 4 on the detector workload)
   const int waves = g->tune.lane_waves ? g->tune.lane_waves : (phys ? 3 : 4);
-  const bool stage = g->tune.lane_stage ? g->tune.lane_stage == 2 : !phys;
+  const bool stage = g->tune.lane_stage ? g->tune.lane_stage == 2 : true;
   const LaneKernel k = select_lane_kernel(g->has_bool, fp32, phys, waves, stage);
   int64_t grid = g->tune.lane_grid > 0 ? g->tune.lane_grid
                                        : (int64_t)resident_blocks(g, reinterpret_cast<const void*>(k)) * g->n_cu;
