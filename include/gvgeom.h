@@ -318,12 +318,18 @@ int gv_probe_fma64(double* out, int64_t n_lanes, int32_t iters, void* stream);
  *   lane_stage    1 off, 2 on: the lane kernel stages 8 steps of outputs in
  *                 LDS before writing a track's rows (default on);
  *   lane_grid     workgroups (256 threads) of the persistent lane kernel,
- *                 >= 0 (default: as many as the device holds at once).
+ *                 >= 0 (default: as many as the device holds at once);
+ *   lane_sched    1: every live lane of a wavefront takes a step in every
+ *                 iteration; 2: only the lanes whose volume is in the step
+ *                 class (solid type and daughter access) most of the
+ *                 wavefront's live lanes are in take a step, the others wait,
+ *                 so lanes that fell behind catch up (default 2; geometries
+ *                 with composites always 1).
  * A change of cell_bits re-sizes the transport workspace at the next
  * transport.  GV_EINVAL for a field out of range (nothing changed). */
 typedef struct {
   int32_t step_grid, scatter_grid, cell_bits, solid_block, solid_grid, step_waves;
-  int32_t transport, sort_bits, sort_key, lane_waves, lane_stage, lane_grid;
+  int32_t transport, sort_bits, sort_key, lane_waves, lane_stage, lane_grid, lane_sched;
 } gv_tuning;
 int gv_set_tuning(gv_geom* g, const gv_tuning* t);
 int gv_get_tuning(const gv_geom* g, gv_tuning* t);

@@ -25,7 +25,7 @@ FP64, FP32_REFINE = 0, 1
 WORK_N = 33  # work counters returned by gv_profile_read (28 transport, 5 polycone)
 PROF_EVENTS, PROF_WORK = 1, 2
 TUNING_FIELDS = ("step_grid", "scatter_grid", "cell_bits", "solid_block", "solid_grid", "step_waves",
-                 "transport", "sort_bits", "sort_key", "lane_waves", "lane_stage", "lane_grid")
+                 "transport", "sort_bits", "sort_key", "lane_waves", "lane_stage", "lane_grid", "lane_sched")
 
 
 class _Tuning(C.Structure):

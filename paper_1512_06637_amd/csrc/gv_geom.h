@@ -52,6 +52,7 @@ struct DevGeom {
   int n_mat, n_proc;
   CQ mat_rate;       // [n_mat][n_proc] n sigma = 1 / mean free path, 1/mm
   CQI lv_mat;        // [n_lv] material of each LV
+  CQI lv_class;      // [n_lv] step class: branch of the step code (daughter access mode x 8 + solid type)
 };
 
 __device__ __forceinline__ V3 ld3(const double* x, const double* y, const double* z, int64_t i) {

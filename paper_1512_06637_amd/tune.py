@@ -4,7 +4,7 @@ The choices are the fields of gvgeom.h's gv_tuning: the form of the
 transport (lane form: one persistent kernel carrying each track in one lane,
 tracks ordered by a direction key; basket form: regrouping by volume before
 every step), the lane form's direction key and cells, register budget, output
-staging and persistent grid, the basket form's workgroup counts, direction cells and register
+staging, persistent grid and lane scheduling, the basket form's workgroup counts, direction cells and register
 budget, and the block size and workgroup cap of the one-lane-per-track
 kernels (solid-level queries).  None of them changes a result; the tuner
 checks that on every candidate (bitwise-equal outputs) and keeps the fastest,
@@ -37,6 +37,7 @@ LANE_FORM_SPACE = {
     "lane_waves": [0, 3, 4],
     "lane_stage": [0, 1, 2],
     "lane_grid": [0, 1024, 2048],
+    "lane_sched": [0, 1],
 }
 BASKET_FORM_SPACE = {
     "transport": [1],
@@ -131,6 +132,8 @@ def tune_form(g, a, space, max_steps=128, calls=5, log=print):
 
     g.set_tuning(**{k: v[0] for k, v in space.items()})
     ref = g.transport(*a, max_steps=max_steps, out=new_out())
+    for _ in range(10):  # warm-up: clocks and caches before the first timing
+        g.transport(*a, max_steps=max_steps, out=ref)
     torch.cuda.synchronize()
     out = new_out()
     best = {k: v[0] for k, v in space.items()}

@@ -111,10 +111,12 @@ def compare_transport(got, ref, idx=None):
 
 
 # the transport forms (gvgeom.h gv_tuning): lane form with the default order,
-# lane form in index order, unstaged, 3 waves; basket form (8,192 tracks or more)
-FORMS = {"lane": {"transport": 0, "sort_bits": -1, "lane_stage": 0, "lane_waves": 0},
-         "lane_unsorted_unstaged": {"transport": 2, "sort_bits": 0, "lane_stage": 1, "lane_waves": 3},
-         "basket": {"transport": 1, "sort_bits": -1, "lane_stage": 0, "lane_waves": 0}}
+# lane form in index order, unstaged, 3 waves; lane form with every live lane
+# stepping in every iteration; basket form (8,192 tracks or more)
+FORMS = {"lane": {"transport": 0, "sort_bits": -1, "lane_stage": 0, "lane_waves": 0, "lane_sched": 0},
+         "lane_unsorted_unstaged": {"transport": 2, "sort_bits": 0, "lane_stage": 1, "lane_waves": 3, "lane_sched": 0},
+         "lane_every_lane_steps": {"transport": 2, "sort_bits": -1, "lane_stage": 0, "lane_waves": 0, "lane_sched": 1},
+         "basket": {"transport": 1, "sort_bits": -1, "lane_stage": 0, "lane_waves": 0, "lane_sched": 0}}
 
 
 @pytest.mark.parametrize("form", list(FORMS))

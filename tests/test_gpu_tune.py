@@ -24,6 +24,8 @@ SHAPES = [
     {"lane_stage": 1},
     {"lane_stage": 1, "lane_waves": 3, "sort_bits": 0},
     {"lane_waves": 4, "lane_stage": 2, "sort_key": 2},
+    {"lane_sched": 1},
+    {"lane_sched": 1, "lane_waves": 3, "sort_bits": 0},
     {"lane_grid": 7},
     {"lane_grid": 300, "lane_waves": 3},
     # basket form: step and regrouping grids, direction cells, register budget
@@ -37,7 +39,7 @@ SHAPES = [
     dict(BASKET, step_grid=97, scatter_grid=3, cell_bits=4, step_waves=3),
 ]
 DEFAULTS = {"step_grid": 0, "scatter_grid": 0, "cell_bits": -1, "step_waves": 0, "transport": 0, "sort_bits": -1,
-            "sort_key": 0, "lane_waves": 0, "lane_stage": 0, "lane_grid": 0}
+            "sort_key": 0, "lane_waves": 0, "lane_stage": 0, "lane_grid": 0, "lane_sched": 0}
 
 
 def _bits(out):
@@ -101,7 +103,7 @@ def test_tuning_rejects_bad_fields():
     import paper_1512_06637_amd as G
     g = G.Geometry(W.detector_blob(), tuned=False)
     for bad in [{"step_grid": 5000}, {"cell_bits": 3}, {"solid_block": 100}, {"step_waves": 5}, {"transport": 3},
-                {"sort_bits": 8}, {"sort_key": 3}, {"lane_waves": 2}, {"lane_stage": 3},
+                {"sort_bits": 8}, {"sort_key": 3}, {"lane_waves": 2}, {"lane_stage": 3}, {"lane_sched": 3},
                 {"lane_grid": -1}]:
         with pytest.raises(G.GVError):
             g.set_tuning(**bad)
