@@ -1437,7 +1437,11 @@ int lane_transport(gv_geom* g, const LaneCtl& L, int64_t n, const double* x, con
     GV_TRY(launched(fn));
     hipLaunchKernelGGL(k_ls_scan, dim3(1), dim3(1024), 0, s, L, cells);
     GV_TRY(launched(fn));
-    hipLaunchKernelGGL(k_ls_scatter, dim3(stream_grid(n)), dim3(kBlock), 0, s, n, L);
+    // the scatter's chunks: at most 64 workgroups, so that a key's run is
+    // reserved by at most 64 global atomics
+    const int64_t chunk = std::max<int64_t>(4096, (n + 63) / 64);
+    hipLaunchKernelGGL(k_ls_scatter, dim3((unsigned)((n + chunk - 1) / chunk)), dim3(1024), 4 * (size_t)cells, s, n,
+                       chunk, cells, L);
     GV_TRY(launched(fn));
   }
   // defaults: staged outputs; 4 waves per SIMD for navigation, 3 for

@@ -136,13 +136,22 @@ __global__ void __launch_bounds__(1024) k_ls_scan(LaneCtl L, int cells) {
   }
 }
 
-// Places: each track takes the next free place of its key (the order inside
-// a key depends on the atomics' order, which changes no result).
-__global__ void k_ls_scatter(int64_t n, LaneCtl L) {
-  for (int64_t i = gtid(); i < n; i += gstride()) {
-    const uint32_t pos = atomicAdd(&L.cnt[L.key[i]], 1u);
-    L.perm[pos] = (int32_t)i;
-  }
+// Places: each workgroup takes `chunk` consecutive tracks, counts their keys
+// in LDS, reserves each key's run of places with one global atomic, and gives
+// each of its tracks the next place of its key's run (4 cells bytes of
+// dynamic LDS).  The order inside a key depends on the atomics' order, which
+// changes no result.
+__global__ void __launch_bounds__(1024) k_ls_scatter(int64_t n, int64_t chunk, int cells, LaneCtl L) {
+  extern __shared__ uint32_t key_run[];
+  const int64_t a = (int64_t)blockIdx.x * chunk, b = min(n, a + chunk);
+  for (int c = threadIdx.x; c < cells; c += blockDim.x) key_run[c] = 0u;
+  __syncthreads();
+  for (int64_t i = a + threadIdx.x; i < b; i += blockDim.x) atomicAdd(&key_run[L.key[i]], 1u);
+  __syncthreads();
+  for (int c = threadIdx.x; c < cells; c += blockDim.x)
+    if (key_run[c]) key_run[c] = atomicAdd(&L.cnt[c], key_run[c]);
+  __syncthreads();
+  for (int64_t i = a + threadIdx.x; i < b; i += blockDim.x) L.perm[atomicAdd(&key_run[L.key[i]], 1u)] = (int32_t)i;
 }
 
 // One track's state while a lane carries it.
@@ -152,6 +161,7 @@ struct LaneTrack {
   int64_t i;    // track index
   int pv, k, zero_run;
   uint32_t fl;
+  uint64_t procs;  // physics, staged outputs: the process codes of the run, byte k % 8 for step k
 };
 
 // Starts track i: its volume (given or located) and entry 0 of its sequence.
@@ -171,6 +181,7 @@ __device__ __forceinline__ bool lane_begin(const DevGeom& G, LaneTrack& T, int64
   T.k = 0;
   T.zero_run = 0;
   T.safe = 0.0;
+  T.procs = 0;
   int pv = start_pv ? start_pv[i] : locate<B>(G, T.p);
   if (pv < -1 || pv >= G.n_pv) {
     pv = -1;
@@ -196,21 +207,29 @@ struct LaneStage {
 
 // One step of a carried track; returns true when the track has ended (left
 // the world, stuck, or out of steps), after writing its count and flags.
-// With ST > 0 the step length and next volume go to the lane's LDS column and
-// are written to the track's rows ST steps at a time (and at its end), so the
-// row stores of a lane come in runs of consecutive addresses.
+// With ST > 0 the step length and next volume go to the lane's LDS column
+// (and a physics step's process code to a byte of T.procs) and are written
+// to the track's rows ST steps at a time (and at its end), so the row stores
+// of a lane come in runs of consecutive addresses; all lanes of a wavefront
+// that started together write their runs in the same iteration, and a full
+// run goes out in 16-byte stores (its process codes in one 8-byte store).
 template <bool F32, bool PHYS, bool B, int ST>
 __device__ __forceinline__ bool lane_step(const DevGeom& G, LaneTrack& T, int lv, int max_steps,
                                           int32_t* __restrict__ out_pv, double* __restrict__ out_step,
                                           int32_t* __restrict__ out_nsteps, uint32_t* __restrict__ out_flags,
                                           const PhysArgs& P, int8_t* __restrict__ out_proc, LaneStage S) {
+  static_assert(ST == 0 || ST == 8, "a staged run is 8 steps (the process codes of a run fill 64 bits)");
   NoWork w;
   int nx;
   double st;
   if (PHYS) {
     int proc;
     st = step_physics<F32, B>(G, lv, T.pv, T.p, T.d, (uint32_t)T.i, T.k, P, T.safe, &nx, &proc, &T.fl, w);
-    if (out_proc) out_proc[(size_t)T.i * max_steps + T.k] = (int8_t)proc;
+    if (ST == 0) {
+      if (out_proc) out_proc[(size_t)T.i * max_steps + T.k] = (int8_t)proc;
+    } else {
+      T.procs |= (uint64_t)(uint8_t)proc << (8 * (T.k % 8));
+    }
   } else {
     st = step_culled<F32, B>(G, lv, T.pv, T.p, T.d, &nx, &T.fl, w);
     T.p = advance(T.p, st, T.d);
@@ -239,9 +258,31 @@ __device__ __forceinline__ bool lane_step(const DevGeom& G, LaneTrack& T, int lv
     const int m = (T.k - 1) % ST + 1, k0 = T.k - m;
     double* rs = out_step + (size_t)T.i * max_steps + k0;
     int32_t* rp = out_pv + (size_t)T.i * (max_steps + 1) + k0 + 1;
-    for (int j = 0; j < m; ++j) {
-      rs[j] = S.st[64 * j];
-      rp[j] = S.pv[64 * j];
+    if (m == ST) {
+      double vs[ST > 0 ? ST : 1];
+      int32_t vp[ST > 0 ? ST : 1];
+      for (int j = 0; j < ST; ++j) {
+        vs[j] = S.st[64 * j];
+        vp[j] = S.pv[64 * j];
+      }
+      __builtin_memcpy(rs, vs, sizeof vs);
+      __builtin_memcpy(rp, vp, sizeof vp);
+    } else {
+      for (int j = 0; j < m; ++j) {
+        rs[j] = S.st[64 * j];
+        rp[j] = S.pv[64 * j];
+      }
+    }
+    if (PHYS) {
+      if (out_proc) {
+        int8_t* rq = out_proc + (size_t)T.i * max_steps + k0;
+        if (m == ST) {
+          __builtin_memcpy(rq, &T.procs, 8);
+        } else {
+          for (int j = 0; j < m; ++j) rq[j] = (int8_t)(T.procs >> (8 * j));
+        }
+      }
+      T.procs = 0;
     }
   }
   if (end) {
