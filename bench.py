@@ -497,6 +497,8 @@ def main():
     ap.add_argument("--no-composites", action="store_true", help="skip the composite-solid legs")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-probes", action="store_true", help="skip the HBM and FP64 roof probes")
+    ap.add_argument("--transport", choices=["tuned", "lane", "basket"], default="tuned",
+                    help="transport form of the navigation legs: the stored tuning's (default), or forced")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 256 MiB device to device (a kernel of known traffic for counter scaling)")
     args = ap.parse_args()
@@ -521,6 +523,8 @@ def main():
     blob = W.detector_blob()
     tracks = W.config3_tracks(args.n)
     g = G.Geometry(blob)
+    if args.transport != "tuned":
+        g.set_tuning(**dict(g.get_tuning(), transport=1 if args.transport == "basket" else 2))
     a = [torch.from_numpy(v).to("cuda") for v in tracks.arrays()]
     max_steps = 128
     n = tracks.n
