@@ -214,7 +214,7 @@ struct LaneStage {
 // that started together write their runs in the same iteration, and a full
 // run goes out in 16-byte stores (its process codes in one 8-byte store).
 template <bool F32, bool PHYS, bool B, int ST>
-__device__ __forceinline__ bool lane_step(const DevGeom& G, LaneTrack& T, int lv, int max_steps,
+__device__ __forceinline__ bool lane_step(const DevGeom& G, LaneTrack& T, int lv, int pv, int max_steps,
                                           int32_t* __restrict__ out_pv, double* __restrict__ out_step,
                                           int32_t* __restrict__ out_nsteps, uint32_t* __restrict__ out_flags,
                                           const PhysArgs& P, int8_t* __restrict__ out_proc, LaneStage S) {
@@ -224,14 +224,14 @@ __device__ __forceinline__ bool lane_step(const DevGeom& G, LaneTrack& T, int lv
   double st;
   if (PHYS) {
     int proc;
-    st = step_physics<F32, B>(G, lv, T.pv, T.p, T.d, (uint32_t)T.i, T.k, P, T.safe, &nx, &proc, &T.fl, w);
+    st = step_physics<F32, B>(G, lv, pv, T.p, T.d, (uint32_t)T.i, T.k, P, T.safe, &nx, &proc, &T.fl, w);
     if (ST == 0) {
       if (out_proc) out_proc[(size_t)T.i * max_steps + T.k] = (int8_t)proc;
     } else {
       T.procs |= (uint64_t)(uint8_t)proc << (8 * (T.k % 8));
     }
   } else {
-    st = step_culled<F32, B>(G, lv, T.pv, T.p, T.d, &nx, &T.fl, w);
+    st = step_culled<F32, B>(G, lv, pv, T.p, T.d, &nx, &T.fl, w);
     T.p = advance(T.p, st, T.d);
   }
   if (ST == 0) {
@@ -336,8 +336,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WV))) 
     }
     if (!CLS) {
       if (live)
-        while (!lane_step<F32, PHYS, B, ST>(G, T, G.pv_lv[T.pv], max_steps, out_pv, out_step, out_nsteps, out_flags,
-                                            P, out_proc, S)) {
+        while (!lane_step<F32, PHYS, B, ST>(G, T, G.pv_lv[T.pv], T.pv, max_steps, out_pv, out_step, out_nsteps,
+                                            out_flags, P, out_proc, S)) {
         }
       continue;
     }
@@ -360,9 +360,34 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WV))) 
         }
         rest &= ~m;
       }
-      if (live && cl == best)
-        live = !lane_step<F32, PHYS, B, ST>(G, T, lv, max_steps, out_pv, out_step, out_nsteps, out_flags, P, out_proc,
-                                            S);
+      // When every stepping lane is in one logical volume (always in the
+      // world, whose volume is unique; in a layer or a module when the
+      // wavefront's tracks are all in one), the step runs with that volume
+      // (and, for navigation, the placed volume too when shared) as
+      // wavefront-uniform values: the volume's tables then come through
+      // scalar loads instead of per-lane gathers.
+      const bool mine = live && cl == best;
+      const int lead = __ffsll((unsigned long long)__ballot(mine)) - 1;
+      const int lv0 = __builtin_amdgcn_readlane(lv, lead);
+      const bool uni_lv = __ballot(mine && lv != lv0) == 0;
+      if (!PHYS && uni_lv) {
+        const int pv0 = __builtin_amdgcn_readlane(T.pv, lead);
+        if (__ballot(mine && T.pv != pv0) == 0) {
+          if (mine)
+            live = !lane_step<F32, PHYS, B, ST>(G, T, lv0, pv0, max_steps, out_pv, out_step, out_nsteps, out_flags,
+                                                P, out_proc, S);
+        } else if (mine) {
+          live = !lane_step<F32, PHYS, B, ST>(G, T, lv0, T.pv, max_steps, out_pv, out_step, out_nsteps, out_flags, P,
+                                              out_proc, S);
+        }
+      } else if (uni_lv) {
+        if (mine)
+          live = !lane_step<F32, PHYS, B, ST>(G, T, lv0, T.pv, max_steps, out_pv, out_step, out_nsteps, out_flags, P,
+                                              out_proc, S);
+      } else if (mine) {
+        live = !lane_step<F32, PHYS, B, ST>(G, T, lv, T.pv, max_steps, out_pv, out_step, out_nsteps, out_flags, P,
+                                            out_proc, S);
+      }
     }
   }
 }
