@@ -119,8 +119,11 @@ def tune_transport(g, a, max_steps=128, calls=5, log=print):
     return best, best_ms, lt + bt
 
 
-def tune_form(g, a, space, max_steps=128, calls=5, log=print):
-    """Coordinate descent over one form's knobs.  Returns (choice, ms, table)."""
+def tune_form(g, a, space, max_steps=128, calls=5, log=print, passes=2):
+    """Coordinate descent over one form's knobs, `passes` sweeps (the second
+    sweeps each knob again with the others at the first sweep's choice: knobs
+    interact, e.g. the best number of direction cells depends on the key).
+    Returns (choice, ms, table)."""
     import torch
     n = a[0].shape[0]
 
@@ -150,16 +153,27 @@ def tune_form(g, a, space, max_steps=128, calls=5, log=print):
     best_ms = run(best)
     table.append({"cfg": dict(best), "ms": best_ms})
     log(f"tune transport: default {best} {best_ms:.3f} ms")
-    for knob, vals in space.items():
-        for v in vals[1:] if best[knob] == vals[0] else vals:
-            if v == best[knob]:
-                continue
-            cfg = dict(best, **{knob: v})
-            ms = run(cfg)
-            table.append({"cfg": cfg, "ms": ms})
-            log(f"tune transport: {knob}={v} {ms:.3f} ms")
-            if ms < best_ms * 0.995:  # keep a change only for a measurable gain
-                best, best_ms = cfg, ms
+    tried = {tuple(sorted(best.items()))}
+    for sweep in range(passes):
+        changed = False
+        for knob, vals in space.items():
+            for v in vals:
+                cfg = dict(best, **{knob: v})
+                key = tuple(sorted(cfg.items()))
+                if key in tried:
+                    continue
+                tried.add(key)
+                ms = run(cfg)
+                table.append({"cfg": cfg, "ms": ms})
+                log(f"tune transport: {knob}={v} {ms:.3f} ms")
+                if ms < best_ms * 0.995:  # keep a change only for a measurable gain
+                    best, best_ms = cfg, ms
+                    changed = True
+        if not changed:
+            break
+        if sweep + 1 < passes:  # re-time the choice so the next sweep compares like with like
+            best_ms = run(best)
+            log(f"tune transport: pass {sweep + 1} choice {best} {best_ms:.3f} ms")
     return best, best_ms, table
 
 

@@ -132,6 +132,48 @@ def test_fused_all_matches_separate(geo, name):
     check(name, SOLIDS[name], t, fused)
 
 
+@pytest.mark.parametrize("name", NAMES)
+def test_fused_distances_bitwise_equal_separate(geo, name):
+    """The fused query's distances are the separate queries' bit for bit (the
+    same per-ray steps, whatever kernel schedules them: the polycone's
+    DistanceToIn and fused queries compact their walking rays per wavefront,
+    its DistanceToOut runs one lane per track)."""
+    import torch
+    t = mixed_tracks(name, N_SMALL)
+    lv = NAMES.index(name)
+    a = [cuda(v) for v in t.arrays()]
+    n = t.n
+    o = [torch.empty(n, dtype=torch.int8, device="cuda")] + [torch.empty(n, dtype=torch.float64, device="cuda")
+                                                             for _ in range(3)]
+    geo.solid_all(lv, *a, *o)
+    din = geo.distance(lv, 0, *a)
+    dout = geo.distance(lv, 1, *a)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(o[2]).view(np.int64), host(din).view(np.int64))
+    assert np.array_equal(host(o[3]).view(np.int64), host(dout).view(np.int64))
+
+
+@pytest.mark.parametrize("name", ["pcon", "pcon_hollow"])
+def test_pcon_compacted_edge_sizes(geo, name):
+    """Ragged sizes around the compacting kernel's tiles (64 tracks per
+    wavefront step, 1,024 per workgroup), against the oracle."""
+    import torch
+    lv = NAMES.index(name)
+    base = mixed_tracks(name, 2100)
+    for n in (1, 2, 63, 64, 65, 255, 1023, 1024, 1025, 2100):
+        t = base.take(np.arange(n))
+        a = [cuda(v) for v in t.arrays()]
+        din = host(geo.distance(lv, 0, *a))
+        o = [torch.empty(n, dtype=torch.int8, device="cuda")] + [torch.empty(n, dtype=torch.float64, device="cuda")
+                                                                 for _ in range(3)]
+        geo.solid_all(lv, *a, *o)
+        torch.cuda.synchronize()
+        ref, diag = O.distance(SOLIDS[name], 0, t)
+        _, _, bad = compare_values(din, ref, diag, what=f"{name} din n={n}")
+        assert bad.size == 0, n
+        assert np.array_equal(host(o[2]).view(np.int64), din.view(np.int64)), n
+
+
 def test_edge_sizes(geo):
     import torch
     lv = NAMES.index("box")
