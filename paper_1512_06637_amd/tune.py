@@ -34,7 +34,7 @@ LANE_FORM_SPACE = {
     "transport": [0],  # the default form: lane, basket for geometries holding composites
     "sort_bits": [-1, 0, 5, 6],
     "sort_key": [0, 2],
-    "lane_waves": [0, 3, 4],
+    "lane_waves": [0, 3],  # 0: 4 waves per SIMD for navigation, 3 for physics-limited steps (the field serves both)
     "lane_stage": [0, 1, 2],
     "lane_grid": [0, 1024, 2048],
     "lane_sched": [0, 1],
