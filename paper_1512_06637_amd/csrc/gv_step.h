@@ -299,8 +299,14 @@ constexpr int kCullMin = 8;  // LVs with fewer daughters run the plain loop
 // inward from the start; each walk stops at the first tube whose parameter
 // exceeds the best distance so far (or the mother's exit) by more than
 // kTolerance + 1e-6 mm (a margin well above the parameters' rounding), and a
-// tube radially holding the point is evaluated directly.  Equal distances keep
-// the lowest placement index, as the plain loop does.
+// tube radially holding the point is evaluated directly -- unless the ray
+// leaves it within kTolerance / 8 while moving outward: a point that has just
+// left a tube through its rmax holds it radially to rounding, and since r^2
+// grows by at least 2 B t (B >= 0), rmax^2 - rho^2 < B kTolerance / 4 keeps
+// the ray inside rmax for less than kTolerance / 8 (no entry) and the point
+// within kTolerance / 2 of rmax (not inside), so the tube's DistanceToIn would
+// return +inf.  Equal distances keep the lowest placement index, as the plain
+// loop does.
 template <class W>
 __device__ __forceinline__ void daughters_radial(const DevGeom& G, int r0, int off, int cnt, V3 pl, V3 dl,
                                                  double dout, double& best, int& bestk, bool& neg, W& w) {
@@ -324,7 +330,7 @@ __device__ __forceinline__ void daughters_radial(const DevGeom& G, int r0, int o
   };
   auto beyond = [&](double t) { return t - 1e-6 - 1e-12 * t > fmin(best, dout) + kTol; };
   const bool holds = j > 0 && rho2 <= R2[2 * (j - 1) + 1];
-  if (holds) eval(j - 1);
+  if (holds && !(B >= 0.0 && R2[2 * (j - 1) + 1] - rho2 < 0.25 * kTol * B)) eval(j - 1);
   if (!(A > 0.0)) return;  // parallel to the axis: the radius never changes
   for (int m = j; m < cnt; ++m) {  // outward: larger root of A t^2 + 2 B t + (rho^2 - rmin^2), C < 0
     const double C = rho2 - R2[2 * m];

@@ -75,10 +75,10 @@ DIST_OUT = {"world": BOX_DIST_OUT, "layer": TUBE_DIST_OUT, "module": BOX_DIST_OU
 
 # Radial walk (an LV whose daughters are concentric tubes, the detector's
 # world): per step rho^2, A, B (9), the count of tubes with rmin^2 <= rho^2
-# over the world's 20 tubes (2 each) and the holding test (1); per crossing
-# bound C, the discriminant, a square root, the stable root and the margin
-# test (12).
-RADIAL_LOOKUP = 9 + 2 * 20 + 1
+# over the world's 20 tubes (2 each), the holding test (1) and the test that
+# the ray leaves a held tube at once (4); per crossing bound C, the
+# discriminant, a square root, the stable root and the margin test (12).
+RADIAL_LOOKUP = 9 + 2 * 20 + 1 + 4
 RADIAL_BOUND = 12
 # Phi sectors (the detector's layers): per step the segment end (4), the
 # closest approach to the axis (13), its guard (7), two pseudo-angles (8 each,
