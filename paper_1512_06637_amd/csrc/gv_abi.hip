@@ -661,6 +661,7 @@ extern "C" int geom_load(const void* blob, size_t nbytes, gv_geom** out) {
     T.pv_child_off.resize(npv);
     T.pv_child.resize(npv > 0 ? npv - 1 : 0);
     T.pv_gxf.resize((size_t)npv * 12);
+    std::vector<int> pv_k(npv, -1);
     T.max_depth = height[world];
     // DFS pre-order expansion with an explicit stack
     struct Frame {
@@ -689,6 +690,7 @@ extern "C" int geom_load(const void* blob, size_t nbytes, gv_geom** out) {
       int pl = lv_doff[f.lv] + k;
       int parent = f.pv;
       T.pv_child[T.pv_child_off[parent] + k] = next_id;
+      pv_k[next_id] = k;
       double g[12];
       compose(&T.pv_gxf[12 * (size_t)parent], &dau_xf[12 * (size_t)pl], g);
       open(dau_lv[pl], parent, g);
@@ -715,7 +717,7 @@ extern "C" int geom_load(const void* blob, size_t nbytes, gv_geom** out) {
         {lv_rad.data(), lv_rad.size() * 4, 0},       {rad_r2.data(), rad_r2.size() * 8, 0},
         {rad_k.data(), rad_k.size() * 4, 0},         {lv_phi.data(), lv_phi.size() * 4, 0},
         {phi_mask.data(), phi_mask.size() * 8, 0},   {nullptr, 5 * 8, 0},
-        {lv_class.data(), lv_class.size() * 4, 0}};
+        {lv_class.data(), lv_class.size() * 4, 0},   {pv_k.data(), pv_k.size() * 4, 0}};
     size_t total = 0;
     for (auto& p : parts) {
       p.off = total;
@@ -782,6 +784,7 @@ extern "C" int geom_load(const void* blob, size_t nbytes, gv_geom** out) {
     D.phi_mask = (CQL)(base + parts[26].off);
     g->pcon_work = (unsigned long long*)(base + parts[27].off);  // zeroed by the upload
     D.lv_class = (CQI)(base + parts[28].off);
+    D.pv_k = (CQI)(base + parts[29].off);
     g->n_lv = n_lv;
     g->n_pv = (int)npv;
     g->n_place = n_place;

@@ -31,12 +31,19 @@ struct alignas(64) TRec {
   double x, y, z, dx, dy, dz;
   double safe;  // physics-limited transport: lower bound of the distance to the volume's boundaries
   int pv;
-  int zfc;  // zero-length steps in a row (bits 0-7) | flags (8-15) | coarse direction cell (16-31)
+  // zero-length steps in a row (bits 0-3) | flags (4-7) | 1 + placement index
+  // of the box daughter of pv the track left last (8-15; 0: none, or an index
+  // beyond 254, which only forgoes skipping it) | coarse direction cell (16-31)
+  int zfc;
 };
 static_assert(sizeof(TRec) == 64, "record layout");
-__device__ __forceinline__ int zfc_pack(int zr, uint32_t fl, int cc) { return zr | (int)(fl << 8) | (cc << 16); }
-__device__ __forceinline__ int zfc_zr(int v) { return v & 0xff; }
-__device__ __forceinline__ uint32_t zfc_fl(int v) { return (uint32_t)(v >> 8) & 0xffu; }
+static_assert((kFlagOverflow | kFlagStuck | kFlagLocateFail) <= 0xfu, "flags fit in 4 bits");
+__device__ __forceinline__ int zfc_pack(int zr, uint32_t fl, int left, int cc) {
+  return zr | (int)(fl << 4) | ((left >= 0 && left < 255 ? left + 1 : 0) << 8) | (cc << 16);
+}
+__device__ __forceinline__ int zfc_zr(int v) { return v & 0xf; }
+__device__ __forceinline__ uint32_t zfc_fl(int v) { return (uint32_t)(v >> 4) & 0xfu; }
+__device__ __forceinline__ int zfc_left(int v) { return ((v >> 8) & 0xff) - 1; }
 __device__ __forceinline__ int zfc_cc(int v) { return (v >> 16) & 0xffff; }
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return __lanemask_lt(); }
@@ -219,7 +226,7 @@ __global__ void k_bt_place(const int* __restrict__ perm, const double* __restric
     r.dz = dz[id];
     r.safe = 0.0;
     r.pv = out_pv[(size_t)id * (max_steps + 1)];
-    r.zfc = zfc_pack(0, 0u, dir_cell(r.dx, r.dy, r.dz, cb));
+    r.zfc = zfc_pack(0, 0u, -1, dir_cell(r.dx, r.dy, r.dz, cb));
     rec[sl] = r;
     slot_id[sl] = id;
     list0[sl] = (int)sl;
@@ -505,12 +512,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WV))) 
       uint32_t fl = zfc_fl(r.zfc);
       int nx, proc = -1;
       double st;
+      bool exited = false;
       if (PHYS) {
-        st = step_physics<F32, B>(G, b, r.pv, p, d, (uint32_t)id, k, P, r.safe, &nx, &proc, &fl, w);
+        st = step_physics<F32, B>(G, b, r.pv, p, d, (uint32_t)id, k, P, r.safe, &nx, &proc, &fl, w,
+                                  zfc_left(r.zfc), &exited);
       } else {
-        st = step_culled<F32, B>(G, b, r.pv, p, d, &nx, &fl, w);
+        st = step_culled<F32, B>(G, b, r.pv, p, d, &nx, &fl, w, zfc_left(r.zfc), &exited);
         p = advance(p, st, d);
       }
+      // leaving pv into its mother: pv's placement index goes along (see the lane form)
+      const int left = nx != r.pv ? (exited ? G.pv_k[r.pv] : -1) : zfc_left(r.zfc);
       if (ob_step) {  // staged by slot, moved to the rows at the end
         ob_step[(size_t)k * cap + sl] = st;
         ob_pv[(size_t)k * cap + sl] = nx;
@@ -541,7 +552,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WV))) 
         r.y = p.y;
         r.z = p.z;
         r.pv = nx;
-        r.zfc = zfc_pack(zr, fl, zfc_cc(r.zfc));
+        r.zfc = zfc_pack(zr, fl, left, zfc_cc(r.zfc));
         rec[sl] = r;
         nlv_out = G.pv_lv[nx] << cb | zfc_cc(r.zfc);
       }

@@ -53,6 +53,7 @@ struct DevGeom {
   CQ mat_rate;       // [n_mat][n_proc] n sigma = 1 / mean free path, 1/mm
   CQI lv_mat;        // [n_lv] material of each LV
   CQI lv_class;      // [n_lv] step class: branch of the step code (daughter access mode x 8 + solid type)
+  CQI pv_k;          // [n_pv] placement index of each PV among its parent's daughters (-1: the world)
 };
 
 __device__ __forceinline__ V3 ld3(const double* x, const double* y, const double* z, int64_t i) {

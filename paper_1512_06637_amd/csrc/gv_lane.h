@@ -160,6 +160,7 @@ struct LaneTrack {
   double safe;  // physics: distance still to go to the last boundary found
   int64_t i;    // track index
   int pv, k, zero_run;
+  int left;     // placement index of the box daughter of pv the track left last (-1: none)
   uint32_t fl;
   uint64_t procs;  // physics, staged outputs: the process codes of the run, byte k % 8 for step k
 };
@@ -180,6 +181,7 @@ __device__ __forceinline__ bool lane_begin(const DevGeom& G, LaneTrack& T, int64
   T.fl = 0u;
   T.k = 0;
   T.zero_run = 0;
+  T.left = -1;
   T.safe = 0.0;
   T.procs = 0;
   int pv = start_pv ? start_pv[i] : locate<B>(G, T.p);
@@ -222,18 +224,23 @@ __device__ __forceinline__ bool lane_step(const DevGeom& G, LaneTrack& T, int lv
   NoWork w;
   int nx;
   double st;
+  bool exited = false;
   if (PHYS) {
     int proc;
-    st = step_physics<F32, B>(G, lv, pv, T.p, T.d, (uint32_t)T.i, T.k, P, T.safe, &nx, &proc, &T.fl, w);
+    st = step_physics<F32, B>(G, lv, pv, T.p, T.d, (uint32_t)T.i, T.k, P, T.safe, &nx, &proc, &T.fl, w, T.left,
+                              &exited);
     if (ST == 0) {
       if (out_proc) out_proc[(size_t)T.i * max_steps + T.k] = (int8_t)proc;
     } else {
       T.procs |= (uint64_t)(uint8_t)proc << (8 * (T.k % 8));
     }
   } else {
-    st = step_culled<F32, B>(G, lv, pv, T.p, T.d, &nx, &T.fl, w);
+    st = step_culled<F32, B>(G, lv, pv, T.p, T.d, &nx, &T.fl, w, T.left, &exited);
     T.p = advance(T.p, st, T.d);
   }
+  // a track that leaves pv into its mother carries pv's placement index there
+  // (the line does not change, so pv is behind it); entering a daughter clears it
+  if (nx != pv) T.left = exited ? G.pv_k[pv] : -1;
   if (ST == 0) {
     out_step[(size_t)T.i * max_steps + T.k] = st;
     out_pv[(size_t)T.i * (max_steps + 1) + T.k + 1] = nx;

@@ -358,9 +358,11 @@ __device__ __forceinline__ void daughters_radial(const DevGeom& G, int r0, int o
 // union of the masks of the sectors it sweeps holds every daughter whose
 // extent it can meet, and those candidates go through the SafetyToIn bound
 // and DistanceToIn in index order, as in the culled loop's second pass.
+// left: the index of a box daughter the ray has left (-1: none); a straight
+// ray leaves a convex solid once, so it is not a candidate.
 template <class S, bool F32, class W>
 __device__ __forceinline__ void daughters_phi(const DevGeom& G, int lv, int m0, int off, int cnt, V3 pl, V3 dl,
-                                              double dout, double& best, int& bestk, bool& neg, W& w) {
+                                              double dout, double& best, int& bestk, bool& neg, W& w, int left) {
   const double T = dout + kTol;
   const double A = dl.x * dl.x + dl.y * dl.y;
   const double tc = A > 0.0 ? fmin(fmax(-(pl.x * dl.x + pl.y * dl.y) / A, 0.0), T) : 0.0;
@@ -382,6 +384,7 @@ __device__ __forceinline__ void daughters_phi(const DevGeom& G, int lv, int m0, 
     w.add(kWorkPhiSec);
     if (s == s1) break;
   }
+  if (S::kType == kBox && left >= 0) cand &= ~(1ull << left);
   // FP32 screen of the bound (as in the culled loop): only when every active
   // lane's point and exit lie in the range the FP32 margins cover
   bool use32 = false;
@@ -427,9 +430,12 @@ __device__ __forceinline__ void daughters_phi(const DevGeom& G, int lv, int m0, 
 
 // One ComputeStep of a track in placed volume pv (logical volume lv) with no
 // physics limit.  Valid for any lv; fastest when lv is wavefront-uniform.
+// left: placement index of a box daughter of lv the track has left along its
+// present line (-1: none), which the ray cannot meet again; *exited (if given)
+// says whether the step ends at the mother's exit.
 template <bool F32, bool B, class W>
 __device__ __forceinline__ double step_culled(const DevGeom& G, int lv, int pv, V3 p, V3 d, int* next,
-                                              uint32_t* flags, W& w) {
+                                              uint32_t* flags, W& w, int left = -1, bool* exited = nullptr) {
   CQ X = G.pv_gxf + 12 * (size_t)pv;
   V3 pl = to_child_p(X, p), dl = to_child_d(X, d);
   double dout = solid_dist_out<B>(G.lv_type[lv], G.par + G.lv_par[lv], pl, dl);
@@ -446,9 +452,9 @@ __device__ __forceinline__ double step_culled(const DevGeom& G, int lv, int pv, 
   if (rad >= 0) {
     daughters_radial(G, rad, off, cnt, pl, dl, dout, best, bestk, neg, w);
   } else if (phs >= 0 && dtype == kBox) {
-    daughters_phi<Box, F32>(G, lv, phs, off, cnt, pl, dl, dout, best, bestk, neg, w);
+    daughters_phi<Box, F32>(G, lv, phs, off, cnt, pl, dl, dout, best, bestk, neg, w, left);
   } else if (phs >= 0 && dtype == kTubs) {
-    daughters_phi<Tubs, F32>(G, lv, phs, off, cnt, pl, dl, dout, best, bestk, neg, w);
+    daughters_phi<Tubs, F32>(G, lv, phs, off, cnt, pl, dl, dout, best, bestk, neg, w, -1);
   } else if (dtype == kBox && cnt >= kCullMin) {
     daughters_culled<Box, F32>(G, lv, off, cnt, pl, dl, dout, best, bestk, neg, w);
   } else if (dtype == kTubs && cnt >= kCullMin) {
@@ -479,9 +485,11 @@ __device__ __forceinline__ double step_culled(const DevGeom& G, int lv, int pv, 
   *flags = fl;
   if (bestk >= 0 && best <= dout) {
     *next = G.pv_child[G.pv_child_off[pv] + bestk];
+    if (exited) *exited = false;
     return best;
   }
   *next = G.pv_parent[pv];
+  if (exited) *exited = true;
   return dout;
 }
 
@@ -519,7 +527,7 @@ struct PhysArgs {
 template <bool F32, bool B, class W>
 __device__ __forceinline__ double step_physics(const DevGeom& G, int lv, int pv, V3& p, V3 d, uint32_t track, int k,
                                                const PhysArgs& P, double& safe, int* next, int* proc,
-                                               uint32_t* flags, W& w) {
+                                               uint32_t* flags, W& w, int left = -1, bool* exited = nullptr) {
   int pr = -1;
   const double ps = physics_length(G.mat_rate, G.n_proc, G.lv_mat[lv], P.seed, track, (uint32_t)k, &pr);
   if (P.shortcut && ps + kTol < safe) {
@@ -529,10 +537,11 @@ __device__ __forceinline__ double step_physics(const DevGeom& G, int lv, int pv,
     *next = pv;
     *proc = pr;
     p = advance(p, ps, d);
+    if (exited) *exited = false;
     return ps;
   }
   int nx;
-  const double sg = step_culled<F32, B>(G, lv, pv, p, d, &nx, flags, w);  // min(best daughter, exit)
+  const double sg = step_culled<F32, B>(G, lv, pv, p, d, &nx, flags, w, left, exited);  // min(best daughter, exit)
   double st;
   if (ps < sg) {
     w.add(kWorkPhys);
@@ -541,6 +550,7 @@ __device__ __forceinline__ double step_physics(const DevGeom& G, int lv, int pv,
     *proc = pr;
     p = advance(p, st, d);
     safe = P.shortcut ? sg - ps : 0.0;
+    if (exited) *exited = false;
   } else {
     st = sg;
     *next = nx;
