@@ -214,10 +214,12 @@ __device__ __forceinline__ float lower_bound32(CQF Y, F3 p, float pmax) {
 // is) and collects per-lane candidate masks; pass 2 takes each lane's
 // candidates in index order, checks the SafetyToIn bound, and evaluates
 // DistanceToIn only where it can still win.  Index order with a strict < keeps
-// the lowest index among equal minima, as the plain loop does.
+// the lowest index among equal minima, as the plain loop does.  left: a box
+// daughter the ray has left (-1: none), not a candidate (as in daughters_phi).
 template <class S, bool F32, class W>
 __device__ __forceinline__ void daughters_culled(const DevGeom& G, int lv, int off, int cnt, V3 pl, V3 dl,
-                                                 double dout, double& best, int& bestk, bool& neg, W& w) {
+                                                 double dout, double& best, int& bestk, bool& neg, W& w,
+                                                 int left) {
   const double bound = dout + kTol;
   bool use32 = false;
   F3 p32{}, inv32{}, pin32{};
@@ -254,6 +256,7 @@ __device__ __forceinline__ void daughters_culled(const DevGeom& G, int lv, int o
           c0, m, grp, [&](int k) { return box_hit64(G.dau_box + 6 * (size_t)(off + k), inv, pin, bound); },
           [&](int gi) { return box_hit64(G.grp_box + 6 * (size_t)gi, inv, pin, bound); }, w);
     }
+    if (S::kType == kBox && left >= c0 && left < c0 + m) cand &= ~(1ull << (left - c0));
     while (cand) {
       const int k = __builtin_ctzll(cand);
       cand &= cand - 1;
@@ -369,7 +372,7 @@ __device__ __forceinline__ void daughters_phi(const DevGeom& G, int lv, int m0, 
   const double cx = pl.x + tc * dl.x, cy = pl.y + tc * dl.y;
   const double guard = 1e-3 * (fmax(fmax(fabs(pl.x), fabs(pl.y)), fabs(pl.z)) + 1.0);
   if (!(cx * cx + cy * cy > guard * guard) || !(T < GV_INF)) {
-    daughters_culled<S, F32>(G, lv, off, cnt, pl, dl, dout, best, bestk, neg, w);
+    daughters_culled<S, F32>(G, lv, off, cnt, pl, dl, dout, best, bestk, neg, w, left);
     return;
   }
   w.add(kWorkPhi);
@@ -456,9 +459,9 @@ __device__ __forceinline__ double step_culled(const DevGeom& G, int lv, int pv, 
   } else if (phs >= 0 && dtype == kTubs) {
     daughters_phi<Tubs, F32>(G, lv, phs, off, cnt, pl, dl, dout, best, bestk, neg, w, -1);
   } else if (dtype == kBox && cnt >= kCullMin) {
-    daughters_culled<Box, F32>(G, lv, off, cnt, pl, dl, dout, best, bestk, neg, w);
+    daughters_culled<Box, F32>(G, lv, off, cnt, pl, dl, dout, best, bestk, neg, w, left);
   } else if (dtype == kTubs && cnt >= kCullMin) {
-    daughters_culled<Tubs, F32>(G, lv, off, cnt, pl, dl, dout, best, bestk, neg, w);
+    daughters_culled<Tubs, F32>(G, lv, off, cnt, pl, dl, dout, best, bestk, neg, w, -1);
   } else if (dtype == kBox) {
     daughters_of_type<Box>(G, off, cnt, pl, dl, best, bestk, neg);
     w.add(kWorkPlain + kBox, (unsigned)cnt);
