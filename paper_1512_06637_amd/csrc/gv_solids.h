@@ -84,6 +84,14 @@ __device__ __forceinline__ double rcp_fast(double d) {
 }
 __device__ __forceinline__ double div_fast(double a, double b) { return a * rcp_fast(b); }
 
+// pseudo_angle with the reciprocal of rcp_fast: a few ulp from it, for the
+// sector lookups of navigation, whose sector masks are widened by 1e-4.
+__device__ __forceinline__ double pseudo_angle_fast(double x, double y) {
+  const double r = rcp_fast(fabs(x) + fabs(y));
+  if (y >= 0.0) return x >= 0.0 ? y * r : 1.0 - x * r;
+  return x < 0.0 ? 2.0 - y * r : 3.0 + x * r;
+}
+
 __device__ __forceinline__ int code_of(double s) {
   return s < -kHalf ? kInside : (s > kHalf ? kOutside : kSurface);
 }

@@ -338,7 +338,7 @@ __device__ __forceinline__ void daughters_radial(const DevGeom& G, int r0, int o
   for (int m = j; m < cnt; ++m) {  // outward: larger root of A t^2 + 2 B t + (rho^2 - rmin^2), C < 0
     const double C = rho2 - R2[2 * m];
     const double sq = sqrt(B * B - A * C);
-    const double t = B <= 0.0 ? (sq - B) / A : -C / (B + sq);
+    const double t = B <= 0.0 ? div_fast(sq - B, A) : -div_fast(C, B + sq);
     w.add(kWorkRadBound);
     if (beyond(t)) break;
     eval(m);
@@ -348,7 +348,7 @@ __device__ __forceinline__ void daughters_radial(const DevGeom& G, int r0, int o
     const double C = rho2 - R2[2 * m + 1];
     const double disc = B * B - A * C;
     if (disc < -1e-12 * (B * B + A * C)) break;  // misses rmax_m, hence every inner tube
-    const double t = C / (sqrt(fmax(disc, 0.0)) - B);
+    const double t = div_fast(C, sqrt(fmax(disc, 0.0)) - B);
     w.add(kWorkRadBound);
     if (beyond(t)) break;
     eval(m);
@@ -368,7 +368,7 @@ __device__ __forceinline__ void daughters_phi(const DevGeom& G, int lv, int m0, 
                                               double dout, double& best, int& bestk, bool& neg, W& w, int left) {
   const double T = dout + kTol;
   const double A = dl.x * dl.x + dl.y * dl.y;
-  const double tc = A > 0.0 ? fmin(fmax(-(pl.x * dl.x + pl.y * dl.y) / A, 0.0), T) : 0.0;
+  const double tc = A > 0.0 ? fmin(fmax(-div_fast(pl.x * dl.x + pl.y * dl.y, A), 0.0), T) : 0.0;
   const double cx = pl.x + tc * dl.x, cy = pl.y + tc * dl.y;
   const double guard = 1e-3 * (fmax(fmax(fabs(pl.x), fabs(pl.y)), fabs(pl.z)) + 1.0);
   if (!(cx * cx + cy * cy > guard * guard) || !(T < GV_INF)) {
@@ -376,7 +376,7 @@ __device__ __forceinline__ void daughters_phi(const DevGeom& G, int lv, int m0, 
     return;
   }
   w.add(kWorkPhi);
-  const double a0 = pseudo_angle(pl.x, pl.y), a1 = pseudo_angle(pl.x + T * dl.x, pl.y + T * dl.y);
+  const double a0 = pseudo_angle_fast(pl.x, pl.y), a1 = pseudo_angle_fast(pl.x + T * dl.x, pl.y + T * dl.y);
   const bool ccw = pl.x * dl.y - pl.y * dl.x >= 0.0;
   auto sec = [](double a) { return min(kPhiSectors - 1, max(0, (int)(a * (kPhiSectors / 4.0)))); };
   const int s1 = sec(ccw ? a1 : a0);
