@@ -696,6 +696,12 @@ extern "C" int geom_load(const void* blob, size_t nbytes, gv_geom** out) {
       open(dau_lv[pl], parent, g);
     }
 
+    std::vector<int> pv_lc(2 * (size_t)npv);
+    for (long i = 0; i < npv; ++i) {
+      pv_lc[2 * i] = T.pv_lv[i];
+      pv_lc[2 * i + 1] = lv_class[T.pv_lv[i]];
+    }
+
     // one device allocation, 256-byte aligned sub-arrays
     struct Part {
       const void* src;
@@ -717,7 +723,8 @@ extern "C" int geom_load(const void* blob, size_t nbytes, gv_geom** out) {
         {lv_rad.data(), lv_rad.size() * 4, 0},       {rad_r2.data(), rad_r2.size() * 8, 0},
         {rad_k.data(), rad_k.size() * 4, 0},         {lv_phi.data(), lv_phi.size() * 4, 0},
         {phi_mask.data(), phi_mask.size() * 8, 0},   {nullptr, 5 * 8, 0},
-        {lv_class.data(), lv_class.size() * 4, 0},   {pv_k.data(), pv_k.size() * 4, 0}};
+        {lv_class.data(), lv_class.size() * 4, 0},   {pv_k.data(), pv_k.size() * 4, 0},
+        {pv_lc.data(), pv_lc.size() * 4, 0}};
     size_t total = 0;
     for (auto& p : parts) {
       p.off = total;
@@ -785,6 +792,7 @@ extern "C" int geom_load(const void* blob, size_t nbytes, gv_geom** out) {
     g->pcon_work = (unsigned long long*)(base + parts[27].off);  // zeroed by the upload
     D.lv_class = (CQI)(base + parts[28].off);
     D.pv_k = (CQI)(base + parts[29].off);
+    D.pv_lc = (CQI)(base + parts[30].off);
     g->n_lv = n_lv;
     g->n_pv = (int)npv;
     g->n_place = n_place;

@@ -54,6 +54,7 @@ struct DevGeom {
   CQI lv_mat;        // [n_lv] material of each LV
   CQI lv_class;      // [n_lv] step class: branch of the step code (daughter access mode x 8 + solid type)
   CQI pv_k;          // [n_pv] placement index of each PV among its parent's daughters (-1: the world)
+  CQI pv_lc;         // [2 n_pv] logical volume and step class of each PV (one 8-byte load)
 };
 
 __device__ __forceinline__ V3 ld3(const double* x, const double* y, const double* z, int64_t i) {

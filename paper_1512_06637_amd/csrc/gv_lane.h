@@ -350,9 +350,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WV))) 
     }
     for (uint64_t lm = __ballot(live); lm; lm = __ballot(live)) {
       int lv = -1, cl = -1;
-      if (live) {
-        lv = G.pv_lv[T.pv];
-        cl = G.lv_class[lv];
+      if (live) {  // volume and class in one load
+        const unsigned long long lc = reinterpret_cast<CQL>(G.pv_lc)[T.pv];
+        lv = (int)(uint32_t)lc;
+        cl = (int)(uint32_t)(lc >> 32);
       }
       // the class most live lanes are in (few classes are present at once;
       // on equal counts the first found)
