@@ -395,6 +395,20 @@ def grid_description():
     return lvs
 
 
+def big_grid_description():
+    """A 9 x 9 grid of boxes in a box mother, through the z axis: 81 box
+    daughters, so the culled loop runs over two chunks of 64 daughters (with
+    group boxes) and the box a track has just left can sit in either."""
+    lvs = [LV(box(200.0, 200.0, 200.0), [], "world"), LV(box(110.0, 110.0, 60.0), [], "holder"),
+           LV(box(8.0, 6.0, 40.0), [], "cell")]
+    lvs[0].placements.append((1, np.eye(3), np.zeros(3)))
+    for i in range(9):
+        for j in range(9):
+            lvs[1].placements.append((2, rot_z(0.15 * (i - j) / 4.0),
+                                      np.array([22.0 * (i - 4), 22.0 * (j - 4), 4.0 * (i - j) / 2.0])))
+    return lvs
+
+
 def bundle_description():
     """A world cube holding a box that holds 12 tilted tubes in two planes of
     3 x 2, two of them on the z axis (no phi index: the culled loop runs over

@@ -8,8 +8,9 @@ every branch, against the oracle's plain loop over all daughters.
   and with A = 0.
 * Ring: sixteen boxes around the z axis inside a box mother; segments through
   the axis region take the culled loop, the others the phi sectors.
-* Grid (25 boxes through the axis) and bundle (12 tilted tubes): no index
-  applies, so the culled loop runs, with group boxes for the grid.
+* Grid (25 boxes through the axis), big grid (81 boxes: two chunks of 64
+  daughters) and bundle (12 tilted tubes): no index applies, so the culled
+  loop runs, with group boxes for the grids.
 
 Bar: the navigation bar of the detector tests (sequences, counts and flags
 bit-exact for tracks the oracle does not flag; steps within 1e-12 relative +
@@ -28,6 +29,7 @@ CASES = {
     "nested_tubes": (W.nested_tubes_description, (390.0, 390.0, 390.0), (0.0, 0.0, 0.0)),
     "ring": (W.ring_description, (99.0, 99.0, 49.0), (0.0, 0.0, 10.0)),
     "grid": (W.grid_description, (119.0, 119.0, 59.0), (0.0, 0.0, 0.0)),
+    "big_grid": (W.big_grid_description, (109.0, 109.0, 59.0), (0.0, 0.0, 0.0)),
     "bundle": (W.bundle_description, (119.0, 119.0, 89.0), (0.0, 0.0, 0.0)),
 }
 
@@ -69,7 +71,7 @@ def test_index_transport(case, n):
                 assert w[26] > 0 and w[27] >= w[26] and w[1] > 0  # box tests: the near-axis fallback ran
                 assert w[24] == 0
             else:  # culled loop: box tests and bound checks of the daughter type
-                t_d = 0 if name == "grid" else 1
+                t_d = 0 if name in ("grid", "big_grid") else 1  # box or tube daughters
                 assert w[1] > 0 and w[2 + t_d] > 0 and w[8 + t_d] > 0 and w[24] == 0 and w[26] == 0
 
 
