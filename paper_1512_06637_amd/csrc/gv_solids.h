@@ -163,6 +163,19 @@ __device__ __forceinline__ Iv cyl_interior(double R2, V3 p, V3 d) {
   return Iv{t1, t2};
 }
 
+// cyl_interior for an excluded cylinder (a tube's rmin): with C >= 0 (the
+// point on or outside it) and B >= 0 (moving away from the axis) both roots
+// are <= 0 -- q = -(B + sqrt D) <= 0, so q / A <= 0 and C / q <= 0, signs
+// exact -- and pieces_of treats such an interval exactly as no interval, so
+// it is returned as none without the square root and the divisions
+__device__ __forceinline__ Iv cyl_interior_ahead(double R2, V3 p, V3 d) {
+#pragma clang fp contract(off)
+  double B = p.x * d.x + p.y * d.y;
+  double C = p.x * p.x + p.y * p.y - R2;
+  if (C >= 0.0 && B >= 0.0) return iv_none();
+  return cyl_interior(R2, p, d);
+}
+
 // interior of the sphere |x|^2 <= R^2
 __device__ __forceinline__ Iv sph_interior(double R2, V3 p, V3 d) {
 #pragma clang fp contract(off)
@@ -378,7 +391,7 @@ struct Tubs {
   }
   __device__ static __forceinline__ void pieces(CQ q, V3 p, V3 d, Pieces& P) {
     Iv A = iv_and(cyl_interior(q[L::TB_RMAX2], p, d), slab(p.z, d.z, q[L::TB_DZ]));
-    Iv X1 = q[L::TB_RMIN] > 0.0 ? cyl_interior(q[L::TB_RMIN2], p, d) : iv_none();
+    Iv X1 = q[L::TB_RMIN] > 0.0 ? cyl_interior_ahead(q[L::TB_RMIN2], p, d) : iv_none();
     Iv allow, excl;
     phi_intervals(q, L::TB_NS, L::TB_NE, (int)q[L::TB_PHI], p, d, allow, excl);
     pieces_of(iv_and(A, allow), X1, excl, P);
