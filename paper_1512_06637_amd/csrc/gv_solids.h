@@ -105,11 +105,12 @@ __device__ __forceinline__ Iv iv_none() { return Iv{GV_INF, -GV_INF}; }
 __device__ __forceinline__ Iv iv_and(Iv a, Iv b) { return Iv{fmax(a.lo, b.lo), fmin(a.hi, b.hi)}; }
 __device__ __forceinline__ bool iv_empty(Iv a) { return !(a.lo <= a.hi); }
 
-// {t : a + b t <= 0}
-__device__ __forceinline__ Iv halfspace(double a, double b) {
+// {t : a + b t <= 0}, or with `open` {t : a + b t < 0}: the two differ only
+// for a ray parallel to the plane (b == 0) that lies in it (a == 0)
+__device__ __forceinline__ Iv halfspace(double a, double b, bool open = false) {
   if (b > 0.0) return Iv{-GV_INF, -div_fast(a, b)};
   if (b < 0.0) return Iv{-div_fast(a, b), GV_INF};
-  return a <= 0.0 ? iv_all() : iv_none();
+  return (open ? a < 0.0 : a <= 0.0) ? iv_all() : iv_none();
 }
 
 // {t : |z + t dz| <= h}
@@ -308,7 +309,9 @@ __device__ __forceinline__ void phi_intervals(CQ q, int ns, int ne, int mode, V3
   if (mode == 1) {
     allow = iv_and(halfspace(as, bs), halfspace(ae, be));
   } else {
-    excl = iv_and(halfspace(-as, -bs), halfspace(-ae, -be));
+    // the excluded wedge is open: its planes belong to the solid, as a
+    // wedge <= pi holds its own planes
+    excl = iv_and(halfspace(-as, -bs, true), halfspace(-ae, -be, true));
   }
 }
 
