@@ -509,6 +509,7 @@ static double first_interval(const or_solid* s, const double p[3], const double 
   double R[OR_MAX_ROOTS];
   int n = or_roots(s, p, d, R);
   sort_small(R, n);
+  double short_a = -1.0; /* start of the band-only short interval just passed */
   double a = 0.0;
   for (int i = 0; i <= n; ++i) {
     double b = (i < n) ? R[i] : INFINITY;
@@ -520,12 +521,22 @@ static double first_interval(const or_solid* s, const double p[3], const double 
         *diag |= OR_D_GRAZE;
         if (a < *t_suspect) *t_suspect = a;
       }
+      /* the answer follows a band-only interval no longer than kTolerance
+       * (two surfaces met within kTolerance of each other along the ray, a
+       * plane's line crossed just beyond a surface, or a start point in the
+       * band with a crossing within kTolerance ahead): either end of that
+       * interval is a correct answer */
+      if (short_a >= 0.0) {
+        *diag |= OR_D_NEAR_TIE;
+        if (short_a < *t_suspect) *t_suspect = short_a;
+      }
       return a;
     }
     if (c == OR_SURFACE && b - a > OR_KTOL) {
       *diag |= OR_D_GRAZE;
       if (a < *t_suspect) *t_suspect = a;
     }
+    short_a = (c == OR_SURFACE && !(b - a > OR_KTOL)) ? a : -1.0;
     a = b;
   }
   return INFINITY;
