@@ -22,6 +22,7 @@ EXTRA = {
     "tubs_narrow": W.tubs(0.0, 15.0, 20.0, -0.4, 0.7 * math.pi),
     "sphere_full": W.sphere(0.0, 30.0),
     "tubs_half": W.tubs(2.0, 15.0, 20.0, 0.25, math.pi),
+    "tubs_hollow_full": W.tubs(3.0, 12.0, 10.0),
 }
 SOLIDS = dict(W.config_solids(), **EXTRA)
 NAMES = list(SOLIDS)
@@ -208,6 +209,43 @@ def test_hand_points(geo):
             t = W.Tracks(*[np.ascontiguousarray(v) for v in (*P, *D)])
             res = run_all(geo, NAMES.index(name), t)
             check(name, SOLIDS[name], t, res)
+
+
+def test_tube_inner_cylinder_cases(geo):
+    """Points on and near a hollow tube's inner cylinder (exactly on it on the
+    axes, within rounding of it elsewhere, and 1e-12 relative to 0.5 mm off
+    it on both sides) moving out from the axis, along the cylinder, towards
+    the axis and along z, with signed zeros: the cases where the inner
+    cylinder's two roots lie behind the point, at it, or do not exist, which
+    decide whether the inner surface is solved at all."""
+    offs = [0.0] + [sg * e for e in (1e-10, 4e-10, 1e-9, 1e-6, 0.5) for sg in (-1.0, 1.0)]
+    for name in ("tubs", "tubs_half", "tubs_hollow_full"):
+        rmin, _, dz = SOLIDS[name].params[:3]
+        offs_n = offs + [-1e-12 * rmin, 1e-12 * rmin]
+        P, D = [], []
+        axes = [(1.0, 0.0), (0.0, 1.0), (-1.0, 0.0), (0.0, -1.0)]
+        angles = axes + [(math.cos(a), math.sin(a)) for a in (0.3, 2.0, 4.4)]
+        for c, s in angles:
+            u, v = np.array([c, s, 0.0]), np.array([-s, c, 0.0])
+            dirs = [u, -u, v, -v, (u + v) / math.sqrt(2), (v - u) / math.sqrt(2),
+                    np.array([0.0, 0.0, 1.0]), np.array([0.0, 0.0, -1.0]),
+                    (u + np.array([0.0, 0.0, 1.0])) / math.sqrt(2), (1e-3 * u + v) / math.sqrt(1 + 1e-6)]
+            for off in offs_n:
+                r = rmin + off
+                for z in (0.0, 0.5 * dz, dz):
+                    for d in dirs:
+                        P.append((r * c, r * s, z))
+                        D.append(d)
+        # signed zeros: on the cylinder at phi = 0 moving along it with
+        # p.y = -0 and d.x = -0 (the radial product is -0)
+        for d in ((-0.0, 1.0, 0.0), (-0.0, -1.0, 0.0), (-0.0, 0.0, 1.0)):
+            P.append((rmin, -0.0, 0.0))
+            D.append(d)
+        P, D = np.array(P, dtype=float).T, np.array(D, dtype=float).T
+        t = W.Tracks(*[np.ascontiguousarray(a) for a in (*P, *D)])
+        say(f"[tube inner cylinder] {name} n={t.n}")
+        res = run_all(geo, NAMES.index(name), t)
+        check(name, SOLIDS[name], t, res)
 
 
 @pytest.mark.parametrize("name", ["pcon", "pcon_hollow"])
