@@ -447,3 +447,30 @@ def test_hit_conditioning_flag_closed_form():
     d, diag = O.distance(bx, 0, t)
     assert not diag[0] & O.D_COND and d[0] == 40.0
     assert abs(d[1] - 5.0) < 1e-6 and diag[1] & O.D_COND
+
+
+def test_near_tie_after_short_band_interval():
+    """A point within kTolerance/2 of a surface is on it, so an answer that
+    follows a band-only interval no longer than kTolerance is a near tie.
+    Box (10, 20, 30), start (0, -delta, 0), direction (1, 2, 0)/sqrt(5): the
+    x face is met at t_x = 10 sqrt(5) and the y face at
+    t_y = (20 + delta) sqrt(5) / 2, closed forms.  With delta = 4e-10 the two
+    lie 4.5e-10 apart and the ray between them stays within 2e-10 of the x
+    face: the answer is t_y, marked NEAR_TIE.  With delta = 4e-8 the ray
+    leaves the band before t_y: the answer is t_x, unmarked.  A start 1e-10
+    inside a face moving out is marked (a crossing within kTolerance of a
+    band point); one 1 mm inside is not."""
+    bx = W.box(10.0, 20.0, 30.0)
+    r5 = math.sqrt(5.0)
+    for delta, far in ((4e-10, True), (4e-8, False)):
+        t = W.Tracks(np.array([0.0]), np.array([-delta]), np.array([0.0]), np.array([1.0 / r5]),
+                     np.array([2.0 / r5]), np.array([0.0]))
+        d, diag = O.distance(bx, 1, t)
+        tx, ty = 10.0 * r5, (20.0 + delta) * r5 / 2.0
+        assert abs(d[0] - (ty if far else tx)) <= 1e-12 * tx, (delta, d[0], tx, ty)
+        assert bool(diag[0] & O.D_NEAR_TIE) == far, (delta, diag[0])
+    t = W.Tracks(np.array([10.0 - 1e-10, 9.0]), np.array([0.0, 0.0]), np.array([0.0, 0.0]),
+                 np.array([1.0, 1.0]), np.array([0.0, 0.0]), np.array([0.0, 0.0]))
+    d, diag = O.distance(bx, 1, t)
+    assert abs(d[0] - 1e-10) < 1e-15 and diag[0] & O.D_NEAR_TIE
+    assert d[1] == 1.0 and not diag[1] & O.D_NEAR_TIE
