@@ -248,6 +248,50 @@ def test_tube_inner_cylinder_cases(geo):
         check(name, SOLIDS[name], t, res)
 
 
+@pytest.mark.parametrize("name", ["cons", "cons_seg", "sphere"])
+def test_cone_sphere_inner_surface_cases(geo, name):
+    """Points on and near the inner surface of a hollow cone (full and a
+    three-quarter segment whose planes lie off the axes) and of a spherical
+    shell, 1e-10 mm to 0.5 mm off it on both sides, moving out from the axis
+    or centre, towards it, along the surface's generator, tangentially and
+    along z."""
+    s = SOLIDS[name]
+    P, D = [], []
+    offs = [0.0] + [sg * e for e in (1e-10, 4e-10, 1e-9, 1e-6, 0.5) for sg in (-1.0, 1.0)]
+    angles = [(1.0, 0.0), (0.0, 1.0), (-1.0, 0.0), (0.0, -1.0)] + [(math.cos(a), math.sin(a)) for a in (0.3, 2.0, 4.4)]
+    ez = np.array([0.0, 0.0, 1.0])
+    if s.type == W.CONS:
+        rmin1, _, rmin2, _, dz = s.params[:5]
+        for zf in (-1.0, 0.0, 0.5, 1.0):
+            z = zf * dz
+            rin = rmin1 + (rmin2 - rmin1) * (z + dz) / (2 * dz)
+            for c, sn in angles:
+                u, v = np.array([c, sn, 0.0]), np.array([-sn, c, 0.0])
+                g = (rmin2 - rmin1) * u + 2 * dz * ez
+                g = g / np.linalg.norm(g)  # along the inner cone's generator
+                for off in offs:
+                    r = rin + off
+                    for d in (u, -u, v, ez, -ez, g, -g, (u + ez) / math.sqrt(2)):
+                        P.append((r * c, r * sn, z))
+                        D.append(d)
+    else:
+        rmin = s.params[0]
+        for c, sn in angles:
+            for cz in (0.0, 0.6, -1.0):
+                w = np.array([c * math.sqrt(1 - cz * cz), sn * math.sqrt(1 - cz * cz), cz])
+                t1 = np.cross(w, ez if abs(cz) < 0.9 else np.array([1.0, 0.0, 0.0]))
+                t1 = t1 / np.linalg.norm(t1)
+                for off in offs:
+                    for d in (w, -w, t1, ez, -ez, (w + t1) / math.sqrt(2)):
+                        P.append(tuple((rmin + off) * w))
+                        D.append(d)
+    P, D = np.array(P, dtype=float).T, np.array(D, dtype=float).T
+    t = W.Tracks(*[np.ascontiguousarray(a) for a in (*P, *D)])
+    say(f"[inner surface] {name} n={t.n}")
+    res = run_all(geo, NAMES.index(name), t)
+    check(name, s, t, res)
+
+
 @pytest.mark.parametrize("name", ["pcon", "pcon_hollow"])
 def test_polycone_walk_counters(geo, name):
     """The polycone's work counters (profiling only) add up: every point not
